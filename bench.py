@@ -1,0 +1,203 @@
+#!/usr/bin/env python3
+"""Benchmark: Reverse Cuthill-McKee orderings per second on one MI355X.
+
+One step = one complete ordering (checks, degrees, bandwidth/profile before,
+components, pseudo-peripheral search, labelled BFS, reversal,
+bandwidth/profile after, statistics readback) of a graph already resident in
+HBM, through the library's C ABI.  The default workload is the 128^3 3D
+7-point stencil pattern (2,097,152 vertices, 14,581,760 entries), randomly
+relabelled with seed 2.
+
+Prints one JSON line.  Besides the throughput it reports:
+  - teps: edges traversed per second (the entries scanned by every BFS pass);
+  - roofline: the dominant kernel (the persistent ordering kernel), its
+    algorithmic bytes per launch over its average duration measured with HIP
+    events recorded by the library on the launch stream (RCM_TIMING=1);
+  - cpu_baseline: the CPU oracle timed on the host on a bounded sample.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+WORKLOADS = {
+    "grid2d_64x64": (0, "2D 5-point 64x64, relabelled (seed 1)"),
+    "grid3d_128x128x128": (1, "3D 7-point 128^3, relabelled (seed 2)"),
+    "strip_32x500000_drop1pct": (2, "2D 5-point 32x500,000 strip, 1% edges dropped, relabelled (seed 3)"),
+}
+
+# rocprofv3 FETCH_SIZE/WRITE_SIZE of the ordering kernel on the default
+# workload, per launch (KiB), scaled by the copy-kernel calibration factor
+# (see profiles/); None until measured for the current kernel.
+MEASURED_TRAFFIC_BYTES = None
+
+
+def order_kernel_bytes(n: int, m: int, k_pp: int) -> int:
+    """Algorithmic HBM bytes of one launch of the ordering kernel for a
+    component of n vertices and m directed off-diagonal entries:
+      every unlabelled BFS pass: 8m + 20n (rowptr 8n, colidx 4m, visited
+        gather 4m, visited write 4n, frontier write + read 8n);
+      the labelled BFS: 8m + 48n (adds claims, degrees, labels);
+      the reversal: 12n (read the order, write perm and iperm)."""
+    return k_pp * (8 * m + 20 * n) + (8 * m + 48 * n) + 12 * n
+
+
+def whole_call_bytes(n: int, nnz: int, m: int, k_pp: int) -> int:
+    """Algorithmic bytes of a whole ordering: the kernel above plus the
+    input scan (4n + 4nnz) and the result scan (8n + 8nnz)."""
+    return order_kernel_bytes(n, m, k_pp) + (4 * n + 4 * nnz) + (8 * n + 8 * nnz)
+
+
+def cpu_baseline(g, budget_s: float):
+    import oracle
+
+    runs = 0
+    t0 = time.perf_counter()
+    while True:
+        r = oracle.rcm(g.n, g.rowptr, g.colidx)
+        runs += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    dt = time.perf_counter() - t0
+    assert r.status == oracle.OK
+    return {
+        "value": runs / dt,
+        "unit": "orderings/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"{runs} full orderings of the same workload, single-threaded C oracle, "
+                  f"{dt:.1f} s",
+    }, r
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="grid3d_128x128x128", choices=sorted(WORKLOADS))
+    ap.add_argument("--team-size", type=int, default=0)
+    ap.add_argument("--block-threads", type=int, default=0)
+    ap.add_argument("--cpu-budget", type=float, default=12.0,
+                    help="seconds of oracle work for the CPU baseline (0 = skip)")
+    ap.add_argument("--no-check", action="store_true", help="skip the oracle comparison")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build runs on a single MI355X "
+              "(no multi-GPU path); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    os.environ["RCM_TIMING"] = "1"
+    import numpy as np
+    import torch
+
+    from paper_1610_08128_amd import inputs, rcm
+
+    cfg, desc = WORKLOADS[args.workload]
+    g = inputs.config(cfg)
+    dev = torch.device("cuda", 0)
+    rp = torch.from_numpy(g.rowptr).to(dev)
+    ci = torch.from_numpy(g.colidx).to(dev)
+    opts = dict(team_size=args.team_size, block_threads=args.block_threads)
+    ws = torch.empty(rcm.workspace_bytes(g.n, g.nnz, **opts), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.Stream(device=dev)
+    torch.cuda.synchronize()
+
+    def step():
+        return rcm.order(rp, ci, workspace=ws, stream=stream, **opts)
+
+    with torch.cuda.stream(stream):
+        for _ in range(args.warmup):
+            perm, st = step()
+        torch.cuda.synchronize()
+        kern_ms, total_ms = [], []
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            perm, st = step()
+            tm = rcm.last_timings()
+            kern_ms.append(tm["team_kernel_ms"] + tm["small_kernel_ms"])
+            total_ms.append(tm["total_ms"])
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+    phases = rcm.last_timings()
+
+    k_pp = st["num_bfs"] if st["num_components"] == 1 else None
+    m = st["edges_traversed"] // (st["num_bfs"] + 1) if st["num_components"] == 1 else None
+    ms_per_step = dt * 1000.0 / args.steps
+    value = args.steps / dt
+    teps = st["edges_traversed"] * args.steps / dt
+
+    roofline = None
+    if k_pp is not None:
+        kbytes = order_kernel_bytes(g.n, m, k_pp)
+        kavg_s = float(np.mean(kern_ms)) / 1000.0
+        achieved = kbytes / kavg_s / 1e9
+        roofline = {
+            "bound": "hbm",
+            "kernel": "k_order (persistent team kernel: pseudo-peripheral BFS passes, "
+                      "labelled BFS, reversal)",
+            "achieved": round(achieved, 2),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 5),
+            "traffic": MEASURED_TRAFFIC_BYTES,
+            "algorithmic_bytes_per_launch": kbytes,
+            "avg_launch_ms": round(kavg_s * 1000.0, 4),
+            "whole_call_hbm_frac": round(
+                whole_call_bytes(g.n, g.nnz, m, k_pp) / (ms_per_step / 1000.0) / 1e9
+                / HBM_PEAK_GBS, 5),
+        }
+
+    check = None
+    cpu = None
+    if args.cpu_budget > 0:
+        cpu, want = cpu_baseline(g, args.cpu_budget)
+        if not args.no_check:
+            check = bool(np.array_equal(perm.cpu().numpy(), want.perm)) and st == want.stats
+    out = {
+        "metric": "RCM orderings/s",
+        "value": round(value, 3),
+        "unit": "orderings/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{args.workload}: {desc}",
+            "n": g.n,
+            "nnz": g.nnz,
+            "pseudo_diameter": st["pseudo_diameter"],
+            "bfs_passes": st["num_bfs"] + 1,
+            "team_size": args.team_size or 8,
+            "block_threads": args.block_threads or 1024,
+        },
+        "teps": round(teps, 1),
+        "nnz_per_s": round(g.nnz * args.steps / dt, 1),
+        "edges_traversed_per_ordering": st["edges_traversed"],
+        "bandwidth": [st["bandwidth_before"], st["bandwidth_after"]],
+        "profile": [st["profile_before"], st["profile_after"]],
+        "phases_ms_last_step": {k: round(v, 4) for k, v in phases.items()},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "matches_oracle": check,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,173 @@
+/*
+ * rcm.h -- Reverse Cuthill-McKee ordering of a symmetric sparsity pattern on
+ * one AMD Instinct MI355X (gfx950), as a C ABI.
+ *
+ * The operation is the one stated in the paper "The Reverse Cuthill-McKee
+ * Algorithm in Distributed-Memory" (Azad, Jacquelin, Buluc, Ng), Section I:
+ * for a symmetric matrix A, find a permutation P such that P A P^T has a
+ * small bandwidth.  The ordering is computed as in the paper:
+ *
+ *   - per connected component (Section III-B), taken in increasing order of
+ *     the component's lowest vertex id, which is also the start vertex;
+ *   - a pseudo-peripheral root found by repeated breadth-first searches
+ *     (Algorithm 2; Algorithm 4 gives the same searches in matrix form);
+ *   - a level-synchronous labelled BFS (Algorithm 3): each level is expanded
+ *     by a sparse-matrix x sparse-vector product over the (select2nd, min)
+ *     semiring so every new vertex takes its lowest-labelled parent, then the
+ *     new level is ordered by (parent label, degree, vertex id) (SortPerm,
+ *     Table I) and labelled consecutively;
+ *   - the labels are reversed (last line of Algorithm 1).
+ *
+ * Every tie is broken deterministically, so the permutation is unique:
+ * degree = number of off-diagonal entries in the row; "minimum degree"
+ * ties go to the lower vertex id; the start vertex of a component is its
+ * lowest id.  Bandwidth and envelope size (Section II-A) are reported for
+ * the input order and for the result, with 0-based indices and the diagonal
+ * treated as present: beta_k = k - min(k, lowest column in row k), bandwidth
+ * = max beta_k, profile = sum beta_k (64-bit).
+ *
+ * Conventions shared by every entry point:
+ *   - CSR arrays are DEVICE pointers owned by the caller (int32 rowptr[n+1],
+ *     int32 colidx[nnz], nnz = rowptr[n] < 2^31).  Rows need not be sorted;
+ *     self loops are allowed and ignored.  The library never frees caller
+ *     memory and keeps no state between calls.
+ *   - perm_out[k] (device, int32[n]) receives the original vertex placed at
+ *     position k (new -> old), so that B = A[perm][:, perm] = P A P^T.
+ *   - iperm_out (device, int32[n], optional) receives old -> new.
+ *   - stats (HOST pointer, optional) receives the statistics below.
+ *   - stream is a hipStream_t passed as void* (NULL = the default stream).
+ *     Work is enqueued on it; the call returns after that work completes
+ *     (the component schedule and the statistics need small readbacks), so
+ *     perm_out, iperm_out and stats are final on return.
+ *   - Errors are returned as rcm_status; nothing is thrown across the ABI.
+ *     On an error, output arrays may hold partial results.
+ */
+#ifndef RCM_H_
+#define RCM_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RCM_OK = 0,
+  RCM_ERR_INVALID_ARGUMENT = 1,    /* n < 0, NULL pointer with n > 0, bad option */
+  RCM_ERR_BAD_CSR = 2,             /* rowptr[0] != 0, decreasing rowptr, colidx out of
+                                      range, or (full check) a duplicate entry      */
+  RCM_ERR_NOT_SYMMETRIC = 3,       /* full check only: (i,j) present without (j,i)  */
+  RCM_ERR_WORKSPACE_TOO_SMALL = 4, /* caller workspace below rcm_workspace_bytes()  */
+  RCM_ERR_OUT_OF_MEMORY = 5,       /* internal device allocation failed             */
+  RCM_ERR_ABORTED = 6,             /* a device-side wait exceeded its spin limit    */
+  RCM_ERR_HIP = 7                  /* a HIP runtime call failed                     */
+} rcm_status;
+
+/* Statistics of one ordering (one graph). */
+typedef struct {
+  int64_t bandwidth_before; /* Section II-A beta(A) of the input order        */
+  int64_t profile_before;   /* |Env(A)| of the input order                     */
+  int64_t bandwidth_after;  /* beta(P A P^T)                                   */
+  int64_t profile_after;    /* |Env(P A P^T)|                                  */
+  int64_t edges_traversed;  /* sum over components of (num_bfs + 1) * (directed
+                               off-diagonal entries of the component): the
+                               entries scanned by every level structure of the
+                               pseudo-peripheral search plus the labelled BFS */
+  int32_t num_components;   /* connected components (isolated vertices count) */
+  int32_t pseudo_diameter;  /* max over components of the root's eccentricity */
+  int32_t num_bfs;          /* level structures computed by the pseudo-peripheral
+                               search (Algorithm 2), summed over components;
+                               an isolated vertex counts 2                     */
+  int32_t num_levels;       /* levels of the labelled BFS, summed over comps  */
+} rcm_stats;
+
+/* Options.  Zero-initialised options select every default. */
+typedef struct {
+  int32_t pp_variant;    /* 0: root = start of the last BFS (Algorithm 2, default)
+                            1: root = min-(degree, id) vertex of that BFS's last
+                               level (Algorithm 4's return value)              */
+  int32_t reverse_mode;  /* 0: reverse each component's label block (default)
+                            1: reverse the whole label sequence (Algorithm 1)  */
+  int32_t check_full;    /* 1: also reject duplicate entries (BAD_CSR) and
+                            asymmetric patterns (NOT_SYMMETRIC); costs
+                            O(sum of squared row lengths)                      */
+  int32_t team_size;     /* work-groups cooperating on one large component;
+                            0 = auto (8, one per XCD); 1..64                   */
+  int32_t block_threads; /* threads per work-group for the BFS kernels;
+                            0 = auto; one of 256, 512, 1024                    */
+  int32_t small_cutoff;  /* components with at most this many vertices are
+                            ordered by a single work-group each, many in
+                            parallel; 0 = auto                                 */
+  int32_t narrow_cutoff; /* levels narrower than this are expanded by one
+                            work-group of the team without grid-wide barriers;
+                            0 = auto, -1 = never                               */
+  int32_t reserved[9];
+} rcm_options;
+
+/* Human-readable name of a status code (static string). */
+const char* rcm_status_string(rcm_status s);
+
+/* Fill *opts with the defaults. */
+void rcm_default_options(rcm_options* opts);
+
+/* Device workspace needed by rcm_order_ex for a graph with n vertices and
+ * nnz entries (bytes, 256-byte aligned start expected).  Pure host
+ * arithmetic; never fails (returns 0 for n <= 0). */
+size_t rcm_workspace_bytes(int32_t n, int64_t nnz, const rcm_options* opts);
+
+/* Order one graph with default options; internal workspace; no iperm.
+ * perm_out: device int32[n].  stats: host, nullable. */
+rcm_status rcm_order(int32_t n, const int32_t* rowptr, const int32_t* colidx,
+                     int32_t* perm_out, rcm_stats* stats, void* stream);
+
+/* Order one graph.  opts may be NULL (defaults).  workspace: device memory of
+ * at least rcm_workspace_bytes(n, nnz, opts) bytes, or NULL to let the
+ * library allocate (stream-ordered) and free it within the call. */
+rcm_status rcm_order_ex(int32_t n, const int32_t* rowptr, const int32_t* colidx,
+                        int32_t* perm_out, int32_t* iperm_out, rcm_stats* stats,
+                        const rcm_options* opts, void* workspace, size_t workspace_bytes,
+                        void* stream);
+
+/* Device workspace needed by rcm_order_batched (bytes). */
+size_t rcm_batched_workspace_bytes(int32_t num_graphs, int64_t total_vertices,
+                                   int64_t total_nnz, const rcm_options* opts);
+
+/* Order many independent graphs in one call (each exactly as rcm_order_ex
+ * would, per graph).
+ *   vtx_offsets, nnz_offsets: HOST int64[G+1], prefix sums of the graphs'
+ *     vertex counts and entry counts (offsets[0] = 0).
+ *   rowptr_cat: device int32, graph g's local rowptr (starting at 0, n_g+1
+ *     entries) stored at rowptr_cat[vtx_offsets[g] + g].
+ *   colidx_cat: device int32, graph g's local column indices at
+ *     colidx_cat[nnz_offsets[g] ...].
+ *   perm_cat: device int32[total_vertices]; graph g's permutation (local ids)
+ *     at perm_cat[vtx_offsets[g] ...].
+ *   stats: host rcm_stats[G], nullable.
+ * Totals must stay below 2^31 vertices and entries.  The first invalid graph
+ * decides the returned status; on error no graph's output is guaranteed. */
+rcm_status rcm_order_batched(int32_t num_graphs, const int64_t* vtx_offsets,
+                             const int64_t* nnz_offsets, const int32_t* rowptr_cat,
+                             const int32_t* colidx_cat, int32_t* perm_cat, rcm_stats* stats,
+                             const rcm_options* opts, void* workspace, size_t workspace_bytes,
+                             void* stream);
+
+/* Wall-clock phase timings of the last call made by this host thread, in
+ * milliseconds, measured with HIP events on the call's stream when the
+ * environment variable RCM_TIMING=1 is set (zero otherwise). */
+typedef struct {
+  float validate_ms;     /* CSR checks, degrees, bandwidth/profile before  */
+  float components_ms;   /* connected components and the component schedule */
+  float order_ms;        /* pseudo-peripheral searches + labelled BFS + reversal */
+  float after_ms;        /* bandwidth/profile after and statistics          */
+  float total_ms;
+  float small_kernel_ms; /* the launch ordering small components, one work-group each */
+  float team_kernel_ms;  /* the launch ordering large components with a team */
+} rcm_timings;
+void rcm_last_timings(rcm_timings* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RCM_H_ */

@@ -1,0 +1,522 @@
+// C ABI of the ordering library and its host-side orchestration.
+//
+// Call flow (one graph, or a batch treated as the disjoint union of its
+// graphs, which the per-component ordering makes equivalent):
+//   1. argument checks; rowptr[0] and rowptr[n] read back;
+//   2. CSR checks + degrees + bandwidth/profile of the input order;
+//   3. (optional) duplicate / symmetry check;
+//   4. connected components -> seeds (lowest ids) -> sizes and label offsets
+//      -> three task lists: isolated vertices, small components (one
+//      work-group each) and large components (one team of work-groups);
+//   5. the ordering kernels;
+//   6. bandwidth/profile of the result and per-graph statistics.
+// Small readbacks (status flags, component counts, statistics) synchronise
+// the stream a handful of times per call; everything else stays on device.
+
+#include <algorithm>
+#include <cstdlib>
+#include <cstring>
+#include <vector>
+
+#include "rcm_common.hpp"
+
+using namespace rcm;
+
+namespace {
+
+thread_local rcm_timings g_timings;
+
+inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+struct Opts {
+  int pp_variant = 0;
+  int reverse_mode = 0;
+  int check_full = 0;
+  int team_size = 8;
+  int threads = 1024;
+  int small_threads = 256;
+  int small_cutoff = 1 << 14;
+  int narrow_cutoff = 0;
+};
+
+bool parse_options(const rcm_options* o, Opts* out) {
+  Opts r;
+  if (o) {
+    if (o->pp_variant != 0 && o->pp_variant != 1) return false;
+    if (o->reverse_mode != 0 && o->reverse_mode != 1) return false;
+    if (o->check_full != 0 && o->check_full != 1) return false;
+    if (o->team_size < 0 || o->team_size > kMaxTeam) return false;
+    if (o->block_threads != 0 && o->block_threads != 256 && o->block_threads != 512 &&
+        o->block_threads != 1024)
+      return false;
+    if (o->small_cutoff < 0) return false;
+    r.pp_variant = o->pp_variant;
+    r.reverse_mode = o->reverse_mode;
+    r.check_full = o->check_full;
+    if (o->team_size) r.team_size = o->team_size;
+    if (o->block_threads) r.threads = o->block_threads;
+    if (o->small_cutoff) r.small_cutoff = o->small_cutoff;
+    r.narrow_cutoff = o->narrow_cutoff;
+  }
+  *out = r;
+  return true;
+}
+
+// Workspace layout (every region 256-byte aligned).
+struct Layout {
+  size_t deg, beta, parent, flags, pos, csize, seeds, visit, claim, q, tmp, iperm;
+  size_t sizes, offs, results, t_single, t_small, t_big, scan_blk;
+  size_t seg_off, comp_seg_off, segstats, gctl, teams, small_ctl, misc;
+  size_t rowptr_g, colidx_g;
+  size_t total;
+};
+
+Layout make_layout(int64_t n, int64_t nnz, int64_t nseg, bool batched, int teams_small) {
+  Layout L;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = off;
+    off += align_up(bytes);
+    return at;
+  };
+  const size_t N = static_cast<size_t>(n);
+  L.deg = take(4 * N);
+  L.beta = take(4 * N);
+  L.parent = take(4 * N);
+  L.flags = take(4 * N);
+  L.pos = take(4 * N + 4 * (N / 4096 + 2));
+  L.csize = take(4 * N);
+  L.seeds = take(4 * N);
+  L.visit = take(4 * N);
+  L.claim = take(4 * N);
+  L.q = take(4 * N);
+  L.tmp = take(4 * N);
+  L.iperm = take(4 * N);
+  L.sizes = take(4 * N);
+  L.offs = take(4 * N);
+  L.results = take(sizeof(CompResult) * N);
+  L.t_single = take(sizeof(CompTask) * N);
+  L.t_small = take(sizeof(CompTask) * N);
+  L.t_big = take(sizeof(CompTask) * N);
+  L.scan_blk = take(4 * (N / 4096 + 2));
+  L.seg_off = take(4 * static_cast<size_t>(nseg + 1));
+  L.comp_seg_off = take(4 * static_cast<size_t>(nseg + 1));
+  L.segstats = take(sizeof(SegStats) * static_cast<size_t>(nseg));
+  L.gctl = take(sizeof(GlobalCtl));
+  L.teams = take(sizeof(TeamCtl) * kMaxTeam);
+  L.small_ctl = take(sizeof(TeamCtl) * static_cast<size_t>(teams_small));
+  L.misc = take(256);
+  if (batched) {
+    L.rowptr_g = take(4 * (N + 1));
+    L.colidx_g = take(4 * static_cast<size_t>(nnz));
+  } else {
+    L.rowptr_g = L.colidx_g = 0;
+  }
+  L.total = off;
+  return L;
+}
+
+constexpr int kSmallTeams = 1024;
+
+struct Timer {
+  bool on;
+  hipStream_t s;
+  hipEvent_t ev[6];
+  hipEvent_t kev[4];  // around the small-component and the team launches
+  bool kused[2] = {false, false};
+  int k = 0;
+  explicit Timer(hipStream_t st) : s(st) {
+    const char* e = std::getenv("RCM_TIMING");
+    on = e && e[0] == '1';
+    if (on) {
+      for (auto& x : ev) (void)hipEventCreate(&x);
+      for (auto& x : kev) (void)hipEventCreate(&x);
+    }
+  }
+  void kmark(int which, bool start) {
+    if (!on) return;
+    (void)hipEventRecord(kev[2 * which + (start ? 0 : 1)], s);
+    kused[which] = true;
+  }
+  void mark() {
+    if (on && k < 6) (void)hipEventRecord(ev[k++], s);
+  }
+  void finish() {
+    rcm_timings t{};
+    if (on && k >= 2) {
+      (void)hipEventSynchronize(ev[k - 1]);
+      float ms[5] = {0, 0, 0, 0, 0};
+      for (int i = 0; i + 1 < k && i < 4; ++i) (void)hipEventElapsedTime(&ms[i], ev[i], ev[i + 1]);
+      t.validate_ms = ms[0];
+      t.components_ms = ms[1];
+      t.order_ms = ms[2];
+      t.after_ms = ms[3];
+      (void)hipEventElapsedTime(&t.total_ms, ev[0], ev[k - 1]);
+    }
+    g_timings = t;
+  }
+  ~Timer() {
+    if (on)
+      for (auto& x : ev) (void)hipEventDestroy(x);
+  }
+};
+
+#define HIP_TRY(expr)                      \
+  do {                                     \
+    hipError_t _he = (expr);               \
+    if (_he != hipSuccess) return RCM_ERR_HIP; \
+  } while (0)
+
+// Read a few device ints synchronously.
+rcm_status read_ints(int32_t* host, const int32_t* dev, int count, hipStream_t s) {
+  HIP_TRY(hipMemcpyAsync(host, dev, sizeof(int32_t) * count, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return RCM_OK;
+}
+
+// The ordering of a (possibly segmented) graph whose CSR is global.
+rcm_status run(const Graph& gin, const int32_t* seg_off_host, const Opts& opt, char* ws,
+               const Layout& L, int32_t* perm_out, int32_t* iperm_out, rcm_stats* stats_host,
+               hipStream_t s, Timer& timer) {
+  Graph g = gin;
+  const size_t N = static_cast<size_t>(g.n);
+  int32_t* deg = reinterpret_cast<int32_t*>(ws + L.deg);
+  int32_t* beta = reinterpret_cast<int32_t*>(ws + L.beta);
+  int32_t* parent = reinterpret_cast<int32_t*>(ws + L.parent);
+  int32_t* flags = reinterpret_cast<int32_t*>(ws + L.flags);
+  int32_t* pos = reinterpret_cast<int32_t*>(ws + L.pos);
+  int32_t* csize = reinterpret_cast<int32_t*>(ws + L.csize);
+  int32_t* seeds = reinterpret_cast<int32_t*>(ws + L.seeds);
+  int32_t* visit = reinterpret_cast<int32_t*>(ws + L.visit);
+  uint32_t* claim = reinterpret_cast<uint32_t*>(ws + L.claim);
+  int32_t* q = reinterpret_cast<int32_t*>(ws + L.q);
+  int32_t* tmp = reinterpret_cast<int32_t*>(ws + L.tmp);
+  int32_t* iperm = iperm_out ? iperm_out : reinterpret_cast<int32_t*>(ws + L.iperm);
+  int32_t* sizes = reinterpret_cast<int32_t*>(ws + L.sizes);
+  int32_t* offs = reinterpret_cast<int32_t*>(ws + L.offs);
+  CompResult* results = reinterpret_cast<CompResult*>(ws + L.results);
+  CompTask* t_single = reinterpret_cast<CompTask*>(ws + L.t_single);
+  CompTask* t_small = reinterpret_cast<CompTask*>(ws + L.t_small);
+  CompTask* t_big = reinterpret_cast<CompTask*>(ws + L.t_big);
+  int32_t* scan_blk = reinterpret_cast<int32_t*>(ws + L.scan_blk);
+  int32_t* seg_off = reinterpret_cast<int32_t*>(ws + L.seg_off);
+  int32_t* comp_seg_off = reinterpret_cast<int32_t*>(ws + L.comp_seg_off);
+  SegStats* segstats = reinterpret_cast<SegStats*>(ws + L.segstats);
+  GlobalCtl* gctl = reinterpret_cast<GlobalCtl*>(ws + L.gctl);
+  TeamCtl* teams = reinterpret_cast<TeamCtl*>(ws + L.teams);
+  TeamCtl* small_ctl = reinterpret_cast<TeamCtl*>(ws + L.small_ctl);
+  int32_t* misc = reinterpret_cast<int32_t*>(ws + L.misc);  // [0..2] errors, [4] ncomp, [8..10] counts
+
+  HIP_TRY(hipMemcpyAsync(seg_off, seg_off_host, sizeof(int32_t) * (g.nseg + 1),
+                         hipMemcpyHostToDevice, s));
+  g.seg_off = seg_off;
+  HIP_TRY(hipMemsetAsync(misc, 0, 256, s));
+  HIP_TRY(hipMemsetAsync(segstats, 0, sizeof(SegStats) * g.nseg, s));
+
+  timer.mark();
+  // 2. checks, degrees, input bandwidth/profile
+  HIP_TRY(launch_validate_scan(g, deg, beta, segstats, misc + 0, s));
+  int32_t h[4];
+  rcm_status st = read_ints(h, misc, 1, s);
+  if (st != RCM_OK) return st;
+  if (h[0]) return RCM_ERR_BAD_CSR;
+  // 3. optional full check
+  if (opt.check_full) {
+    HIP_TRY(launch_full_check(g, misc + 1, misc + 2, s));
+    st = read_ints(h, misc, 3, s);
+    if (st != RCM_OK) return st;
+    if (h[1]) return RCM_ERR_BAD_CSR;
+    if (h[2]) return RCM_ERR_NOT_SYMMETRIC;
+  }
+  timer.mark();
+  // 4. components and tasks
+  HIP_TRY(launch_components(g, parent, csize, flags, pos, seeds, misc + 4, s));
+  st = read_ints(h, misc + 4, 1, s);
+  if (st != RCM_OK) return st;
+  const int32_t ncomp = h[0];
+  HIP_TRY(launch_tasks(g, ncomp, seeds, csize, opt.small_cutoff, opt.reverse_mode, t_single,
+                       t_small, t_big, misc + 8, sizes, offs, scan_blk, results, s));
+  st = read_ints(h, misc + 8, 3, s);
+  if (st != RCM_OK) return st;
+  const int32_t n_single = h[0], n_small = h[1], n_big = h[2];
+  timer.mark();
+  // 5. ordering
+  HIP_TRY(hipMemsetAsync(visit, 0, 4 * N, s));
+  HIP_TRY(hipMemsetAsync(claim, 0xFF, 4 * N, s));
+  HIP_TRY(hipMemsetAsync(gctl, 0, sizeof(GlobalCtl), s));
+  HIP_TRY(launch_singletons(t_single, n_single, q, perm_out, iperm, results, s));
+  BfsParams P;
+  P.rowptr = g.rowptr;
+  P.colidx = g.colidx;
+  P.deg = deg;
+  P.visit = visit;
+  P.claim = claim;
+  P.q = q;
+  P.tmp = tmp;
+  P.perm = perm_out;
+  P.iperm = iperm;
+  P.results = results;
+  P.gctl = gctl;
+  P.n = g.n;
+  P.pp_variant = opt.pp_variant;
+  P.reverse_mode = opt.reverse_mode;
+  P.narrow_cutoff = opt.narrow_cutoff;
+  if (n_small > 0) {
+    P.tasks = t_small;
+    P.ntasks = n_small;
+    P.teams = small_ctl;
+    P.team_size = 1;
+    const int nb = std::min(n_small, kSmallTeams);
+    HIP_TRY(hipMemsetAsync(small_ctl, 0, sizeof(TeamCtl) * nb, s));
+    timer.kmark(0, true);
+    HIP_TRY(launch_order_small(P, nb, opt.small_threads, s));
+    timer.kmark(0, false);
+  }
+  if (n_big > 0) {
+    P.tasks = t_big;
+    P.ntasks = n_big;
+    P.teams = teams;
+    P.team_size = opt.team_size;
+    HIP_TRY(hipMemsetAsync(teams, 0, sizeof(TeamCtl), s));
+    timer.kmark(1, true);
+    HIP_TRY(launch_order_big(P, opt.threads, s));
+    timer.kmark(1, false);
+  }
+  st = read_ints(h, &gctl->error, 1, s);
+  if (st != RCM_OK) return st;
+  if (h[0] == RCM_ERR_NOT_SYMMETRIC) return RCM_ERR_NOT_SYMMETRIC;
+  if (h[0]) return RCM_ERR_ABORTED;
+  timer.mark();
+  // 6. result statistics
+  HIP_TRY(launch_bw_after(g, perm_out, iperm, beta, segstats, s));
+  HIP_TRY(launch_comp_stats(g, ncomp, seeds, results, comp_seg_off, segstats, s));
+  if (stats_host) {
+    std::vector<SegStats> hs(g.nseg);
+    HIP_TRY(hipMemcpyAsync(hs.data(), segstats, sizeof(SegStats) * g.nseg,
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int i = 0; i < g.nseg; ++i) {
+      rcm_stats& o = stats_host[i];
+      o.bandwidth_before = static_cast<int64_t>(hs[i].bw_before);
+      o.profile_before = static_cast<int64_t>(hs[i].prof_before);
+      o.bandwidth_after = static_cast<int64_t>(hs[i].bw_after);
+      o.profile_after = static_cast<int64_t>(hs[i].prof_after);
+      o.edges_traversed = static_cast<int64_t>(hs[i].edges);
+      o.num_components = hs[i].ncomp;
+      o.pseudo_diameter = hs[i].diameter;
+      o.num_bfs = hs[i].nbfs;
+      o.num_levels = hs[i].nlevels;
+    }
+  } else {
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+  timer.mark();
+  return RCM_OK;
+}
+
+__global__ void k_globalize(int32_t G, const int32_t* __restrict__ vo, const int32_t* __restrict__ no,
+                            const int32_t* __restrict__ rowptr_cat,
+                            const int32_t* __restrict__ colidx_cat, int32_t N, int32_t NNZ,
+                            int32_t* __restrict__ rowptr_g, int32_t* __restrict__ colidx_g,
+                            int32_t* __restrict__ err) {
+  const int32_t stride = gridDim.x * blockDim.x;
+  const int32_t t0 = blockIdx.x * blockDim.x + threadIdx.x;
+  for (int32_t v = t0; v < N; v += stride) {
+    const int g = find_segment(vo, G, v);
+    const int32_t local = v - vo[g];
+    rowptr_g[v] = no[g] + rowptr_cat[vo[g] + g + local];
+  }
+  if (t0 == 0) rowptr_g[N] = NNZ;
+  for (int32_t g = t0; g < G; g += stride) {
+    const int32_t n_g = vo[g + 1] - vo[g];
+    const int32_t first = rowptr_cat[vo[g] + g];
+    const int32_t last = rowptr_cat[vo[g] + g + n_g];
+    if (first != 0 || last != no[g + 1] - no[g]) atomicOr(err, 1);
+  }
+  for (int32_t k = t0; k < NNZ; k += stride) {
+    const int g = find_segment(no, G, k);
+    colidx_g[k] = colidx_cat[k] + vo[g];
+  }
+}
+
+__global__ void k_localize(int32_t N, const int32_t* __restrict__ vo, int32_t G,
+                           int32_t* __restrict__ perm) {
+  for (int32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < N; k += gridDim.x * blockDim.x)
+    perm[k] -= vo[find_segment(vo, G, k)];
+}
+
+rcm_status check_common(int32_t n, const rcm_options* opts, Opts* o) {
+  if (n < 0) return RCM_ERR_INVALID_ARGUMENT;
+  if (!parse_options(opts, o)) return RCM_ERR_INVALID_ARGUMENT;
+  return RCM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* rcm_status_string(rcm_status s) {
+  switch (s) {
+    case RCM_OK: return "ok";
+    case RCM_ERR_INVALID_ARGUMENT: return "invalid argument";
+    case RCM_ERR_BAD_CSR: return "malformed CSR pattern";
+    case RCM_ERR_NOT_SYMMETRIC: return "pattern is not symmetric";
+    case RCM_ERR_WORKSPACE_TOO_SMALL: return "workspace too small";
+    case RCM_ERR_OUT_OF_MEMORY: return "out of device memory";
+    case RCM_ERR_ABORTED: return "aborted: a device-side wait timed out";
+    case RCM_ERR_HIP: return "HIP runtime error";
+  }
+  return "unknown status";
+}
+
+void rcm_default_options(rcm_options* opts) {
+  if (opts) std::memset(opts, 0, sizeof(*opts));
+}
+
+size_t rcm_workspace_bytes(int32_t n, int64_t nnz, const rcm_options* opts) {
+  (void)opts;
+  if (n <= 0) return 0;
+  return make_layout(n, nnz, 1, false, kSmallTeams).total;
+}
+
+size_t rcm_batched_workspace_bytes(int32_t num_graphs, int64_t total_vertices, int64_t total_nnz,
+                                   const rcm_options* opts) {
+  (void)opts;
+  if (num_graphs <= 0 || total_vertices <= 0) return 0;
+  return make_layout(total_vertices, total_nnz, num_graphs, true, kSmallTeams).total;
+}
+
+void rcm_last_timings(rcm_timings* out) {
+  if (out) *out = g_timings;
+}
+
+rcm_status rcm_order_ex(int32_t n, const int32_t* rowptr, const int32_t* colidx,
+                        int32_t* perm_out, int32_t* iperm_out, rcm_stats* stats,
+                        const rcm_options* opts, void* workspace, size_t workspace_bytes,
+                        void* stream) {
+  Opts o;
+  rcm_status st = check_common(n, opts, &o);
+  if (st != RCM_OK) return st;
+  if (stats) std::memset(stats, 0, sizeof(*stats));
+  if (n == 0) return RCM_OK;
+  if (!rowptr || !perm_out) return RCM_ERR_INVALID_ARGUMENT;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int32_t ends[2];
+  HIP_TRY(hipMemcpyAsync(&ends[0], rowptr, 4, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(&ends[1], rowptr + n, 4, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (ends[0] != 0 || ends[1] < 0) return RCM_ERR_BAD_CSR;
+  if (ends[1] > 0 && !colidx) return RCM_ERR_INVALID_ARGUMENT;
+  const Layout L = make_layout(n, ends[1], 1, false, kSmallTeams);
+  char* ws = static_cast<char*>(workspace);
+  bool owned = false;
+  if (ws) {
+    if (workspace_bytes < L.total) return RCM_ERR_WORKSPACE_TOO_SMALL;
+  } else {
+    if (hipMallocAsync(reinterpret_cast<void**>(&ws), L.total, s) != hipSuccess)
+      return RCM_ERR_OUT_OF_MEMORY;
+    owned = true;
+  }
+  Timer timer(s);
+  Graph g{n, ends[1], rowptr, colidx, 1, nullptr};
+  const int32_t seg_host[2] = {0, n};
+  st = run(g, seg_host, o, ws, L, perm_out, iperm_out, stats, s, timer);
+  if (owned) {
+    (void)hipFreeAsync(ws, s);
+    (void)hipStreamSynchronize(s);
+  }
+  timer.finish();
+  return st;
+}
+
+rcm_status rcm_order(int32_t n, const int32_t* rowptr, const int32_t* colidx, int32_t* perm_out,
+                     rcm_stats* stats, void* stream) {
+  return rcm_order_ex(n, rowptr, colidx, perm_out, nullptr, stats, nullptr, nullptr, 0, stream);
+}
+
+rcm_status rcm_order_batched(int32_t num_graphs, const int64_t* vtx_offsets,
+                             const int64_t* nnz_offsets, const int32_t* rowptr_cat,
+                             const int32_t* colidx_cat, int32_t* perm_cat, rcm_stats* stats,
+                             const rcm_options* opts, void* workspace, size_t workspace_bytes,
+                             void* stream) {
+  if (num_graphs < 0) return RCM_ERR_INVALID_ARGUMENT;
+  if (num_graphs == 0) return RCM_OK;
+  if (!vtx_offsets || !nnz_offsets) return RCM_ERR_INVALID_ARGUMENT;
+  Opts o;
+  if (!parse_options(opts, &o)) return RCM_ERR_INVALID_ARGUMENT;
+  if (vtx_offsets[0] != 0 || nnz_offsets[0] != 0) return RCM_ERR_INVALID_ARGUMENT;
+  for (int g = 0; g < num_graphs; ++g)
+    if (vtx_offsets[g + 1] < vtx_offsets[g] || nnz_offsets[g + 1] < nnz_offsets[g])
+      return RCM_ERR_INVALID_ARGUMENT;
+  const int64_t N64 = vtx_offsets[num_graphs];
+  const int64_t NNZ64 = nnz_offsets[num_graphs];
+  if (N64 >= (1ll << 31) - 1 || NNZ64 >= (1ll << 31) - 1) return RCM_ERR_INVALID_ARGUMENT;
+  if (stats) std::memset(stats, 0, sizeof(rcm_stats) * num_graphs);
+  if (N64 == 0) return RCM_OK;
+  if (!rowptr_cat || !perm_cat || (NNZ64 > 0 && !colidx_cat)) return RCM_ERR_INVALID_ARGUMENT;
+  const int32_t N = static_cast<int32_t>(N64), NNZ = static_cast<int32_t>(NNZ64);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const Layout L = make_layout(N, NNZ, num_graphs, true, kSmallTeams);
+  char* ws = static_cast<char*>(workspace);
+  bool owned = false;
+  if (ws) {
+    if (workspace_bytes < L.total) return RCM_ERR_WORKSPACE_TOO_SMALL;
+  } else {
+    if (hipMallocAsync(reinterpret_cast<void**>(&ws), L.total, s) != hipSuccess)
+      return RCM_ERR_OUT_OF_MEMORY;
+    owned = true;
+  }
+  std::vector<int32_t> vo(num_graphs + 1), no(num_graphs + 1);
+  for (int g = 0; g <= num_graphs; ++g) {
+    vo[g] = static_cast<int32_t>(vtx_offsets[g]);
+    no[g] = static_cast<int32_t>(nnz_offsets[g]);
+  }
+  rcm_status st = RCM_OK;
+  Timer timer(s);
+  do {
+    int32_t* rowptr_g = reinterpret_cast<int32_t*>(ws + L.rowptr_g);
+    int32_t* colidx_g = reinterpret_cast<int32_t*>(ws + L.colidx_g);
+    // the graph offsets live in the seg_off / comp_seg_off regions for the
+    // duration of the globalisation (run() rewrites seg_off itself)
+    int32_t* d_vo = reinterpret_cast<int32_t*>(ws + L.seg_off);
+    int32_t* d_no = reinterpret_cast<int32_t*>(ws + L.comp_seg_off);
+    int32_t* err = reinterpret_cast<int32_t*>(ws + L.misc);
+    if (hipMemcpyAsync(d_vo, vo.data(), 4 * vo.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(d_no, no.data(), 4 * no.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemsetAsync(err, 0, 4, s) != hipSuccess) {
+      st = RCM_ERR_HIP;
+      break;
+    }
+    const int threads = 256;
+    const int64_t work = std::max<int64_t>(N, NNZ);
+    const int blocks = static_cast<int>(std::min<int64_t>((work + threads - 1) / threads, 8192));
+    k_globalize<<<blocks, threads, 0, s>>>(num_graphs, d_vo, d_no, rowptr_cat, colidx_cat, N, NNZ,
+                                           rowptr_g, colidx_g, err);
+    int32_t herr = 0;
+    if (hipGetLastError() != hipSuccess || read_ints(&herr, err, 1, s) != RCM_OK) {
+      st = RCM_ERR_HIP;
+      break;
+    }
+    if (herr) {
+      st = RCM_ERR_BAD_CSR;
+      break;
+    }
+    Graph g{N, NNZ, rowptr_g, colidx_g, num_graphs, nullptr};
+    st = run(g, vo.data(), o, ws, L, perm_cat, nullptr, stats, s, timer);
+    if (st != RCM_OK) break;
+    // perm_cat holds union-wide ids; each graph's block lies in its own
+    // vertex range, so subtracting the graph's offset gives local ids
+    // (run() left the graph offsets in its segment table)
+    const int32_t* seg = reinterpret_cast<const int32_t*>(ws + L.seg_off);
+    k_localize<<<std::min((N + 255) / 256, 8192), 256, 0, s>>>(N, seg, num_graphs, perm_cat);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) st = RCM_ERR_HIP;
+  } while (false);
+  if (owned) {
+    (void)hipFreeAsync(ws, s);
+    (void)hipStreamSynchronize(s);
+  }
+  timer.finish();
+  return st;
+}
+
+}  // extern "C"

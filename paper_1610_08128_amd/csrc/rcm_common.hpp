@@ -1,0 +1,254 @@
+// Internal declarations shared by the library's translation units: device
+// helpers, the workspace layout, control blocks and kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rcm.h"
+
+namespace rcm {
+
+constexpr uint32_t kUnclaimed = 0xFFFFFFFFu;
+constexpr uint64_t kMaxKey = ~0ull;
+constexpr int kMaxTeam = 64;
+// A device-side wait gives up (and flags RCM_ERR_ABORTED) after 30 s of the
+// 100 MHz constant-rate clock read by wall_clock64(): far beyond any
+// legitimate wait, short enough to end a broken run cleanly.
+constexpr long long kWaitLimitTicks = 30ll * 100000000ll;
+
+// ---------------------------------------------------------------------------
+// Per-component task and result.
+// ---------------------------------------------------------------------------
+struct CompTask {
+  int32_t seed;    // lowest vertex id of the component = start vertex
+  int32_t size;    // number of vertices
+  int32_t offset;  // first position of the component's label block
+  int32_t index;   // component index (ascending seed order)
+  int32_t anchor;  // Cuthill-McKee label t of the component lands at position anchor - t
+};
+
+struct CompResult {
+  int32_t root;    // pseudo-peripheral root used for the labelled BFS
+  int32_t nbfs;    // level structures computed by the search
+  int32_t levels;  // levels of the labelled BFS
+  int32_t seg;     // graph (segment) the component belongs to
+  int64_t m;       // sum of degrees over the component
+};
+
+// Control block of one team (zeroed before each launch).  Fields written by
+// different agents sit on separate 128-byte lines.
+struct alignas(128) TeamCtl {
+  unsigned long long bar;        // barrier arrivals (monotone)
+  unsigned long long pad0[15];
+  int32_t tail[6];               // append counters, [pass parity][level mod 3]
+  int32_t pad1[26];
+  unsigned long long minkey[6];  // min (deg << 32 | id) per level, same indexing
+  unsigned long long pad2[10];
+  unsigned long long wake;       // narrow-mode release generation
+  unsigned long long pad3[15];
+  int32_t narrow_state[8];       // frontier bounds handed back after narrow levels
+  int32_t pad4[24];
+  int32_t wg_sum[kMaxTeam];      // per-WG counts of the current level
+  long long msum;                // sum of degrees of the current component
+  long long pad5[15];
+};
+
+// Global control shared by all teams of one launch.
+struct alignas(128) GlobalCtl {
+  int32_t queue;                 // next task for single-WG teams
+  int32_t error;                 // set to RCM_ERR_ABORTED by a timed-out wait
+  int32_t pad[30];
+};
+
+// Per-segment (per-graph) accumulators filled by the device.
+struct SegStats {
+  unsigned long long bw_before;
+  unsigned long long prof_before;
+  unsigned long long bw_after;
+  unsigned long long prof_after;
+  unsigned long long edges;
+  int32_t ncomp;
+  int32_t diameter;
+  int32_t nbfs;
+  int32_t nlevels;
+};
+
+// ---------------------------------------------------------------------------
+// Device helpers.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int32_t ld_relaxed(const int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t ld_relaxed(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long ld_relaxed(const unsigned long long* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_relaxed(int32_t* p, int32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint64_t pack_key(int32_t deg, int32_t v) {
+  return (static_cast<uint64_t>(static_cast<uint32_t>(deg)) << 32) | static_cast<uint32_t>(v);
+}
+
+// Wave (64-lane) reductions.
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t x) {
+  for (int o = 32; o > 0; o >>= 1) {
+    uint64_t y = __shfl_xor(x, o, 64);
+    x = y < x ? y : x;
+  }
+  return x;
+}
+__device__ __forceinline__ long long wave_sum_i64(long long x) {
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+__device__ __forceinline__ long long wave_max_i64(long long x) {
+  for (int o = 32; o > 0; o >>= 1) {
+    long long y = __shfl_xor(x, o, 64);
+    x = y > x ? y : x;
+  }
+  return x;
+}
+__device__ __forceinline__ int wave_sum_i32(int x) {
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+
+// Inclusive prefix sum within a wave.
+__device__ __forceinline__ int wave_incl_scan(int x) {
+  const int lane = threadIdx.x & 63;
+  for (int o = 1; o < 64; o <<= 1) {
+    int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  return x;
+}
+
+// Exclusive block scan of one int per thread; returns the exclusive prefix and
+// the block total through *total.  scratch: >= 17 ints of LDS.  All threads
+// of the block must call it.
+__device__ __forceinline__ int block_excl_scan(int x, int* scratch, int* total) {
+  const int lane = threadIdx.x & 63;
+  const int wid = threadIdx.x >> 6;
+  const int nw = (blockDim.x + 63) >> 6;
+  int incl = wave_incl_scan(x);
+  if (lane == 63) scratch[wid] = incl;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int run = 0;
+    for (int w = 0; w < nw; ++w) {
+      int t = scratch[w];
+      scratch[w] = run;
+      run += t;
+    }
+    scratch[16] = run;
+  }
+  __syncthreads();
+  int res = scratch[wid] + incl - x;
+  *total = scratch[16];
+  __syncthreads();
+  return res;
+}
+
+// Block reductions (result valid in every thread).  scratch: >= 16 entries.
+__device__ __forceinline__ long long block_sum_i64(long long x, long long* scratch) {
+  const int lane = threadIdx.x & 63;
+  const int wid = threadIdx.x >> 6;
+  const int nw = (blockDim.x + 63) >> 6;
+  x = wave_sum_i64(x);
+  if (lane == 0) scratch[wid] = x;
+  __syncthreads();
+  long long s = 0;
+  for (int w = 0; w < nw; ++w) s += scratch[w];
+  __syncthreads();
+  return s;
+}
+__device__ __forceinline__ long long block_max_i64(long long x, long long* scratch) {
+  const int lane = threadIdx.x & 63;
+  const int wid = threadIdx.x >> 6;
+  const int nw = (blockDim.x + 63) >> 6;
+  x = wave_max_i64(x);
+  if (lane == 0) scratch[wid] = x;
+  __syncthreads();
+  long long s = scratch[0];
+  for (int w = 1; w < nw; ++w) s = scratch[w] > s ? scratch[w] : s;
+  __syncthreads();
+  return s;
+}
+
+// Segment (graph) of a vertex: largest g with seg_off[g] <= v.  nseg >= 1.
+__device__ __forceinline__ int find_segment(const int32_t* seg_off, int nseg, int32_t v) {
+  int lo = 0, hi = nseg - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (seg_off[mid] <= v) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers (defined in the .hip files).
+// ---------------------------------------------------------------------------
+struct Graph {
+  int32_t n;
+  int32_t nnz;
+  const int32_t* rowptr;  // device, global (segment offsets already applied)
+  const int32_t* colidx;
+  int32_t nseg;
+  const int32_t* seg_off; // device int32[nseg+1] vertex offsets of segments
+};
+
+hipError_t launch_validate_scan(const Graph& g, int32_t* deg, int32_t* beta, SegStats* seg,
+                                int32_t* err, hipStream_t s);
+hipError_t launch_full_check(const Graph& g, int32_t* err_dup, int32_t* err_sym, hipStream_t s);
+hipError_t launch_components(const Graph& g, int32_t* parent, int32_t* csize, int32_t* flags,
+                             int32_t* scan_tmp, int32_t* seeds, int32_t* num_comps,
+                             hipStream_t s);
+hipError_t launch_tasks(const Graph& g, int32_t ncomp, const int32_t* seeds, const int32_t* csize,
+                        int32_t small_cutoff, int32_t reverse_mode, CompTask* tasks_single,
+                        CompTask* tasks_small, CompTask* tasks_big, int32_t* counts,
+                        int32_t* sizes, int32_t* offs, int32_t* scan_blk, CompResult* results,
+                        hipStream_t s);
+hipError_t launch_singletons(const CompTask* tasks, int32_t count, int32_t* q, int32_t* perm,
+                             int32_t* iperm, CompResult* results, hipStream_t s);
+hipError_t launch_bw_after(const Graph& g, const int32_t* perm, const int32_t* iperm,
+                           int32_t* beta, SegStats* seg, hipStream_t s);
+hipError_t launch_comp_stats(const Graph& g, int32_t ncomp, const int32_t* seeds,
+                             const CompResult* results, int32_t* comp_seg_off, SegStats* seg,
+                             hipStream_t s);
+hipError_t launch_exclusive_scan(const int32_t* in, int32_t* out, int32_t count, int32_t* tmp,
+                                 int32_t* total_out, hipStream_t s);
+
+struct BfsParams {
+  const int32_t* rowptr;
+  const int32_t* colidx;
+  const int32_t* deg;
+  int32_t* visit;
+  uint32_t* claim;
+  int32_t* q;
+  int32_t* tmp;
+  int32_t* perm;
+  int32_t* iperm;
+  const CompTask* tasks;
+  int32_t ntasks;
+  CompResult* results;
+  TeamCtl* teams;
+  GlobalCtl* gctl;
+  int32_t n;
+  int32_t team_size;
+  int32_t pp_variant;
+  int32_t reverse_mode;
+  int32_t narrow_cutoff;
+  int32_t use_queue;
+};
+
+hipError_t launch_order_small(const BfsParams& p, int32_t nblocks, int32_t threads,
+                              hipStream_t s);
+hipError_t launch_order_big(const BfsParams& p, int32_t threads, hipStream_t s);
+int max_team_blocks(int32_t threads);
+
+}  // namespace rcm

@@ -1,0 +1,506 @@
+// Preparation and finishing kernels of the ordering:
+//   - CSR checks, degrees and the bandwidth / envelope size of the input
+//     order (Section II-A definitions; degrees form the vector D used by
+//     Algorithms 3 and 4);
+//   - the optional full check (duplicates, symmetry);
+//   - connected components by lock-free union-find (the paper orders each
+//     component separately, Section III-B), their sizes, seeds (lowest id)
+//     and label offsets;
+//   - bandwidth / envelope size of the result and per-graph statistics.
+// All of this is plain memory-bound integer work: coalesced row scans, one
+// random gather per entry, and block-level reductions that issue one global
+// atomic per block and segment.
+
+#include "rcm_common.hpp"
+
+namespace rcm {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+inline int grid_for(int64_t work, int threads, int max_blocks = 8192) {
+  int64_t b = (work + threads - 1) / threads;
+  if (b < 1) b = 1;
+  if (b > max_blocks) b = max_blocks;
+  return static_cast<int>(b);
+}
+
+// ---------------------------------------------------------------------------
+// Row checks + degree + beta of the input order.
+// ---------------------------------------------------------------------------
+__global__ void k_validate_scan(int32_t n, int32_t nnz, const int32_t* __restrict__ rowptr,
+                                const int32_t* __restrict__ colidx, int32_t* __restrict__ deg,
+                                int32_t* __restrict__ beta, int32_t* __restrict__ err) {
+  for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const int32_t a = rowptr[i];
+    const int32_t b = rowptr[i + 1];
+    if (a < 0 || b < a || b > nnz) {
+      deg[i] = 0;
+      beta[i] = 0;
+      atomicOr(err, 1);
+      continue;
+    }
+    int32_t d = 0;
+    int32_t mn = i;
+    bool bad = false;
+    for (int32_t k = a; k < b; ++k) {
+      const int32_t c = colidx[k];
+      if (c < 0 || c >= n) { bad = true; continue; }
+      d += (c != i);
+      mn = c < mn ? c : mn;
+    }
+    if (bad) atomicOr(err, 1);
+    deg[i] = d;
+    beta[i] = i - mn;
+  }
+}
+
+// For graphs made of several segments (batched calls), an entry must stay
+// inside its row's segment.
+__global__ void k_check_segments(int32_t n, const int32_t* __restrict__ rowptr,
+                                 const int32_t* __restrict__ colidx,
+                                 const int32_t* __restrict__ seg_off, int nseg,
+                                 int32_t* __restrict__ err) {
+  for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const int s = find_segment(seg_off, nseg, i);
+    const int32_t lo = seg_off[s], hi = seg_off[s + 1];
+    for (int32_t k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+      const int32_t c = colidx[k];
+      if (c < lo || c >= hi) { atomicOr(err, 1); break; }
+    }
+  }
+}
+
+// Segmented max/sum of a per-vertex value.  Block b covers
+// [b*chunk, (b+1)*chunk); for every segment intersecting it, one block
+// reduction and one pair of atomics.  Segments are contiguous vertex ranges.
+__global__ void k_seg_reduce(const int32_t* __restrict__ vals, int32_t count, int32_t chunk,
+                             const int32_t* __restrict__ seg_off, int nseg,
+                             SegStats* __restrict__ out, int which) {
+  __shared__ long long red[16];
+  const int32_t c0 = blockIdx.x * chunk;
+  if (c0 >= count) return;
+  const int32_t c1 = min(count, c0 + chunk);
+  int s = find_segment(seg_off, nseg, c0);
+  for (; s < nseg && seg_off[s] < c1; ++s) {
+    const int32_t lo = max(c0, seg_off[s]);
+    const int32_t hi = min(c1, seg_off[s + 1]);
+    long long mx = 0, sm = 0;
+    for (int32_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+      const long long v = vals[i];
+      mx = v > mx ? v : mx;
+      sm += v;
+    }
+    mx = block_max_i64(mx, red);
+    sm = block_sum_i64(sm, red);
+    if (threadIdx.x == 0 && hi > lo) {
+      unsigned long long* pmax = which == 0 ? &out[s].bw_before : &out[s].bw_after;
+      unsigned long long* psum = which == 0 ? &out[s].prof_before : &out[s].prof_after;
+      atomicMax(pmax, static_cast<unsigned long long>(mx));
+      atomicAdd(psum, static_cast<unsigned long long>(sm));
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Full check: duplicates in a row, and (i, j) present => (j, i) present.
+// ---------------------------------------------------------------------------
+__global__ void k_full_check(int32_t n, const int32_t* __restrict__ rowptr,
+                             const int32_t* __restrict__ colidx, int32_t* __restrict__ err_dup,
+                             int32_t* __restrict__ err_sym) {
+  for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const int32_t a = rowptr[i], b = rowptr[i + 1];
+    bool dup = false, asym = false;
+    for (int32_t k = a; k < b && !dup; ++k) {
+      const int32_t c = colidx[k];
+      for (int32_t k2 = k + 1; k2 < b; ++k2)
+        if (colidx[k2] == c) { dup = true; break; }
+    }
+    for (int32_t k = a; k < b && !asym; ++k) {
+      const int32_t c = colidx[k];
+      bool found = false;
+      for (int32_t k2 = rowptr[c]; k2 < rowptr[c + 1]; ++k2)
+        if (colidx[k2] == i) { found = true; break; }
+      asym = !found;
+    }
+    if (dup) atomicOr(err_dup, 1);
+    if (asym) atomicOr(err_sym, 1);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Connected components: union-find where a root is only ever hooked under a
+// smaller root, so the final root of each tree is the component's lowest id.
+// parent[] is read and written with device-scope atomics (it changes under
+// other work-groups' feet).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int32_t uf_find(int32_t* parent, int32_t x) {
+  while (true) {
+    const int32_t p = ld_relaxed(parent + x);
+    if (p == x) return x;
+    const int32_t gp = ld_relaxed(parent + p);
+    if (gp != p) {
+      // path halving: gp is an ancestor of x, so pointing x at it is safe
+      __hip_atomic_store(parent + x, gp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    x = gp;
+  }
+}
+
+__global__ void k_cc_init(int32_t n, int32_t* __restrict__ parent) {
+  for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    parent[i] = i;
+}
+
+__global__ void k_cc_hook(int32_t n, const int32_t* __restrict__ rowptr,
+                          const int32_t* __restrict__ colidx, int32_t* parent) {
+  for (int32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += gridDim.x * blockDim.x) {
+    for (int32_t k = rowptr[u]; k < rowptr[u + 1]; ++k) {
+      const int32_t v = colidx[k];
+      if (v >= u) continue;  // each undirected edge once
+      int32_t a = uf_find(parent, u);
+      int32_t b = uf_find(parent, v);
+      while (a != b) {
+        if (a < b) { const int32_t t = a; a = b; b = t; }
+        // hook the larger root a under the smaller root b
+        int32_t expected = a;
+        if (__hip_atomic_compare_exchange_strong(parent + a, &expected, b, __ATOMIC_RELAXED,
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+          break;
+        a = uf_find(parent, expected);
+        b = uf_find(parent, b);
+      }
+    }
+  }
+}
+
+__global__ void k_cc_compress(int32_t n, int32_t* parent, int32_t* __restrict__ flags) {
+  for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const int32_t r = uf_find(parent, i);
+    parent[i] = r;
+    flags[i] = (r == i);
+  }
+}
+
+// Component sizes: histogram of roots with a small LDS hash per block, so a
+// giant component costs one global atomic per block.
+__global__ void k_cc_sizes(int32_t n, const int32_t* __restrict__ parent,
+                           int32_t* __restrict__ csize) {
+  constexpr int H = 256;
+  __shared__ int32_t keys[H];
+  __shared__ int32_t cnts[H];
+  for (int h = threadIdx.x; h < H; h += blockDim.x) { keys[h] = -1; cnts[h] = 0; }
+  __syncthreads();
+  for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const int32_t r = parent[i];
+    uint32_t h = (static_cast<uint32_t>(r) * 2654435761u) >> 24;
+    bool done = false;
+    for (int probe = 0; probe < 8 && !done; ++probe, h = (h + 1) & (H - 1)) {
+      int32_t k = keys[h];
+      if (k == -1) {
+        k = atomicCAS(&keys[h], -1, r);
+        if (k == -1) k = r;
+      }
+      if (k == r) { atomicAdd(&cnts[h], 1); done = true; }
+    }
+    if (!done) atomicAdd(&csize[r], 1);
+  }
+  __syncthreads();
+  for (int h = threadIdx.x; h < H; h += blockDim.x)
+    if (keys[h] >= 0 && cnts[h] > 0) atomicAdd(&csize[keys[h]], cnts[h]);
+}
+
+__global__ void k_scatter_seeds(int32_t n, const int32_t* __restrict__ flags,
+                                const int32_t* __restrict__ pos, int32_t* __restrict__ seeds) {
+  for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    if (flags[i]) seeds[pos[i]] = i;
+}
+
+// ---------------------------------------------------------------------------
+// Exclusive scan (int32), 4096 elements per block.
+// ---------------------------------------------------------------------------
+constexpr int kScanPer = 16;
+constexpr int kScanTile = kThreads * kScanPer;
+
+__global__ void k_scan_reduce(const int32_t* __restrict__ in, int32_t count,
+                              int32_t* __restrict__ sums) {
+  __shared__ long long red[16];
+  const int32_t base = blockIdx.x * kScanTile;
+  long long s = 0;
+  for (int j = 0; j < kScanPer; ++j) {
+    const int32_t i = base + j * kThreads + threadIdx.x;
+    if (i < count) s += in[i];
+  }
+  s = block_sum_i64(s, red);
+  if (threadIdx.x == 0) sums[blockIdx.x] = static_cast<int32_t>(s);
+}
+
+__global__ void k_scan_sums(int32_t* __restrict__ sums, int32_t nb, int32_t* __restrict__ total) {
+  __shared__ int scratch[17];
+  int run = 0;
+  for (int32_t b0 = 0; b0 < nb; b0 += blockDim.x) {
+    const int32_t i = b0 + threadIdx.x;
+    const int x = i < nb ? sums[i] : 0;
+    int tot;
+    const int ex = block_excl_scan(x, scratch, &tot);
+    if (i < nb) sums[i] = run + ex;
+    run += tot;
+  }
+  if (threadIdx.x == 0 && total) *total = run;
+}
+
+__global__ void k_scan_apply(const int32_t* __restrict__ in, int32_t* __restrict__ out,
+                             int32_t count, const int32_t* __restrict__ sums) {
+  __shared__ int scratch[17];
+  const int32_t base = blockIdx.x * kScanTile;
+  // each thread owns kScanPer consecutive elements
+  int vals[kScanPer];
+  int local = 0;
+  for (int j = 0; j < kScanPer; ++j) {
+    const int32_t i = base + threadIdx.x * kScanPer + j;
+    vals[j] = i < count ? in[i] : 0;
+    local += vals[j];
+  }
+  int tot;
+  int ex = block_excl_scan(local, scratch, &tot);
+  int run = sums[blockIdx.x] + ex;
+  for (int j = 0; j < kScanPer; ++j) {
+    const int32_t i = base + threadIdx.x * kScanPer + j;
+    if (i < count) out[i] = run;
+    run += vals[j];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Component tasks.
+// ---------------------------------------------------------------------------
+__global__ void k_gather_sizes(int32_t ncomp, const int32_t* __restrict__ seeds,
+                               const int32_t* __restrict__ csize, int32_t* __restrict__ sizes) {
+  for (int32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < ncomp; c += gridDim.x * blockDim.x)
+    sizes[c] = csize[seeds[c]];
+}
+
+__device__ __forceinline__ void append_task(CompTask* list, int32_t* counter, const CompTask& t) {
+  const int32_t at = atomicAdd(counter, 1);
+  list[at] = t;
+}
+
+__global__ void k_build_tasks(int32_t ncomp, const int32_t* __restrict__ seeds,
+                              const int32_t* __restrict__ sizes, const int32_t* __restrict__ offs,
+                              const int32_t* __restrict__ seg_off, int nseg, int32_t small_cutoff,
+                              int32_t reverse_mode, CompTask* tasks_single, CompTask* tasks_small,
+                              CompTask* tasks_big, int32_t* counts, CompResult* results) {
+  for (int32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < ncomp; c += gridDim.x * blockDim.x) {
+    CompTask t;
+    t.seed = seeds[c];
+    t.size = sizes[c];
+    t.offset = offs[c];
+    t.index = c;
+    const int s = find_segment(seg_off, nseg, t.seed);
+    // label t of the component (0-based, Cuthill-McKee order) lands at
+    // position anchor - t after reversal
+    t.anchor = reverse_mode == 0 ? t.offset + t.size - 1
+                                 : seg_off[s] + seg_off[s + 1] - 1 - t.offset;
+    CompResult r;
+    r.root = t.seed;
+    r.nbfs = 0;
+    r.levels = 0;
+    r.seg = s;
+    r.m = 0;
+    results[c] = r;
+    if (t.size == 1)
+      append_task(tasks_single, counts + 0, t);
+    else if (t.size <= small_cutoff)
+      append_task(tasks_small, counts + 1, t);
+    else
+      append_task(tasks_big, counts + 2, t);
+  }
+}
+
+__global__ void k_singletons(const CompTask* __restrict__ tasks, int32_t count,
+                             int32_t* __restrict__ q, int32_t* __restrict__ perm,
+                             int32_t* __restrict__ iperm, CompResult* __restrict__ results) {
+  for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
+    const CompTask t = tasks[i];
+    q[t.offset] = t.seed;
+    perm[t.anchor] = t.seed;
+    iperm[t.seed] = t.anchor;
+    // an isolated vertex: Algorithm 2 computes two one-level structures
+    results[t.index].root = t.seed;
+    results[t.index].nbfs = 2;
+    results[t.index].levels = 1;
+    results[t.index].m = 0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Result statistics.
+// ---------------------------------------------------------------------------
+__global__ void k_beta_after(int32_t n, const int32_t* __restrict__ rowptr,
+                             const int32_t* __restrict__ colidx, const int32_t* __restrict__ perm,
+                             const int32_t* __restrict__ iperm, int32_t* __restrict__ beta) {
+  for (int32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+    const int32_t v = perm[k];
+    int32_t f = k;
+    for (int32_t e = rowptr[v]; e < rowptr[v + 1]; ++e) {
+      const int32_t j = iperm[colidx[e]];
+      f = j < f ? j : f;
+    }
+    beta[k] = k - f;
+  }
+}
+
+// Per-segment component counts: comp_seg_off[g] = number of seeds below seg_off[g].
+__global__ void k_comp_seg_bounds(int nseg, const int32_t* __restrict__ seg_off,
+                                  const int32_t* __restrict__ seeds, int32_t ncomp,
+                                  int32_t* __restrict__ comp_seg_off) {
+  for (int g = blockIdx.x * blockDim.x + threadIdx.x; g <= nseg; g += gridDim.x * blockDim.x) {
+    const int32_t key = seg_off[g];
+    int32_t lo = 0, hi = ncomp;
+    while (lo < hi) {
+      const int32_t mid = (lo + hi) >> 1;
+      if (seeds[mid] < key) lo = mid + 1; else hi = mid;
+    }
+    comp_seg_off[g] = lo;
+  }
+}
+
+__global__ void k_comp_stats(int32_t ncomp, int32_t chunk, const CompResult* __restrict__ res,
+                             const int32_t* __restrict__ comp_seg_off, int nseg,
+                             SegStats* __restrict__ out) {
+  __shared__ long long red[16];
+  const int32_t c0 = blockIdx.x * chunk;
+  if (c0 >= ncomp) return;
+  const int32_t c1 = min(ncomp, c0 + chunk);
+  int s = find_segment(comp_seg_off, nseg, c0);
+  for (; s < nseg && comp_seg_off[s] < c1; ++s) {
+    const int32_t lo = max(c0, comp_seg_off[s]);
+    const int32_t hi = min(c1, comp_seg_off[s + 1]);
+    long long diam = 0, nb = 0, nl = 0, edges = 0;
+    for (int32_t c = lo + threadIdx.x; c < hi; c += blockDim.x) {
+      const CompResult r = res[c];
+      diam = (r.levels - 1) > diam ? (r.levels - 1) : diam;
+      nb += r.nbfs;
+      nl += r.levels;
+      edges += static_cast<long long>(r.nbfs + 1) * r.m;
+    }
+    diam = block_max_i64(diam, red);
+    nb = block_sum_i64(nb, red);
+    nl = block_sum_i64(nl, red);
+    edges = block_sum_i64(edges, red);
+    if (threadIdx.x == 0 && hi > lo) {
+      atomicAdd(&out[s].ncomp, hi - lo);
+      atomicMax(&out[s].diameter, static_cast<int32_t>(diam));
+      atomicAdd(&out[s].nbfs, static_cast<int32_t>(nb));
+      atomicAdd(&out[s].nlevels, static_cast<int32_t>(nl));
+      atomicAdd(&out[s].edges, static_cast<unsigned long long>(edges));
+    }
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Launchers.
+// ---------------------------------------------------------------------------
+hipError_t launch_exclusive_scan(const int32_t* in, int32_t* out, int32_t count, int32_t* tmp,
+                                 int32_t* total_out, hipStream_t s) {
+  if (count <= 0) {
+    if (total_out) return hipMemsetAsync(total_out, 0, sizeof(int32_t), s);
+    return hipSuccess;
+  }
+  const int nb = (count + kScanTile - 1) / kScanTile;
+  k_scan_reduce<<<nb, kThreads, 0, s>>>(in, count, tmp);
+  k_scan_sums<<<1, 1024, 0, s>>>(tmp, nb, total_out);
+  k_scan_apply<<<nb, kThreads, 0, s>>>(in, out, count, tmp);
+  return hipGetLastError();
+}
+
+hipError_t launch_validate_scan(const Graph& g, int32_t* deg, int32_t* beta, SegStats* seg,
+                                int32_t* err, hipStream_t s) {
+  k_validate_scan<<<grid_for(g.n, kThreads), kThreads, 0, s>>>(g.n, g.nnz, g.rowptr, g.colidx,
+                                                                deg, beta, err);
+  if (g.nseg > 1)
+    k_check_segments<<<grid_for(g.n, kThreads), kThreads, 0, s>>>(g.n, g.rowptr, g.colidx,
+                                                                   g.seg_off, g.nseg, err);
+  constexpr int32_t chunk = 8192;
+  const int nb = (g.n + chunk - 1) / chunk;
+  k_seg_reduce<<<nb, kThreads, 0, s>>>(beta, g.n, chunk, g.seg_off, g.nseg, seg, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_full_check(const Graph& g, int32_t* err_dup, int32_t* err_sym, hipStream_t s) {
+  k_full_check<<<grid_for(g.n, kThreads), kThreads, 0, s>>>(g.n, g.rowptr, g.colidx, err_dup,
+                                                             err_sym);
+  return hipGetLastError();
+}
+
+hipError_t launch_components(const Graph& g, int32_t* parent, int32_t* csize, int32_t* flags,
+                             int32_t* scan_tmp, int32_t* seeds, int32_t* num_comps,
+                             hipStream_t s) {
+  const int nb = grid_for(g.n, kThreads);
+  k_cc_init<<<nb, kThreads, 0, s>>>(g.n, parent);
+  k_cc_hook<<<nb, kThreads, 0, s>>>(g.n, g.rowptr, g.colidx, parent);
+  k_cc_compress<<<nb, kThreads, 0, s>>>(g.n, parent, flags);
+  hipError_t e = hipMemsetAsync(csize, 0, sizeof(int32_t) * static_cast<size_t>(g.n), s);
+  if (e != hipSuccess) return e;
+  k_cc_sizes<<<grid_for(g.n, kThreads, 2048), kThreads, 0, s>>>(g.n, parent, csize);
+  // positions of seeds in ascending id order; reuse seeds as the scan output
+  // then scatter into seeds' final slots (scan output lives in scan_tmp tail)
+  int32_t* pos = scan_tmp;
+  int32_t* blk = scan_tmp + g.n;
+  e = launch_exclusive_scan(flags, pos, g.n, blk, num_comps, s);
+  if (e != hipSuccess) return e;
+  k_scatter_seeds<<<nb, kThreads, 0, s>>>(g.n, flags, pos, seeds);
+  return hipGetLastError();
+}
+
+hipError_t launch_tasks(const Graph& g, int32_t ncomp, const int32_t* seeds, const int32_t* csize,
+                        int32_t small_cutoff, int32_t reverse_mode, CompTask* tasks_single,
+                        CompTask* tasks_small, CompTask* tasks_big, int32_t* counts,
+                        int32_t* sizes, int32_t* offs, int32_t* scan_blk, CompResult* results,
+                        hipStream_t s) {
+  const int nb = grid_for(ncomp, kThreads);
+  k_gather_sizes<<<nb, kThreads, 0, s>>>(ncomp, seeds, csize, sizes);
+  hipError_t e = launch_exclusive_scan(sizes, offs, ncomp, scan_blk, nullptr, s);
+  if (e != hipSuccess) return e;
+  e = hipMemsetAsync(counts, 0, 3 * sizeof(int32_t), s);
+  if (e != hipSuccess) return e;
+  k_build_tasks<<<nb, kThreads, 0, s>>>(ncomp, seeds, sizes, offs, g.seg_off, g.nseg,
+                                        small_cutoff, reverse_mode, tasks_single, tasks_small,
+                                        tasks_big, counts, results);
+  return hipGetLastError();
+}
+
+hipError_t launch_singletons(const CompTask* tasks, int32_t count, int32_t* q, int32_t* perm,
+                             int32_t* iperm, CompResult* results, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  k_singletons<<<grid_for(count, kThreads), kThreads, 0, s>>>(tasks, count, q, perm, iperm,
+                                                              results);
+  return hipGetLastError();
+}
+
+hipError_t launch_bw_after(const Graph& g, const int32_t* perm, const int32_t* iperm,
+                           int32_t* beta, SegStats* seg, hipStream_t s) {
+  k_beta_after<<<grid_for(g.n, kThreads), kThreads, 0, s>>>(g.n, g.rowptr, g.colidx, perm, iperm,
+                                                            beta);
+  constexpr int32_t chunk = 8192;
+  const int nb = (g.n + chunk - 1) / chunk;
+  k_seg_reduce<<<nb, kThreads, 0, s>>>(beta, g.n, chunk, g.seg_off, g.nseg, seg, 1);
+  return hipGetLastError();
+}
+
+hipError_t launch_comp_stats(const Graph& g, int32_t ncomp, const int32_t* seeds,
+                             const CompResult* results, int32_t* comp_seg_off, SegStats* seg,
+                             hipStream_t s) {
+  if (ncomp <= 0) return hipSuccess;
+  k_comp_seg_bounds<<<grid_for(g.nseg + 1, kThreads), kThreads, 0, s>>>(g.nseg, g.seg_off, seeds,
+                                                                       ncomp, comp_seg_off);
+  constexpr int32_t chunk = 4096;
+  const int nb = (ncomp + chunk - 1) / chunk;
+  k_comp_stats<<<nb, kThreads, 0, s>>>(ncomp, chunk, results, comp_seg_off, g.nseg, seg);
+  return hipGetLastError();
+}
+
+}  // namespace rcm

@@ -1,0 +1,220 @@
+"""GPU parity: the HIP library's permutation and statistics equal the CPU
+oracle's bit for bit (the ordering is integer work; every tie is broken by a
+fixed rule, so the result is unique)."""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1610_08128_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_order(g, **opts):
+    import torch
+    from paper_1610_08128_amd import rcm
+
+    rp = torch.from_numpy(g.rowptr).cuda()
+    ci = torch.from_numpy(g.colidx if g.colidx.size else np.zeros(1, np.int32)).cuda()
+    perm, iperm, st = rcm.order(rp, ci, return_iperm=True, **opts)
+    torch.cuda.synchronize()
+    return perm.cpu().numpy(), iperm.cpu().numpy(), st
+
+
+def check(g, *, pp_variant=0, reverse_mode=0, **gpu_opts):
+    _say(f"case {g.name} n={g.n} nnz={g.nnz} pp={pp_variant} rev={reverse_mode} {gpu_opts}")
+    want = oracle.rcm(g.n, g.rowptr, g.colidx, pp_variant=pp_variant, reverse_mode=reverse_mode)
+    assert want.status == oracle.OK
+    perm, iperm, st = gpu_order(g, pp_variant=pp_variant, reverse_mode=reverse_mode, **gpu_opts)
+    if not np.array_equal(perm, want.perm):
+        bad = np.nonzero(perm != want.perm)[0]
+        raise AssertionError(f"perm differs at {bad.size} positions, first {bad[:10]}: "
+                             f"gpu {perm[bad[:10]]} oracle {want.perm[bad[:10]]}")
+    assert np.array_equal(iperm, want.iperm)
+    assert st == want.stats, (st, want.stats)
+    return st
+
+
+def _tiny_graphs():
+    gs = [I.path(1), I.path(2), I.path(3), I.path(7, seed=1), I.complete(2), I.complete(6),
+          I.star(9, 4), I.cycle(8, seed=3), I.grid2d(3, 3, seed=2), I.grid2d(4, 9),
+          I.grid2d(5, 12, seed=5), I.random_tree(40, 3), I.drop_diagonal(I.grid2d(4, 4, seed=1)),
+          I.add_random_self_loops(I.erdos_renyi(30, 0.1, 4), 0.4, 4),
+          I.from_edges(6, np.zeros(0), np.zeros(0), diag=False),
+          I.disjoint_union([I.path(3), I.complete(4), I.path(1), I.cycle(5)], seed=9)]
+    a, b, c, e, f = 0, 1, 2, 3, 4
+    gs.append(I.from_edges(5, np.array([a, a, b, e, b]), np.array([b, e, c, c, f])))
+    for i, g in enumerate(gs):
+        g.name = g.name or f"tiny{i}"
+    return gs
+
+
+@pytest.mark.parametrize("idx", range(17))
+def test_tiny_graphs(idx):
+    g = _tiny_graphs()[idx]
+    for pp in (0, 1):
+        for rev in (0, 1):
+            check(g, pp_variant=pp, reverse_mode=rev)
+
+
+def _random_graph(seed):
+    rng = np.random.default_rng(seed)
+    parts = []
+    for i in range(int(rng.integers(1, 5))):
+        kind = int(rng.integers(0, 5))
+        if kind == 0:
+            parts.append(I.erdos_renyi(int(rng.integers(1, 300)), float(rng.uniform(0.003, 0.05)),
+                                       seed * 7 + i))
+        elif kind == 1:
+            parts.append(I.grid2d(int(rng.integers(1, 30)), int(rng.integers(1, 30)),
+                                  seed=seed + i))
+        elif kind == 2:
+            parts.append(I.random_tree(int(rng.integers(1, 200)), seed + i))
+        elif kind == 3:
+            parts.append(I.grid3d(int(rng.integers(1, 8)), int(rng.integers(1, 8)),
+                                  int(rng.integers(1, 8)), seed=seed + i))
+        else:
+            parts.append(I.rgg_patches(int(rng.integers(20, 400)), seed + i))
+    g = I.disjoint_union(parts, seed=seed)
+    if seed % 3 == 1:
+        g = I.add_random_self_loops(g, 0.2, seed)
+    g.name = f"random{seed}"
+    return g
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_random_graphs_small_path(seed):
+    g = _random_graph(seed)
+    check(g, pp_variant=seed % 2, reverse_mode=(seed // 2) % 2)
+
+
+@pytest.mark.parametrize("seed", range(12))
+@pytest.mark.parametrize("team", [1, 2, 8])
+def test_random_graphs_team_path(seed, team):
+    """small_cutoff=1 sends every non-isolated component to the team path."""
+    g = _random_graph(100 + seed)
+    check(g, small_cutoff=1, team_size=team, block_threads=256)
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3, 4, 5])
+def test_grid_64x64(seed):
+    g = I.config(0, seed=seed)
+    st = check(g)
+    assert st["bandwidth_after"] == 64 and st["profile_after"] == 176736
+    check(g, small_cutoff=1)
+
+
+@pytest.mark.parametrize("team,threads", [(8, 1024), (4, 512), (16, 256)])
+def test_grid_128_cubed(team, threads):
+    g = I.config(1)
+    check(g, team_size=team, block_threads=threads)
+
+
+def test_strip_32x500000():
+    g = I.config(2)
+    check(g)
+
+
+def test_repeated_runs_identical():
+    g = I.config(0, seed=11)
+    first = gpu_order(g)[0]
+    for team in (1, 2, 3, 8):
+        for _ in range(2):
+            assert np.array_equal(gpu_order(g, small_cutoff=1, team_size=team)[0], first)
+    assert np.array_equal(gpu_order(g, small_cutoff=1 << 20)[0], first)
+
+
+def test_status_codes_on_gpu():
+    import torch
+    from paper_1610_08128_amd import rcm
+
+    g = I.path(6)
+    bad = g.colidx.copy()
+    bad[2] = 6
+    with pytest.raises(rcm.RcmError) as e:
+        rcm.order(torch.from_numpy(g.rowptr).cuda(), torch.from_numpy(bad).cuda())
+    assert e.value.status == rcm.ERR_BAD_CSR
+    badr = g.rowptr.copy()
+    badr[3] = badr[2] - 1
+    with pytest.raises(rcm.RcmError) as e:
+        rcm.order(torch.from_numpy(badr).cuda(), torch.from_numpy(g.colidx).cuda())
+    assert e.value.status == rcm.ERR_BAD_CSR
+    # a duplicated entry (0, 1) that keeps the pattern symmetric as a set:
+    # only the full check rejects it
+    rp = np.array([0, 3, 6, 8], np.int32)
+    ci = np.array([0, 1, 1, 0, 1, 2, 1, 2], np.int32)
+    assert oracle.validate(3, rp, ci, True) == oracle.ERR_BAD_CSR
+    with pytest.raises(rcm.RcmError) as e:
+        rcm.order(torch.from_numpy(rp).cuda(), torch.from_numpy(ci).cuda(), check_full=True)
+    assert e.value.status == rcm.ERR_BAD_CSR
+    # an asymmetric pattern without the full check: the traversal notices that
+    # it leaves a component and reports it instead of writing out of bounds
+    dup = g.colidx.copy()
+    dup[1] = dup[0]
+    with pytest.raises(rcm.RcmError) as e:
+        rcm.order(torch.from_numpy(g.rowptr).cuda(), torch.from_numpy(dup).cuda())
+    assert e.value.status == rcm.ERR_NOT_SYMMETRIC
+    rp = np.array([0, 2, 3, 4, 5, 6], np.int32)
+    ci = np.array([0, 4, 1, 2, 3, 4], np.int32)
+    with pytest.raises(rcm.RcmError) as e:
+        rcm.order(torch.from_numpy(rp).cuda(), torch.from_numpy(ci).cuda(), check_full=True)
+    assert e.value.status == rcm.ERR_NOT_SYMMETRIC
+    assert oracle.validate(5, rp, ci, True) == oracle.ERR_NOT_SYMMETRIC
+
+
+def test_caller_workspace_and_stream():
+    import torch
+    from paper_1610_08128_amd import rcm
+
+    g = I.config(0, seed=3)
+    want = oracle.rcm(g.n, g.rowptr, g.colidx)
+    nbytes = rcm.workspace_bytes(g.n, g.nnz)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    s = torch.cuda.Stream()
+    rp = torch.from_numpy(g.rowptr).cuda()
+    ci = torch.from_numpy(g.colidx).cuda()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        perm, st = rcm.order(rp, ci, workspace=ws)
+    s.synchronize()
+    assert np.array_equal(perm.cpu().numpy(), want.perm)
+    small = torch.empty(nbytes - 256, dtype=torch.uint8, device="cuda")
+    with pytest.raises(rcm.RcmError) as e:
+        rcm.order(rp, ci, workspace=small)
+    assert e.value.status == rcm.ERR_WORKSPACE_TOO_SMALL
+
+
+def _check_batch(graphs, **opts):
+    import torch
+    from paper_1610_08128_amd import rcm
+
+    vo, no, rp, ci = I.concat_batch(graphs)
+    _say(f"batch of {len(graphs)} graphs, {vo[-1]} vertices, {no[-1]} nnz {opts}")
+    perm, stats = rcm.order_batched(vo, no, torch.from_numpy(rp).cuda(),
+                                    torch.from_numpy(ci).cuda(), **opts)
+    perm = perm.cpu().numpy()
+    for i, g in enumerate(graphs):
+        want = oracle.rcm(g.n, g.rowptr, g.colidx, pp_variant=opts.get("pp_variant", 0),
+                          reverse_mode=opts.get("reverse_mode", 0))
+        assert np.array_equal(perm[vo[i]:vo[i + 1]], want.perm), f"graph {i}"
+        assert stats[i] == want.stats, (i, stats[i], want.stats)
+
+
+def test_batched_small():
+    graphs = [_random_graph(200 + i) for i in range(10)] + [I.path(1), I.complete(5)]
+    _check_batch(graphs)
+    _check_batch(graphs, reverse_mode=1, pp_variant=1)
+    _check_batch(graphs, small_cutoff=1, team_size=4)
+
+
+def test_batched_512():
+    graphs = I.batch_graphs(512, seed=4)
+    _check_batch(graphs)
