@@ -91,6 +91,10 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=12.0,
                     help="seconds of oracle work for the CPU baseline (0 = skip)")
     ap.add_argument("--no-check", action="store_true", help="skip the oracle comparison")
+    ap.add_argument("--calibrate-copy-mb", type=int, default=0,
+                    help="before the timed steps, run one plain device copy of this many MiB "
+                         "(outside the timed region) so that a counter profile of the same "
+                         "command has a kernel of known traffic to scale by")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs on a single MI355X "
@@ -111,6 +115,12 @@ def main():
     opts = dict(team_size=args.team_size, block_threads=args.block_threads)
     ws = torch.empty(rcm.workspace_bytes(g.n, g.nnz, **opts), dtype=torch.uint8, device=dev)
     stream = torch.cuda.Stream(device=dev)
+    if args.calibrate_copy_mb > 0:
+        src = torch.ones(args.calibrate_copy_mb * (1 << 20) // 4, dtype=torch.int32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     torch.cuda.synchronize()
 
     def step():
@@ -183,15 +193,16 @@ def main():
             "nnz": g.nnz,
             "pseudo_diameter": st["pseudo_diameter"],
             "bfs_passes": st["num_bfs"] + 1,
-            "team_size": args.team_size or 8,
-            "block_threads": args.block_threads or 1024,
+            "team_size": args.team_size or 32,
+            "block_threads": args.block_threads or 512,
         },
         "teps": round(teps, 1),
         "nnz_per_s": round(g.nnz * args.steps / dt, 1),
         "edges_traversed_per_ordering": st["edges_traversed"],
         "bandwidth": [st["bandwidth_before"], st["bandwidth_after"]],
         "profile": [st["profile_before"], st["profile_after"]],
-        "phases_ms_last_step": {k: round(v, 4) for k, v in phases.items()},
+        "phases_ms_last_step": {k: (round(v, 4) if isinstance(v, float) else v)
+                                for k, v in phases.items()},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "matches_oracle": check,

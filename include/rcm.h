@@ -93,15 +93,15 @@ typedef struct {
                             asymmetric patterns (NOT_SYMMETRIC); costs
                             O(sum of squared row lengths)                      */
   int32_t team_size;     /* work-groups cooperating on one large component;
-                            0 = auto (8, one per XCD); 1..64                   */
-  int32_t block_threads; /* threads per work-group for the BFS kernels;
-                            0 = auto; one of 256, 512, 1024                    */
+                            0 = auto (32, four per XCD); 1..64                 */
+  int32_t block_threads; /* threads per work-group of the large-component
+                            team; 0 = auto (512); 256 or 512                   */
   int32_t small_cutoff;  /* components with at most this many vertices are
                             ordered by a single work-group each, many in
                             parallel; 0 = auto                                 */
   int32_t narrow_cutoff; /* levels narrower than this are expanded by one
                             work-group of the team without grid-wide barriers;
-                            0 = auto, -1 = never                               */
+                            0 = auto (256), -1 = never                         */
   int32_t reserved[9];
 } rcm_options;
 
@@ -163,6 +163,15 @@ typedef struct {
   float total_ms;
   float small_kernel_ms; /* the launch ordering small components, one work-group each */
   float team_kernel_ms;  /* the launch ordering large components with a team */
+  float team_pp_ms;      /* device clock of that launch: pseudo-peripheral passes */
+  float team_label_ms;   /* device clock of that launch: labelled BFS */
+  int32_t team_pp_levels;    /* levels expanded by the pseudo-peripheral passes */
+  int32_t team_label_levels; /* levels of the labelled BFS */
+  int64_t phase_ticks[12];   /* diagnostics, 100 MHz device clock of work-group 0:
+                                [0..3] wide unlabelled levels: expand, append,
+                                barrier, count; [4..7] the same for narrow
+                                levels; [8..11] wide labelled levels: claim +
+                                barrier, count + barrier, place + barrier, count */
 } rcm_timings;
 void rcm_last_timings(rcm_timings* out);
 

@@ -32,11 +32,11 @@ struct Opts {
   int pp_variant = 0;
   int reverse_mode = 0;
   int check_full = 0;
-  int team_size = 8;
-  int threads = 1024;
+  int team_size = 32;
+  int threads = 512;
   int small_threads = 256;
   int small_cutoff = 1 << 14;
-  int narrow_cutoff = 0;
+  int narrow_cutoff = 256;
 };
 
 bool parse_options(const rcm_options* o, Opts* out) {
@@ -46,17 +46,17 @@ bool parse_options(const rcm_options* o, Opts* out) {
     if (o->reverse_mode != 0 && o->reverse_mode != 1) return false;
     if (o->check_full != 0 && o->check_full != 1) return false;
     if (o->team_size < 0 || o->team_size > kMaxTeam) return false;
-    if (o->block_threads != 0 && o->block_threads != 256 && o->block_threads != 512 &&
-        o->block_threads != 1024)
+    if (o->block_threads != 0 && o->block_threads != 256 && o->block_threads != 512)
       return false;
     if (o->small_cutoff < 0) return false;
+    if (o->narrow_cutoff < -1) return false;
     r.pp_variant = o->pp_variant;
     r.reverse_mode = o->reverse_mode;
     r.check_full = o->check_full;
     if (o->team_size) r.team_size = o->team_size;
     if (o->block_threads) r.threads = o->block_threads;
     if (o->small_cutoff) r.small_cutoff = o->small_cutoff;
-    r.narrow_cutoff = o->narrow_cutoff;
+    if (o->narrow_cutoff) r.narrow_cutoff = o->narrow_cutoff;
   }
   *out = r;
   return true;
@@ -64,7 +64,7 @@ bool parse_options(const rcm_options* o, Opts* out) {
 
 // Workspace layout (every region 256-byte aligned).
 struct Layout {
-  size_t deg, beta, parent, flags, pos, csize, seeds, visit, claim, q, tmp, iperm;
+  size_t vinfo, beta, parent, flags, pos, csize, seeds, visit, claim, qi, tmp, iperm;
   size_t sizes, offs, results, t_single, t_small, t_big, scan_blk;
   size_t seg_off, comp_seg_off, segstats, gctl, teams, small_ctl, misc;
   size_t rowptr_g, colidx_g;
@@ -80,7 +80,7 @@ Layout make_layout(int64_t n, int64_t nnz, int64_t nseg, bool batched, int teams
     return at;
   };
   const size_t N = static_cast<size_t>(n);
-  L.deg = take(4 * N);
+  L.vinfo = take(16 * N);
   L.beta = take(4 * N);
   L.parent = take(4 * N);
   L.flags = take(4 * N);
@@ -89,7 +89,7 @@ Layout make_layout(int64_t n, int64_t nnz, int64_t nseg, bool batched, int teams
   L.seeds = take(4 * N);
   L.visit = take(4 * N);
   L.claim = take(4 * N);
-  L.q = take(4 * N);
+  L.qi = take(16 * N);
   L.tmp = take(4 * N);
   L.iperm = take(4 * N);
   L.sizes = take(4 * N);
@@ -124,6 +124,7 @@ struct Timer {
   hipEvent_t ev[6];
   hipEvent_t kev[4];  // around the small-component and the team launches
   bool kused[2] = {false, false};
+  long long clk[16] = {};
   int k = 0;
   explicit Timer(hipStream_t st) : s(st) {
     const char* e = std::getenv("RCM_TIMING");
@@ -152,12 +153,21 @@ struct Timer {
       t.order_ms = ms[2];
       t.after_ms = ms[3];
       (void)hipEventElapsedTime(&t.total_ms, ev[0], ev[k - 1]);
+      if (kused[0]) (void)hipEventElapsedTime(&t.small_kernel_ms, kev[0], kev[1]);
+      if (kused[1]) (void)hipEventElapsedTime(&t.team_kernel_ms, kev[2], kev[3]);
+      t.team_pp_ms = static_cast<float>(clk[0] * 1e-5);
+      t.team_label_ms = static_cast<float>(clk[1] * 1e-5);
+      t.team_pp_levels = static_cast<int32_t>(clk[2]);
+      t.team_label_levels = static_cast<int32_t>(clk[3]);
+      for (int i = 0; i < 12; ++i) t.phase_ticks[i] = clk[4 + i];
     }
     g_timings = t;
   }
   ~Timer() {
-    if (on)
+    if (on) {
       for (auto& x : ev) (void)hipEventDestroy(x);
+      for (auto& x : kev) (void)hipEventDestroy(x);
+    }
   }
 };
 
@@ -180,7 +190,7 @@ rcm_status run(const Graph& gin, const int32_t* seg_off_host, const Opts& opt, c
                hipStream_t s, Timer& timer) {
   Graph g = gin;
   const size_t N = static_cast<size_t>(g.n);
-  int32_t* deg = reinterpret_cast<int32_t*>(ws + L.deg);
+  int4* vinfo = reinterpret_cast<int4*>(ws + L.vinfo);
   int32_t* beta = reinterpret_cast<int32_t*>(ws + L.beta);
   int32_t* parent = reinterpret_cast<int32_t*>(ws + L.parent);
   int32_t* flags = reinterpret_cast<int32_t*>(ws + L.flags);
@@ -189,7 +199,7 @@ rcm_status run(const Graph& gin, const int32_t* seg_off_host, const Opts& opt, c
   int32_t* seeds = reinterpret_cast<int32_t*>(ws + L.seeds);
   int32_t* visit = reinterpret_cast<int32_t*>(ws + L.visit);
   uint32_t* claim = reinterpret_cast<uint32_t*>(ws + L.claim);
-  int32_t* q = reinterpret_cast<int32_t*>(ws + L.q);
+  int4* qi = reinterpret_cast<int4*>(ws + L.qi);
   int32_t* tmp = reinterpret_cast<int32_t*>(ws + L.tmp);
   int32_t* iperm = iperm_out ? iperm_out : reinterpret_cast<int32_t*>(ws + L.iperm);
   int32_t* sizes = reinterpret_cast<int32_t*>(ws + L.sizes);
@@ -215,7 +225,7 @@ rcm_status run(const Graph& gin, const int32_t* seg_off_host, const Opts& opt, c
 
   timer.mark();
   // 2. checks, degrees, input bandwidth/profile
-  HIP_TRY(launch_validate_scan(g, deg, beta, segstats, misc + 0, s));
+  HIP_TRY(launch_validate_scan(g, vinfo, beta, segstats, misc + 0, s));
   int32_t h[4];
   rcm_status st = read_ints(h, misc, 1, s);
   if (st != RCM_OK) return st;
@@ -244,14 +254,14 @@ rcm_status run(const Graph& gin, const int32_t* seg_off_host, const Opts& opt, c
   HIP_TRY(hipMemsetAsync(visit, 0, 4 * N, s));
   HIP_TRY(hipMemsetAsync(claim, 0xFF, 4 * N, s));
   HIP_TRY(hipMemsetAsync(gctl, 0, sizeof(GlobalCtl), s));
-  HIP_TRY(launch_singletons(t_single, n_single, q, perm_out, iperm, results, s));
+  HIP_TRY(launch_singletons(t_single, n_single, perm_out, iperm, results, s));
   BfsParams P;
   P.rowptr = g.rowptr;
   P.colidx = g.colidx;
-  P.deg = deg;
+  P.vinfo = vinfo;
   P.visit = visit;
   P.claim = claim;
-  P.q = q;
+  P.qi = qi;
   P.tmp = tmp;
   P.perm = perm_out;
   P.iperm = iperm;
@@ -281,6 +291,11 @@ rcm_status run(const Graph& gin, const int32_t* seg_off_host, const Opts& opt, c
     timer.kmark(1, true);
     HIP_TRY(launch_order_big(P, opt.threads, s));
     timer.kmark(1, false);
+    if (timer.on) {
+      HIP_TRY(hipMemcpyAsync(timer.clk, teams[0].clk, sizeof(timer.clk), hipMemcpyDeviceToHost,
+                             s));
+      HIP_TRY(hipStreamSynchronize(s));
+    }
   }
   st = read_ints(h, &gctl->error, 1, s);
   if (st != RCM_OK) return st;

@@ -11,6 +11,15 @@
 //     launch), default W = 8 so the team spans the 8 XCDs once;
 //   - small components: many single-work-group teams pulling components from
 //     an atomic queue.
+// Narrow levels (fewer vertices than the narrow cutoff) are expanded by the
+// team's first work-group alone, level after level with only __syncthreads,
+// while the others sleep until the frontier widens again or the pass ends.
+//
+// Frontier entries are (vertex, row begin, row end): the row bounds of a
+// vertex are fetched when it is discovered, in the shadow of the append, so
+// expanding the next level starts with one coalesced read.  Rows are read in
+// register batches of kRB entries so that all loads of a batch (columns,
+// then visited/claim words, then atomics) are in flight together.
 //
 // Level step of the labelled BFS (Algorithm 3), for the frontier
 // L_cur = q[cur_b, cur_e) whose labels are exactly the positions p:
@@ -18,7 +27,7 @@
 //      v unlabelled, claim[v] = min(claim[v], p) (an atomic min; claim[] of
 //      already labelled vertices holds labels < cur_b <= p, so the min leaves
 //      them alone -- this is the Select(R == -1) step).
-//   B. The children of p are the neighbours v with claim[v] == p.  Each
+//   B. The children of p are the neighbours v != u with claim[v] == p.  Each
 //      parent counts them.
 //   C. An exclusive scan of the counts over the level (in label order) gives
 //      each parent's first child label; a child's rank among its siblings is
@@ -36,6 +45,7 @@ namespace rcm {
 namespace {
 
 constexpr int kStageCap = 2048;
+constexpr int kRB = 8;  // row batch: entries of a row loaded together
 
 struct Team {
   TeamCtl* ctl;
@@ -43,7 +53,21 @@ struct Team {
   int W;
   int wid;
   unsigned long long nbar;  // barrier arrivals expected so far (thread 0 only)
+  unsigned long long woke;  // narrow episodes seen (thread 0 only)
   bool aborted;
+};
+
+struct Shared {
+  int4 srec[kStageCap];
+  int scan[17];
+  long long red[16];
+  int32_t cnt;
+  int32_t base;
+  unsigned long long key;
+  int flag;
+  int task;
+  int32_t wsum[kMaxTeam];
+  int32_t state[8];
 };
 
 // Record the first error of the launch (RCM_ERR_ABORTED for a wait that timed
@@ -56,8 +80,28 @@ __device__ __forceinline__ void flag_error(GlobalCtl* g, int code) {
                                        __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ void team_barrier(Team& t, int* s_flag) {
-  if (t.W == 1) {
+// Wait (thread 0) until *ctr >= target, giving up after the wall-clock limit
+// or when another work-group has flagged an error.  Returns false on give-up.
+__device__ __forceinline__ bool wait_at_least(Team& t, unsigned long long* ctr,
+                                              unsigned long long target, bool sleepy) {
+  long spins = 0;
+  const long long t0 = wall_clock64();
+  while (ld_relaxed(ctr) < target) {
+    if (sleepy) __builtin_amdgcn_s_sleep(2);
+    if ((++spins & 255) == 0) {
+      if (ld_relaxed(&t.g->error) != 0) return false;
+      if (wall_clock64() - t0 > kWaitLimitTicks) {
+        flag_error(t.g, RCM_ERR_ABORTED);
+        return false;
+      }
+    }
+  }
+  return true;
+}
+
+// Team barrier; `solo` = only this work-group is active (narrow mode or W=1).
+__device__ __forceinline__ void team_barrier(Team& t, Shared& S, bool solo) {
+  if (solo || t.W == 1) {
     __syncthreads();
     return;
   }
@@ -66,40 +110,37 @@ __device__ __forceinline__ void team_barrier(Team& t, int* s_flag) {
     t.nbar += static_cast<unsigned long long>(t.W);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __hip_atomic_fetch_add(&t.ctl->bar, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    int ab = 0;
-    long spins = 0;
-    const long long t0 = wall_clock64();
-    while (ld_relaxed(&t.ctl->bar) < t.nbar) {
-      if ((++spins & 1023) == 0) {
-        if (ld_relaxed(&t.g->error) != 0) {
-          ab = 1;
-          break;
-        }
-        if (wall_clock64() - t0 > kWaitLimitTicks) {
-          ab = 1;
-          flag_error(t.g, RCM_ERR_ABORTED);
-          break;
-        }
-      }
-    }
+    const bool ok = wait_at_least(t, &t.ctl->bar, t.nbar, false);
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    *s_flag = ab;
+    S.flag = ok ? 0 : 1;
   }
   __syncthreads();
-  t.aborted = *s_flag != 0;
+  t.aborted = S.flag != 0;
 }
 
-struct Shared {
-  int32_t stage[kStageCap];
-  int scan[17];
-  long long red[16];
-  int32_t cnt;
-  int32_t base;
-  unsigned long long key;
-  int flag;
-  int task;
-  int32_t wsum[kMaxTeam];
-};
+// Narrow mode hand-over.  Work-group 0 publishes the pass state and wakes
+// the others; they read it back.
+__device__ __forceinline__ void narrow_publish(Team& t, const int32_t* st) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < 8; ++i) st_relaxed(&t.ctl->narrow_state[i], st[i]);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_fetch_add(&t.ctl->wake, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+__device__ __forceinline__ void narrow_wait(Team& t, Shared& S) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    t.woke += 1;
+    const bool ok = wait_at_least(t, &t.ctl->wake, t.woke, true);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    for (int i = 0; i < 8; ++i) S.state[i] = ld_relaxed(&t.ctl->narrow_state[i]);
+    S.flag = ok ? 0 : 1;
+  }
+  __syncthreads();
+  t.aborted = S.flag != 0;
+}
 
 // Split [b, e) into W contiguous chunks; chunk of work-group wid.
 __device__ __forceinline__ void my_chunk(int32_t b, int32_t e, int W, int wid, int32_t& lo,
@@ -111,91 +152,185 @@ __device__ __forceinline__ void my_chunk(int32_t b, int32_t e, int W, int wid, i
   if (lo > e) lo = e;
 }
 
-// One level structure (Section II-A) of the component whose label block
-// starts at o, rooted at `root`.  Vertices are written level by level into
-// q[o ...].  Returns the eccentricity of root and the minimum
-// (degree << 32 | id) over the last level.
+// Load entries [k0, k0 + kRB) of the row [k0, b) (b > k0) into registers with
+// unconditional loads (indices clamped into the row), so that the whole batch
+// is in flight at once.  Lanes past the row end get the row's own vertex u,
+// which every caller treats as "not a neighbour".
+__device__ __forceinline__ void load_batch(const int32_t* __restrict__ colidx, int32_t k0,
+                                           int32_t b, int32_t u, int32_t* nb) {
+#pragma unroll
+  for (int j = 0; j < kRB; ++j) {
+    const int32_t k = k0 + j < b ? k0 + j : b - 1;
+    const int32_t c = colidx[k];
+    nb[j] = k0 + j < b ? c : u;
+  }
+}
+
+__device__ __forceinline__ int4 record(int32_t v, int4 info) {
+  return make_int4(v, info.x, info.y, info.z);
+}
+
+// ---------------------------------------------------------------------------
+// Unlabelled BFS (one level structure).
+// ---------------------------------------------------------------------------
+
+// Expand qi[lo, hi) (this work-group's share of the level).  A neighbour is
+// new when atomicMax(visit, epoch) returns an older stamp; past-the-row lanes
+// hit the parent's own stamp, which already equals epoch.  New vertices go
+// to the LDS stage or, when it is full, straight to qi[cur_e + ...].
+__device__ __forceinline__ void bfs_expand(const BfsParams& P, Shared& S, int32_t lo, int32_t hi,
+                                           int32_t cur_e, int32_t end, int32_t epoch,
+                                           int32_t* tail_slot, uint64_t& mykey) {
+  const int B = blockDim.x;
+  for (int32_t p = lo + threadIdx.x; p < hi; p += B) {
+    const int4 e = P.qi[p];
+    const int32_t u = e.x;
+    for (int32_t k0 = e.y; k0 < e.z; k0 += kRB) {
+      int32_t nb[kRB];
+      load_batch(P.colidx, k0, e.z, u, nb);
+      int32_t old[kRB];
+      int4 inf[kRB];
+      // the records are loaded alongside the atomics (both need only nb)
+#pragma unroll
+      for (int j = 0; j < kRB; ++j) inf[j] = P.vinfo[nb[j]];
+#pragma unroll
+      for (int j = 0; j < kRB; ++j) old[j] = atomicMax(&P.visit[nb[j]], epoch);
+      unsigned mask = 0;
+#pragma unroll
+      for (int j = 0; j < kRB; ++j) mask |= (old[j] < epoch ? 1u : 0u) << j;
+      if (mask == 0) continue;
+#pragma unroll
+      for (int j = 0; j < kRB; ++j) {
+        if (mask >> j & 1u) {
+          const uint64_t kv = pack_key(inf[j].z, nb[j]);
+          mykey = kv < mykey ? kv : mykey;
+        }
+      }
+      int32_t idx = atomicAdd(&S.cnt, __popc(mask));
+#pragma unroll
+      for (int j = 0; j < kRB; ++j) {
+        if (!(mask >> j & 1u)) continue;
+        const int4 r = record(nb[j], inf[j]);
+        if (idx < kStageCap) {
+          S.srec[idx] = r;
+        } else {
+          const int32_t at = atomicAdd(tail_slot, 1);
+          if (cur_e + at < end) P.qi[cur_e + at] = r;
+        }
+        ++idx;
+      }
+    }
+  }
+}
+
+// One level structure (Section II-A) of the component whose label block is
+// [o, end), rooted at `root`.  Vertices are written level by level into qi.
+// Returns the eccentricity of root and the minimum (degree << 32 | id) over
+// the last level.
 __device__ void bfs_pass(const BfsParams& P, Team& t, Shared& S, int32_t o, int32_t end,
                          int32_t root, int32_t epoch, int parity, int32_t& ecc,
                          uint64_t& lastkey) {
+  const long long clk0 = wall_clock64();
   int32_t* tail = t.ctl->tail + parity * 3;
   unsigned long long* minkey = t.ctl->minkey + parity * 3;
   if (t.wid == 0 && threadIdx.x == 0) {
-    P.q[o] = root;
+    const int4 ri = P.vinfo[root];
+    P.qi[o] = record(root, ri);
     P.visit[root] = epoch;
     for (int i = 0; i < 3; ++i) st_relaxed(tail + i, 0);
-    __hip_atomic_store(minkey + 0, pack_key(P.deg[root], root), __ATOMIC_RELAXED,
+    __hip_atomic_store(minkey + 0, pack_key(ri.z, root), __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_AGENT);
     __hip_atomic_store(minkey + 1, kMaxKey, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __hip_atomic_store(minkey + 2, kMaxKey, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
-  team_barrier(t, &S.flag);
+  team_barrier(t, S, false);
   if (t.aborted) return;
   int32_t cur_b = o, cur_e = o + 1, level = 0;
   const int B = blockDim.x;
-  while (true) {
-    const int l3 = level % 3;
-    if (threadIdx.x == 0) {
-      S.cnt = 0;
-      S.key = kMaxKey;
+  bool done = false;
+  while (!done) {
+    // narrow episode: work-group 0 alone while the frontier stays narrow
+    const bool narrow = t.W > 1 && (cur_e - cur_b) < P.narrow_cutoff;
+    if (narrow && t.wid != 0) {
+      narrow_wait(t, S);
+      if (t.aborted) return;
+      cur_b = S.state[0];
+      cur_e = S.state[1];
+      level = S.state[2];
+      done = S.state[3] != 0;
+      continue;
     }
-    __syncthreads();
-    int32_t lo, hi;
-    my_chunk(cur_b, cur_e, t.W, t.wid, lo, hi);
-    uint64_t mykey = kMaxKey;
-    for (int32_t p = lo + threadIdx.x; p < hi; p += B) {
-      const int32_t u = P.q[p];
-      const int32_t a = P.rowptr[u], b = P.rowptr[u + 1];
-      for (int32_t k = a; k < b; ++k) {
-        const int32_t v = P.colidx[k];
-        if (P.visit[v] == epoch) continue;
-        if (atomicExch(&P.visit[v], epoch) == epoch) continue;
-        const uint64_t kv = pack_key(P.deg[v], v);
-        mykey = kv < mykey ? kv : mykey;
-        const int32_t idx = atomicAdd(&S.cnt, 1);
-        if (idx < kStageCap) {
-          S.stage[idx] = v;
-        } else {
-          const int32_t at = atomicAdd(tail + l3, 1);
-          if (cur_e + at < end) P.q[cur_e + at] = v;
+    const bool solo = narrow || t.W == 1;
+    const int W = solo ? 1 : t.W;
+    const int wid = solo ? 0 : t.wid;
+    while (true) {
+      const int l3 = level % 3;
+      if (threadIdx.x == 0) {
+        S.cnt = 0;
+        S.key = kMaxKey;
+      }
+      __syncthreads();
+      int32_t lo, hi;
+      my_chunk(cur_b, cur_e, W, wid, lo, hi);
+      uint64_t mykey = kMaxKey;
+      const long long ta = wall_clock64();
+      bfs_expand(P, S, lo, hi, cur_e, end, epoch, tail + l3, mykey);
+      mykey = wave_min_u64(mykey);
+      if ((threadIdx.x & 63) == 0 && mykey != kMaxKey) atomicMin(&S.key, mykey);
+      __syncthreads();
+      const long long tb = wall_clock64();
+      if (threadIdx.x == 0) {
+        const int32_t ns = S.cnt < kStageCap ? S.cnt : kStageCap;
+        S.base = ns > 0 ? atomicAdd(tail + l3, ns) : 0;
+        if (S.key != kMaxKey) atomicMin(minkey + (level + 1) % 3, S.key);
+        if (wid == 0) {
+          // slots of the level after next; nobody reads them any more
+          st_relaxed(tail + (level + 1) % 3, 0);
+          __hip_atomic_store(minkey + (level + 2) % 3, kMaxKey, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
         }
       }
-    }
-    mykey = wave_min_u64(mykey);
-    if ((threadIdx.x & 63) == 0 && mykey != kMaxKey) atomicMin(&S.key, mykey);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      const int32_t ns = S.cnt < kStageCap ? S.cnt : kStageCap;
-      S.base = ns > 0 ? atomicAdd(tail + l3, ns) : 0;
-      if (S.key != kMaxKey) atomicMin(minkey + (level + 1) % 3, S.key);
-      if (t.wid == 0) {
-        // slots of the level after next; nobody reads them any more
-        st_relaxed(tail + (level + 1) % 3, 0);
-        __hip_atomic_store(minkey + (level + 2) % 3, kMaxKey, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
+      __syncthreads();
+      const long long tc = wall_clock64();
+      {
+        const int32_t ns = S.cnt < kStageCap ? S.cnt : kStageCap;
+        for (int32_t i = threadIdx.x; i < ns; i += B) {
+          const int32_t at = cur_e + S.base + i;
+          if (at < end) P.qi[at] = S.srec[i];
+        }
       }
+      team_barrier(t, S, solo);
+      if (t.aborted) return;
+      const int32_t cnt = ld_relaxed(tail + l3);
+      if (t.wid == 0 && threadIdx.x == 0) {
+        const long long td = wall_clock64();
+        const int slot = solo && t.W > 1 ? 8 : 4;
+        t.ctl->clk[slot + 0] += tb - ta;
+        t.ctl->clk[slot + 1] += tc - tb;
+        t.ctl->clk[slot + 2] += td - tc;
+        t.ctl->clk[slot + 3] += 1;
+      }
+      if (cnt == 0) {
+        done = true;
+        break;
+      }
+      cur_b = cur_e;
+      cur_e += cnt;
+      ++level;
+      if (cur_e > end) {  // left the component: the pattern is not symmetric
+        if (threadIdx.x == 0) flag_error(t.g, RCM_ERR_NOT_SYMMETRIC);
+        done = true;
+        break;
+      }
+      // a narrow episode ends when the frontier widens, a wide one when it
+      // narrows
+      if (narrow && (cur_e - cur_b) >= P.narrow_cutoff) break;
+      if (!narrow && t.W > 1 && (cur_e - cur_b) < P.narrow_cutoff) break;
     }
-    __syncthreads();
-    {
-      const int32_t ns = S.cnt < kStageCap ? S.cnt : kStageCap;
-      for (int32_t i = threadIdx.x; i < ns; i += B)
-        if (cur_e + S.base + i < end) P.q[cur_e + S.base + i] = S.stage[i];
-    }
-    team_barrier(t, &S.flag);
-    if (t.aborted) return;
-    const int32_t cnt = ld_relaxed(tail + l3);
-    if (cnt == 0) {
-      ecc = level;
-      lastkey = ld_relaxed(minkey + l3);
-      break;
-    }
-    cur_b = cur_e;
-    cur_e += cnt;
-    ++level;
-    if (cur_e > end) {  // left the component: the pattern is not symmetric
-      if (threadIdx.x == 0 && t.wid == 0) flag_error(t.g, RCM_ERR_NOT_SYMMETRIC);
-      t.aborted = true;
-      return;
+    if (narrow) {
+      // hand the pass state back to the sleeping work-groups
+      const int32_t st[8] = {cur_b, cur_e, level, done ? 1 : 0, 0, 0, 0, 0};
+      narrow_publish(t, st);
     }
   }
   if (cur_e != end) {
@@ -203,106 +338,243 @@ __device__ void bfs_pass(const BfsParams& P, Team& t, Shared& S, int32_t o, int3
     t.aborted = true;
     return;
   }
+  // the last level's slot is stable until the next pass of the same parity
+  ecc = level;
+  lastkey = ld_relaxed(minkey + level % 3);
   // every work-group has read the counters before the next pass reuses them
-  team_barrier(t, &S.flag);
+  team_barrier(t, S, false);
+  if (t.wid == 0 && threadIdx.x == 0) {
+    t.ctl->clk[0] += wall_clock64() - clk0;
+    t.ctl->clk[2] += level + 1;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Labelled BFS (Algorithm 3).
+// ---------------------------------------------------------------------------
+
+// (select2nd, min) SpMSpV contribution of one newly labelled vertex: its
+// label becomes a claim on every neighbour.  Lanes past the row end and
+// already labelled neighbours hold smaller claims, so the min leaves them
+// alone (the Select(R == -1) step).  Fire-and-forget atomics.
+__device__ __forceinline__ void claim_row(const BfsParams& P, int32_t v, int4 info,
+                                          uint32_t label) {
+  for (int32_t k0 = info.x; k0 < info.y; k0 += kRB) {
+    int32_t nb[kRB];
+    load_batch(P.colidx, k0, info.y, v, nb);
+#pragma unroll
+    for (int j = 0; j < kRB; ++j) atomicMin(&P.claim[nb[j]], label);
+  }
+}
+
+// Children of parent p (vertex u, row [a, b)) ranked by (degree, id) among
+// the siblings, for rows longer than a register batch.
+__device__ __forceinline__ void place_long_row(const BfsParams& P, int32_t p, int32_t u,
+                                               int32_t a, int32_t b, int32_t base, int32_t end,
+                                               long long& my_m) {
+  const uint32_t pl = static_cast<uint32_t>(p);
+  for (int32_t k0 = a; k0 < b; k0 += kRB) {
+    int32_t nb[kRB];
+    load_batch(P.colidx, k0, b, u, nb);
+    uint32_t cl[kRB];
+#pragma unroll
+    for (int j = 0; j < kRB; ++j) cl[j] = P.claim[nb[j]];
+    for (int j = 0; j < kRB; ++j) {
+      if (!(nb[j] != u && cl[j] == pl)) continue;
+      const int4 inf = P.vinfo[nb[j]];
+      const uint64_t kv = pack_key(inf.z, nb[j]);
+      int rank = 0;
+      for (int32_t k1 = a; k1 < b; k1 += kRB) {
+        int32_t w[kRB];
+        load_batch(P.colidx, k1, b, u, w);
+        uint32_t cw[kRB];
+        int32_t dw[kRB];
+#pragma unroll
+        for (int i = 0; i < kRB; ++i) cw[i] = P.claim[w[i]];
+#pragma unroll
+        for (int i = 0; i < kRB; ++i) dw[i] = P.vinfo[w[i]].z;
+#pragma unroll
+        for (int i = 0; i < kRB; ++i)
+          rank += (w[i] != u && cw[i] == pl && pack_key(dw[i], w[i]) < kv) ? 1 : 0;
+      }
+      const int32_t at = base + rank;
+      if (at < end) P.qi[at] = record(nb[j], inf);
+      my_m += inf.z;
+      claim_row(P, nb[j], inf, static_cast<uint32_t>(at));
+    }
+  }
+}
+
+// Count the children of parent p over a long row (batch by batch).
+__device__ __forceinline__ int count_long_row(const BfsParams& P, int32_t p, int32_t u, int32_t a,
+                                              int32_t b) {
+  const uint32_t pl = static_cast<uint32_t>(p);
+  int c = 0;
+  for (int32_t k0 = a; k0 < b; k0 += kRB) {
+    int32_t nb[kRB];
+    load_batch(P.colidx, k0, b, u, nb);
+    uint32_t cl[kRB];
+#pragma unroll
+    for (int j = 0; j < kRB; ++j) cl[j] = P.claim[nb[j]];
+#pragma unroll
+    for (int j = 0; j < kRB; ++j) c += (nb[j] != u && cl[j] == pl) ? 1 : 0;
+  }
+  return c;
 }
 
 // The labelled BFS of Algorithm 3 from `root`; labels are the positions in
-// q[o, o + size).  Returns the number of levels; *msum = sum of degrees.
+// qi[o, end).  Per level: (B) each parent counts its children -- the
+// neighbours whose claim equals its label -- keeping them in registers when
+// its row fits one batch; barrier; (C) a scan of the counts in label order
+// gives every parent its first child label, children are placed by their
+// (degree, id) rank, and each placed child immediately claims its own
+// neighbours for the next level; barrier.  Returns the number of levels;
+// *msum = sum of degrees.
 __device__ int32_t label_pass(const BfsParams& P, Team& t, Shared& S, int32_t o, int32_t end,
                               int32_t root, long long* msum) {
+  const long long clk0 = wall_clock64();
+  const int B = blockDim.x;
+  const int4 rinf = P.vinfo[root];
   if (t.wid == 0 && threadIdx.x == 0) {
-    P.q[o] = root;
+    P.qi[o] = record(root, rinf);
     __hip_atomic_store(&P.claim[root], static_cast<uint32_t>(o), __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_AGENT);
     __hip_atomic_store(&t.ctl->msum, 0ll, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
-  team_barrier(t, &S.flag);
+  // the root's claims, spread over the whole team (its row may be long)
+  for (int32_t k = rinf.x + t.wid * B + threadIdx.x; k < rinf.y; k += t.W * B) {
+    const int32_t v = P.colidx[k];
+    if (v != root) atomicMin(&P.claim[v], static_cast<uint32_t>(o));
+  }
+  team_barrier(t, S, false);
   if (t.aborted) return 0;
-  const int B = blockDim.x;
   int32_t cur_b = o, cur_e = o + 1, levels = 1;
-  long long my_m = (t.wid == 0 && threadIdx.x == 0) ? P.deg[root] : 0;
-  while (true) {
-    int32_t lo, hi;
-    my_chunk(cur_b, cur_e, t.W, t.wid, lo, hi);
-    // A: (select2nd, min) SpMSpV of the frontier, restricted to unlabelled
-    for (int32_t p = lo + threadIdx.x; p < hi; p += B) {
-      const int32_t u = P.q[p];
-      const uint32_t pl = static_cast<uint32_t>(p);
-      for (int32_t k = P.rowptr[u]; k < P.rowptr[u + 1]; ++k) {
-        const int32_t v = P.colidx[k];
-        if (v != u && P.claim[v] > pl) atomicMin(&P.claim[v], pl);
-      }
+  long long my_m = (t.wid == 0 && threadIdx.x == 0) ? rinf.z : 0;
+  bool done = false;
+  while (!done) {
+    const bool narrow = t.W > 1 && (cur_e - cur_b) < P.narrow_cutoff;
+    if (narrow && t.wid != 0) {
+      narrow_wait(t, S);
+      if (t.aborted) return 0;
+      cur_b = S.state[0];
+      cur_e = S.state[1];
+      levels = S.state[2];
+      done = S.state[3] != 0;
+      continue;
     }
-    team_barrier(t, &S.flag);
-    if (t.aborted) return 0;
-    // B: children per parent
-    int wg_total = 0;
-    for (int32_t p = lo + threadIdx.x; p < hi; p += B) {
-      const int32_t u = P.q[p];
-      const uint32_t pl = static_cast<uint32_t>(p);
-      int c = 0;
-      for (int32_t k = P.rowptr[u]; k < P.rowptr[u + 1]; ++k) {
-        const int32_t v = P.colidx[k];
-        c += (v != u && P.claim[v] == pl);
-      }
-      P.tmp[p] = c;
-      wg_total += c;
-    }
-    {
-      const long long tot = block_sum_i64(wg_total, S.red);
-      if (threadIdx.x == 0)
-        st_relaxed(&t.ctl->wg_sum[t.wid], static_cast<int32_t>(tot));
-    }
-    team_barrier(t, &S.flag);
-    if (t.aborted) return 0;
-    if (threadIdx.x < t.W) S.wsum[threadIdx.x] = ld_relaxed(&t.ctl->wg_sum[threadIdx.x]);
-    __syncthreads();
-    int32_t prefix = 0, total = 0;
-    for (int w = 0; w < t.W; ++w) {
-      prefix += w < t.wid ? S.wsum[w] : 0;
-      total += S.wsum[w];
-    }
-    if (total == 0) break;
-    // C: labels = cur_e + (exclusive prefix of counts in label order) +
-    //    rank by (degree, id) among siblings
-    int32_t run = cur_e + prefix;
-    for (int32_t r0 = lo; r0 < hi; r0 += B) {
-      const int32_t p = r0 + threadIdx.x;
-      const int c = p < hi ? P.tmp[p] : 0;
-      int rtot;
-      const int ex = block_excl_scan(c, S.scan, &rtot);
-      if (c > 0) {
-        const int32_t u = P.q[p];
+    const bool solo = narrow || t.W == 1;
+    const int W = solo ? 1 : t.W;
+    const int wid = solo ? 0 : t.wid;
+    while (true) {
+      int32_t lo, hi;
+      my_chunk(cur_b, cur_e, W, wid, lo, hi);
+      const long long ta = wall_clock64();
+      // B: count (and capture) the children of every parent
+      const bool one_round = hi - lo <= B;
+      bool captured = false;
+      int c_mine = 0;
+      int32_t cnb[kRB];
+      int4 cinf[kRB];
+      unsigned cmask = 0;
+      int wg_total = 0;
+      for (int32_t p = lo + threadIdx.x; p < hi; p += B) {
+        const int4 e = P.qi[p];
+        const int32_t u = e.x;
         const uint32_t pl = static_cast<uint32_t>(p);
-        const int32_t a = P.rowptr[u], b = P.rowptr[u + 1];
-        const int32_t base = run + ex;
-        for (int32_t k = a; k < b; ++k) {
-          const int32_t v = P.colidx[k];
-          if (v == u || P.claim[v] != pl) continue;
-          const int32_t dv = P.deg[v];
-          const uint64_t kv = pack_key(dv, v);
-          int rank = 0;
-          for (int32_t k2 = a; k2 < b; ++k2) {
-            const int32_t w = P.colidx[k2];
-            if (w == u || P.claim[w] != pl) continue;
-            rank += pack_key(P.deg[w], w) < kv;
+        int c;
+        if (one_round && e.z - e.y <= kRB) {
+          if (e.z > e.y) {
+            load_batch(P.colidx, e.y, e.z, u, cnb);
+            uint32_t cl[kRB];
+#pragma unroll
+            for (int j = 0; j < kRB; ++j) cl[j] = P.claim[cnb[j]];
+#pragma unroll
+            for (int j = 0; j < kRB; ++j) cinf[j] = P.vinfo[cnb[j]];
+#pragma unroll
+            for (int j = 0; j < kRB; ++j) cmask |= (cnb[j] != u && cl[j] == pl ? 1u : 0u) << j;
           }
-          if (base + rank < end) P.q[base + rank] = v;
-          my_m += dv;
+          captured = true;
+          c = __popc(cmask);
+        } else {
+          c = count_long_row(P, p, u, e.y, e.z);
+          P.tmp[p] = c;
         }
+        c_mine = c;
+        wg_total += c;
       }
-      run += rtot;
+      {
+        const long long tot = block_sum_i64(wg_total, S.red);
+        if (threadIdx.x == 0) st_relaxed(&t.ctl->wg_sum[wid], static_cast<int32_t>(tot));
+      }
+      team_barrier(t, S, solo);
+      if (t.aborted) return 0;
+      const long long tb = wall_clock64();
+      if (threadIdx.x < W) S.wsum[threadIdx.x] = ld_relaxed(&t.ctl->wg_sum[threadIdx.x]);
+      __syncthreads();
+      int32_t prefix = 0, total = 0;
+      for (int w = 0; w < W; ++w) {
+        prefix += w < wid ? S.wsum[w] : 0;
+        total += S.wsum[w];
+      }
+      if (total == 0) {
+        done = true;
+        break;
+      }
+      // C: place the children, then claim for the next level
+      int32_t run = cur_e + prefix;
+      for (int32_t r0 = lo; r0 < hi; r0 += B) {
+        const int32_t p = r0 + threadIdx.x;
+        const int c = p < hi ? (one_round ? c_mine : P.tmp[p]) : 0;
+        int rtot;
+        const int ex = block_excl_scan(c, S.scan, &rtot);
+        if (c > 0) {
+          const int32_t base = run + ex;
+          if (captured) {
+            uint64_t key[kRB];
+#pragma unroll
+            for (int j = 0; j < kRB; ++j)
+              key[j] = (cmask >> j & 1u) ? pack_key(cinf[j].z, cnb[j]) : kMaxKey;
+            for (int j = 0; j < kRB; ++j) {
+              if (!(cmask >> j & 1u)) continue;
+              int rank = 0;
+#pragma unroll
+              for (int i = 0; i < kRB; ++i) rank += key[i] < key[j] ? 1 : 0;
+              const int32_t at = base + rank;
+              if (at < end) P.qi[at] = record(cnb[j], cinf[j]);
+              my_m += cinf[j].z;
+              claim_row(P, cnb[j], cinf[j], static_cast<uint32_t>(at));
+            }
+          } else {
+            const int4 e = P.qi[p];
+            place_long_row(P, p, e.x, e.y, e.z, base, end, my_m);
+          }
+        }
+        run += rtot;
+      }
+      const long long tc = wall_clock64();
+      team_barrier(t, S, solo);
+      if (t.aborted) return 0;
+      if (t.wid == 0 && threadIdx.x == 0 && !solo) {
+        const long long td = wall_clock64();
+        t.ctl->clk[12] += tb - ta;
+        t.ctl->clk[13] += tc - tb;
+        t.ctl->clk[14] += td - tc;
+        t.ctl->clk[15] += 1;
+      }
+      cur_b = cur_e;
+      cur_e += total;
+      ++levels;
+      if (cur_e > end) {
+        if (threadIdx.x == 0) flag_error(t.g, RCM_ERR_NOT_SYMMETRIC);
+        done = true;
+        break;
+      }
+      if (narrow && (cur_e - cur_b) >= P.narrow_cutoff) break;
+      if (!narrow && t.W > 1 && (cur_e - cur_b) < P.narrow_cutoff) break;
     }
-    team_barrier(t, &S.flag);
-    if (t.aborted) return 0;
-    cur_b = cur_e;
-    cur_e += total;
-    ++levels;
-    if (cur_e > end) {
-      if (threadIdx.x == 0 && t.wid == 0) flag_error(t.g, RCM_ERR_NOT_SYMMETRIC);
-      t.aborted = true;
-      return 0;
+    if (narrow) {
+      const int32_t st[8] = {cur_b, cur_e, levels, done ? 1 : 0, 0, 0, 0, 0};
+      narrow_publish(t, st);
     }
   }
   if (cur_e != end) {
@@ -313,19 +585,23 @@ __device__ int32_t label_pass(const BfsParams& P, Team& t, Shared& S, int32_t o,
   const long long tot_m = block_sum_i64(my_m, S.red);
   if (threadIdx.x == 0 && tot_m != 0)
     __hip_atomic_fetch_add(&t.ctl->msum, tot_m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  team_barrier(t, &S.flag);
+  team_barrier(t, S, false);
   *msum = __hip_atomic_load(&t.ctl->msum, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (t.wid == 0 && threadIdx.x == 0) {
+    t.ctl->clk[1] += wall_clock64() - clk0;
+    t.ctl->clk[3] += levels;
+  }
   // msum is reset by the next component's setup, after several barriers
   return levels;
 }
 
 __device__ void order_component(const BfsParams& P, Team& t, Shared& S, const CompTask& task) {
   const int32_t o = task.offset;
+  const int32_t end = o + task.size;
   // Algorithm 2: start at the component's lowest id
   int32_t ecc = 0;
   uint64_t lastkey = 0;
   int32_t nbfs = 1;
-  const int32_t end = o + task.size;
   bfs_pass(P, t, S, o, end, task.seed, 1, 0, ecc, lastkey);
   if (t.aborted) return;
   int32_t r = task.seed;
@@ -352,14 +628,14 @@ __device__ void order_component(const BfsParams& P, Team& t, Shared& S, const Co
   // reversal: Cuthill-McKee label t of this component goes to anchor - t
   const int32_t nthreads = t.W * blockDim.x;
   for (int32_t i = t.wid * blockDim.x + threadIdx.x; i < task.size; i += nthreads) {
-    const int32_t v = P.q[o + i];
+    const int32_t v = P.qi[o + i].x;
     const int32_t pos = task.anchor - i;
     P.perm[pos] = v;
     if (v >= 0 && v < P.n) P.iperm[v] = pos;
   }
 }
 
-__global__ void __launch_bounds__(1024) k_order(BfsParams P) {
+__global__ void __launch_bounds__(512) k_order(BfsParams P) {
   __shared__ Shared S;
   Team t;
   t.W = P.team_size;
@@ -369,6 +645,7 @@ __global__ void __launch_bounds__(1024) k_order(BfsParams P) {
   t.ctl = P.teams + team;
   t.g = P.gctl;
   t.nbar = 0;
+  t.woke = 0;
   t.aborted = false;
   for (int iter = 0;; ++iter) {
     int ti;

@@ -51,7 +51,10 @@ struct alignas(128) TeamCtl {
   int32_t pad4[24];
   int32_t wg_sum[kMaxTeam];      // per-WG counts of the current level
   long long msum;                // sum of degrees of the current component
-  long long pad5[15];
+  long long clk[16];             // work-group 0's clock (diagnostics): [0] pp ticks,
+                                 // [1] labelled ticks, [2] pp levels, [3] labelled
+                                 // levels, [4..15] per-phase ticks
+
 };
 
 // Global control shared by all teams of one launch.
@@ -202,7 +205,7 @@ struct Graph {
   const int32_t* seg_off; // device int32[nseg+1] vertex offsets of segments
 };
 
-hipError_t launch_validate_scan(const Graph& g, int32_t* deg, int32_t* beta, SegStats* seg,
+hipError_t launch_validate_scan(const Graph& g, int4* vinfo, int32_t* beta, SegStats* seg,
                                 int32_t* err, hipStream_t s);
 hipError_t launch_full_check(const Graph& g, int32_t* err_dup, int32_t* err_sym, hipStream_t s);
 hipError_t launch_components(const Graph& g, int32_t* parent, int32_t* csize, int32_t* flags,
@@ -213,8 +216,8 @@ hipError_t launch_tasks(const Graph& g, int32_t ncomp, const int32_t* seeds, con
                         CompTask* tasks_small, CompTask* tasks_big, int32_t* counts,
                         int32_t* sizes, int32_t* offs, int32_t* scan_blk, CompResult* results,
                         hipStream_t s);
-hipError_t launch_singletons(const CompTask* tasks, int32_t count, int32_t* q, int32_t* perm,
-                             int32_t* iperm, CompResult* results, hipStream_t s);
+hipError_t launch_singletons(const CompTask* tasks, int32_t count, int32_t* perm, int32_t* iperm,
+                             CompResult* results, hipStream_t s);
 hipError_t launch_bw_after(const Graph& g, const int32_t* perm, const int32_t* iperm,
                            int32_t* beta, SegStats* seg, hipStream_t s);
 hipError_t launch_comp_stats(const Graph& g, int32_t ncomp, const int32_t* seeds,
@@ -226,10 +229,10 @@ hipError_t launch_exclusive_scan(const int32_t* in, int32_t* out, int32_t count,
 struct BfsParams {
   const int32_t* rowptr;
   const int32_t* colidx;
-  const int32_t* deg;
+  const int4* vinfo;  // per vertex: row begin, row end, degree, 0
   int32_t* visit;
   uint32_t* claim;
-  int32_t* q;
+  int4* qi;           // per position: vertex, row begin, row end, degree
   int32_t* tmp;
   int32_t* perm;
   int32_t* iperm;

@@ -29,14 +29,16 @@ inline int grid_for(int64_t work, int threads, int max_blocks = 8192) {
 // ---------------------------------------------------------------------------
 // Row checks + degree + beta of the input order.
 // ---------------------------------------------------------------------------
+// vinfo[i] = (row begin, row end, degree, 0): one 16-byte record per vertex,
+// read by the traversal in a single load.
 __global__ void k_validate_scan(int32_t n, int32_t nnz, const int32_t* __restrict__ rowptr,
-                                const int32_t* __restrict__ colidx, int32_t* __restrict__ deg,
+                                const int32_t* __restrict__ colidx, int4* __restrict__ vinfo,
                                 int32_t* __restrict__ beta, int32_t* __restrict__ err) {
   for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     const int32_t a = rowptr[i];
     const int32_t b = rowptr[i + 1];
     if (a < 0 || b < a || b > nnz) {
-      deg[i] = 0;
+      vinfo[i] = make_int4(0, 0, 0, 0);
       beta[i] = 0;
       atomicOr(err, 1);
       continue;
@@ -51,7 +53,7 @@ __global__ void k_validate_scan(int32_t n, int32_t nnz, const int32_t* __restric
       mn = c < mn ? c : mn;
     }
     if (bad) atomicOr(err, 1);
-    deg[i] = d;
+    vinfo[i] = make_int4(a, b, d, 0);
     beta[i] = i - mn;
   }
 }
@@ -319,11 +321,10 @@ __global__ void k_build_tasks(int32_t ncomp, const int32_t* __restrict__ seeds,
 }
 
 __global__ void k_singletons(const CompTask* __restrict__ tasks, int32_t count,
-                             int32_t* __restrict__ q, int32_t* __restrict__ perm,
-                             int32_t* __restrict__ iperm, CompResult* __restrict__ results) {
+                             int32_t* __restrict__ perm, int32_t* __restrict__ iperm,
+                             CompResult* __restrict__ results) {
   for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
     const CompTask t = tasks[i];
-    q[t.offset] = t.seed;
     perm[t.anchor] = t.seed;
     iperm[t.seed] = t.anchor;
     // an isolated vertex: Algorithm 2 computes two one-level structures
@@ -417,10 +418,10 @@ hipError_t launch_exclusive_scan(const int32_t* in, int32_t* out, int32_t count,
   return hipGetLastError();
 }
 
-hipError_t launch_validate_scan(const Graph& g, int32_t* deg, int32_t* beta, SegStats* seg,
+hipError_t launch_validate_scan(const Graph& g, int4* vinfo, int32_t* beta, SegStats* seg,
                                 int32_t* err, hipStream_t s) {
   k_validate_scan<<<grid_for(g.n, kThreads), kThreads, 0, s>>>(g.n, g.nnz, g.rowptr, g.colidx,
-                                                                deg, beta, err);
+                                                                vinfo, beta, err);
   if (g.nseg > 1)
     k_check_segments<<<grid_for(g.n, kThreads), kThreads, 0, s>>>(g.n, g.rowptr, g.colidx,
                                                                    g.seg_off, g.nseg, err);
@@ -473,11 +474,10 @@ hipError_t launch_tasks(const Graph& g, int32_t ncomp, const int32_t* seeds, con
   return hipGetLastError();
 }
 
-hipError_t launch_singletons(const CompTask* tasks, int32_t count, int32_t* q, int32_t* perm,
-                             int32_t* iperm, CompResult* results, hipStream_t s) {
+hipError_t launch_singletons(const CompTask* tasks, int32_t count, int32_t* perm, int32_t* iperm,
+                             CompResult* results, hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  k_singletons<<<grid_for(count, kThreads), kThreads, 0, s>>>(tasks, count, q, perm, iperm,
-                                                              results);
+  k_singletons<<<grid_for(count, kThreads), kThreads, 0, s>>>(tasks, count, perm, iperm, results);
   return hipGetLastError();
 }
 

@@ -85,6 +85,11 @@ class Timings(ctypes.Structure):
         ("total_ms", ctypes.c_float),
         ("small_kernel_ms", ctypes.c_float),
         ("team_kernel_ms", ctypes.c_float),
+        ("team_pp_ms", ctypes.c_float),
+        ("team_label_ms", ctypes.c_float),
+        ("team_pp_levels", ctypes.c_int32),
+        ("team_label_levels", ctypes.c_int32),
+        ("phase_ticks", ctypes.c_int64 * 12),
     ]
 
 
@@ -153,7 +158,9 @@ def batched_workspace_bytes(num_graphs: int, total_vertices: int, total_nnz: int
 def last_timings() -> Dict[str, float]:
     t = Timings()
     lib().rcm_last_timings(ctypes.byref(t))
-    return {f: float(getattr(t, f)) for f, _ in t._fields_}
+    out = {f: getattr(t, f) for f, _ in t._fields_}
+    out["phase_ticks"] = list(t.phase_ticks)
+    return out
 
 
 def _stream_handle(stream) -> Optional[int]:

@@ -97,11 +97,13 @@ def test_random_graphs_small_path(seed):
 
 
 @pytest.mark.parametrize("seed", range(12))
-@pytest.mark.parametrize("team", [1, 2, 8])
-def test_random_graphs_team_path(seed, team):
-    """small_cutoff=1 sends every non-isolated component to the team path."""
+@pytest.mark.parametrize("team,narrow", [(1, 0), (2, -1), (8, -1), (8, 16), (4, 4096)])
+def test_random_graphs_team_path(seed, team, narrow):
+    """small_cutoff=1 sends every non-isolated component to the team path;
+    narrow_cutoff moves levels between the whole team and its first
+    work-group."""
     g = _random_graph(100 + seed)
-    check(g, small_cutoff=1, team_size=team, block_threads=256)
+    check(g, small_cutoff=1, team_size=team, block_threads=256, narrow_cutoff=narrow)
 
 
 @pytest.mark.parametrize("seed", [1, 2, 3, 4, 5])
@@ -112,10 +114,11 @@ def test_grid_64x64(seed):
     check(g, small_cutoff=1)
 
 
-@pytest.mark.parametrize("team,threads", [(8, 1024), (4, 512), (16, 256)])
-def test_grid_128_cubed(team, threads):
+@pytest.mark.parametrize("team,threads,narrow", [(32, 512, 0), (4, 512, -1), (16, 256, 1024),
+                                                 (8, 512, 100000)])
+def test_grid_128_cubed(team, threads, narrow):
     g = I.config(1)
-    check(g, team_size=team, block_threads=threads)
+    check(g, team_size=team, block_threads=threads, narrow_cutoff=narrow)
 
 
 def test_strip_32x500000():
