@@ -167,11 +167,13 @@ typedef struct {
   float team_label_ms;   /* device clock of that launch: labelled BFS */
   int32_t team_pp_levels;    /* levels expanded by the pseudo-peripheral passes */
   int32_t team_label_levels; /* levels of the labelled BFS */
-  int64_t phase_ticks[12];   /* diagnostics, 100 MHz device clock of work-group 0:
-                                [0..3] wide unlabelled levels: expand, append,
-                                barrier, count; [4..7] the same for narrow
-                                levels; [8..11] wide labelled levels: claim +
-                                barrier, count + barrier, place + barrier, count */
+  int64_t phase_ticks[12];   /* diagnostics, 100 MHz device clock of work-group 0
+                                of the team launch: [0..3] wide unlabelled levels
+                                (expand, append, barrier ticks; level count);
+                                [4, 5] unlabelled levels of the LDS engine (ticks,
+                                count); [6, 7] one-work-group global unlabelled
+                                levels; [8, 9] wide labelled levels; [10, 11]
+                                labelled levels of the LDS engine               */
 } rcm_timings;
 void rcm_last_timings(rcm_timings* out);
 

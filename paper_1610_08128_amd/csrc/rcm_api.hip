@@ -16,6 +16,7 @@
 #include <algorithm>
 #include <cstdlib>
 #include <cstring>
+#include <cstdio>
 #include <vector>
 
 #include "rcm_common.hpp"
@@ -118,14 +119,17 @@ Layout make_layout(int64_t n, int64_t nnz, int64_t nseg, bool batched, int teams
 
 constexpr int kSmallTeams = 1024;
 
+// Phase timing with HIP events on the call's stream (RCM_TIMING=1).
+// Event slots: 0 start, 1 checks done, 2/3 around the component search,
+// 4 ordering done, 5 statistics done; kernel slots around the launches.
 struct Timer {
   bool on;
   hipStream_t s;
   hipEvent_t ev[6];
-  hipEvent_t kev[4];  // around the small-component and the team launches
+  bool used[6] = {false, false, false, false, false, false};
+  hipEvent_t kev[4];
   bool kused[2] = {false, false};
   long long clk[16] = {};
-  int k = 0;
   explicit Timer(hipStream_t st) : s(st) {
     const char* e = std::getenv("RCM_TIMING");
     on = e && e[0] == '1';
@@ -134,25 +138,33 @@ struct Timer {
       for (auto& x : kev) (void)hipEventCreate(&x);
     }
   }
+  void mark(int slot) {
+    if (!on) return;
+    (void)hipEventRecord(ev[slot], s);
+    used[slot] = true;
+  }
   void kmark(int which, bool start) {
     if (!on) return;
     (void)hipEventRecord(kev[2 * which + (start ? 0 : 1)], s);
     kused[which] = true;
   }
-  void mark() {
-    if (on && k < 6) (void)hipEventRecord(ev[k++], s);
+  float span(int a, int b) {
+    float ms = 0.f;
+    if (used[a] && used[b]) (void)hipEventElapsedTime(&ms, ev[a], ev[b]);
+    return ms;
   }
   void finish() {
     rcm_timings t{};
-    if (on && k >= 2) {
-      (void)hipEventSynchronize(ev[k - 1]);
-      float ms[5] = {0, 0, 0, 0, 0};
-      for (int i = 0; i + 1 < k && i < 4; ++i) (void)hipEventElapsedTime(&ms[i], ev[i], ev[i + 1]);
-      t.validate_ms = ms[0];
-      t.components_ms = ms[1];
-      t.order_ms = ms[2];
-      t.after_ms = ms[3];
-      (void)hipEventElapsedTime(&t.total_ms, ev[0], ev[k - 1]);
+    if (on && used[0]) {
+      int last = 0;
+      for (int i = 0; i < 6; ++i)
+        if (used[i]) last = i;
+      (void)hipEventSynchronize(ev[last]);
+      t.validate_ms = span(0, 1);
+      t.components_ms = span(2, 3);
+      t.order_ms = span(1, 4);
+      t.after_ms = span(4, 5);
+      t.total_ms = span(0, last);
       if (kused[0]) (void)hipEventElapsedTime(&t.small_kernel_ms, kev[0], kev[1]);
       if (kused[1]) (void)hipEventElapsedTime(&t.team_kernel_ms, kev[2], kev[3]);
       t.team_pp_ms = static_cast<float>(clk[0] * 1e-5);
@@ -176,6 +188,19 @@ struct Timer {
     hipError_t _he = (expr);               \
     if (_he != hipSuccess) return RCM_ERR_HIP; \
   } while (0)
+
+// With RCM_DEBUG=1 the library reports on stderr where a device-side check
+// failed (site, component, pass, level, frontier bounds, block end).
+void report_device_error(const GlobalCtl* gctl, hipStream_t s) {
+  const char* e = std::getenv("RCM_DEBUG");
+  if (!(e && e[0] == '1')) return;
+  int32_t d[9] = {};
+  if (hipMemcpyAsync(d, &gctl->error, sizeof(d), hipMemcpyDeviceToHost, s) != hipSuccess) return;
+  if (hipStreamSynchronize(s) != hipSuccess) return;
+  std::fprintf(stderr,
+               "rcm: device error %d at site %d component %d pass %d level %d frontier [%d, %d) "
+               "block end %d\n", d[0], d[1], d[2], d[3], d[4], d[5], d[6], d[7]);
+}
 
 // Read a few device ints synchronously.
 rcm_status read_ints(int32_t* host, const int32_t* dev, int count, hipStream_t s) {
@@ -223,7 +248,7 @@ rcm_status run(const Graph& gin, const int32_t* seg_off_host, const Opts& opt, c
   HIP_TRY(hipMemsetAsync(misc, 0, 256, s));
   HIP_TRY(hipMemsetAsync(segstats, 0, sizeof(SegStats) * g.nseg, s));
 
-  timer.mark();
+  timer.mark(0);
   // 2. checks, degrees, input bandwidth/profile
   HIP_TRY(launch_validate_scan(g, vinfo, beta, segstats, misc + 0, s));
   int32_t h[4];
@@ -238,23 +263,11 @@ rcm_status run(const Graph& gin, const int32_t* seg_off_host, const Opts& opt, c
     if (h[1]) return RCM_ERR_BAD_CSR;
     if (h[2]) return RCM_ERR_NOT_SYMMETRIC;
   }
-  timer.mark();
-  // 4. components and tasks
-  HIP_TRY(launch_components(g, parent, csize, flags, pos, seeds, misc + 4, s));
-  st = read_ints(h, misc + 4, 1, s);
-  if (st != RCM_OK) return st;
-  const int32_t ncomp = h[0];
-  HIP_TRY(launch_tasks(g, ncomp, seeds, csize, opt.small_cutoff, opt.reverse_mode, t_single,
-                       t_small, t_big, misc + 8, sizes, offs, scan_blk, results, s));
-  st = read_ints(h, misc + 8, 3, s);
-  if (st != RCM_OK) return st;
-  const int32_t n_single = h[0], n_small = h[1], n_big = h[2];
-  timer.mark();
-  // 5. ordering
+  timer.mark(1);
+  // 4-5. components and ordering
   HIP_TRY(hipMemsetAsync(visit, 0, 4 * N, s));
   HIP_TRY(hipMemsetAsync(claim, 0xFF, 4 * N, s));
   HIP_TRY(hipMemsetAsync(gctl, 0, sizeof(GlobalCtl), s));
-  HIP_TRY(launch_singletons(t_single, n_single, perm_out, iperm, results, s));
   BfsParams P;
   P.rowptr = g.rowptr;
   P.colidx = g.colidx;
@@ -271,37 +284,99 @@ rcm_status run(const Graph& gin, const int32_t* seg_off_host, const Opts& opt, c
   P.pp_variant = opt.pp_variant;
   P.reverse_mode = opt.reverse_mode;
   P.narrow_cutoff = opt.narrow_cutoff;
-  if (n_small > 0) {
-    P.tasks = t_small;
-    P.ntasks = n_small;
-    P.teams = small_ctl;
-    P.team_size = 1;
-    const int nb = std::min(n_small, kSmallTeams);
-    HIP_TRY(hipMemsetAsync(small_ctl, 0, sizeof(TeamCtl) * nb, s));
-    timer.kmark(0, true);
-    HIP_TRY(launch_order_small(P, nb, opt.small_threads, s));
-    timer.kmark(0, false);
-  }
-  if (n_big > 0) {
-    P.tasks = t_big;
-    P.ntasks = n_big;
+  auto run_team = [&](const CompTask* tasks, int32_t count, bool timed) -> rcm_status {
+    P.tasks = tasks;
+    P.ntasks = count;
     P.teams = teams;
     P.team_size = opt.team_size;
     HIP_TRY(hipMemsetAsync(teams, 0, sizeof(TeamCtl), s));
-    timer.kmark(1, true);
+    if (timed) timer.kmark(1, true);
     HIP_TRY(launch_order_big(P, opt.threads, s));
-    timer.kmark(1, false);
-    if (timer.on) {
+    if (timed) timer.kmark(1, false);
+    if (timed && timer.on) {
       HIP_TRY(hipMemcpyAsync(timer.clk, teams[0].clk, sizeof(timer.clk), hipMemcpyDeviceToHost,
                              s));
       HIP_TRY(hipStreamSynchronize(s));
     }
+    return RCM_OK;
+  };
+  // The component of vertex 0 has the lowest seed of all, so its label block
+  // starts at 0 whatever the other components are: it is ordered first by
+  // the team, its size found by its first level structure, and the
+  // component search below only has to cover the vertices it did not reach.
+  // (Single graphs only; a batch runs the search over every graph.)
+  const bool head = g.nseg == 1;
+  int32_t head_size = 0;
+  if (head) {
+    const CompTask ht{0, -1, 0, 0, opt.reverse_mode == 1 ? g.n - 1 : -1};
+    const CompResult hr{0, 0, 0, 0, 0, 0, 0};
+    HIP_TRY(hipMemcpyAsync(t_big, &ht, sizeof(ht), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(results, &hr, sizeof(hr), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemsetAsync(seeds, 0, sizeof(int32_t), s));
+    st = run_team(t_big, 1, true);
+    if (st != RCM_OK) return st;
+    int32_t hres[8];
+    HIP_TRY(hipMemcpyAsync(hres, results, sizeof(CompResult), hipMemcpyDeviceToHost, s));
+    st = read_ints(h, &gctl->error, 1, s);
+    if (st != RCM_OK) return st;
+    if (h[0]) report_device_error(gctl, s);
+    if (h[0] == RCM_ERR_NOT_SYMMETRIC) return RCM_ERR_NOT_SYMMETRIC;
+    if (h[0]) return RCM_ERR_ABORTED;
+    head_size = hres[4];
+    if (head_size < 1 || head_size > g.n) return RCM_ERR_HIP;
   }
+  int32_t ncomp = head ? 1 : 0;
+  if (head_size < g.n) {
+    int32_t* seeds_rest = head ? seeds + 1 : seeds;
+    timer.mark(2);
+    HIP_TRY(launch_components(g, head ? visit : nullptr, parent, csize, flags, pos, seeds_rest,
+                              misc + 4, misc + 5, s));
+    st = read_ints(h, misc + 4, 2, s);
+    if (st != RCM_OK) return st;
+    if (h[1]) {
+      if (std::getenv("RCM_DEBUG")) std::fprintf(stderr, "rcm: edge into the ordered head\n");
+      return RCM_ERR_NOT_SYMMETRIC;
+    }
+    const int32_t nrest = h[0];
+    ncomp += nrest;
+    HIP_TRY(launch_tasks(g, nrest, seeds_rest, csize, opt.small_cutoff, opt.reverse_mode,
+                         head_size, head ? 1 : 0, t_single, t_small, t_big, misc + 8, sizes, offs,
+                         scan_blk, results, s));
+    st = read_ints(h, misc + 8, 4, s);
+    if (st != RCM_OK) return st;
+    // every vertex must belong to exactly one component (only an asymmetric
+    // pattern can break this)
+    if (head_size + h[3] != g.n) {
+      if (std::getenv("RCM_DEBUG"))
+        std::fprintf(stderr, "rcm: components cover %d + %d of %d vertices\n", head_size, h[3],
+                     g.n);
+      return RCM_ERR_NOT_SYMMETRIC;
+    }
+    timer.mark(3);
+    const int32_t n_single = h[0], n_small = h[1], n_big = h[2];
+    HIP_TRY(launch_singletons(t_single, n_single, perm_out, iperm, results, s));
+    if (n_small > 0) {
+      P.tasks = t_small;
+      P.ntasks = n_small;
+      P.teams = small_ctl;
+      P.team_size = 1;
+      const int nb = std::min(n_small, kSmallTeams);
+      HIP_TRY(hipMemsetAsync(small_ctl, 0, sizeof(TeamCtl) * nb, s));
+      timer.kmark(0, true);
+      HIP_TRY(launch_order_small(P, nb, opt.small_threads, s));
+      timer.kmark(0, false);
+    }
+    if (n_big > 0) {
+      st = run_team(t_big, n_big, !head);
+      if (st != RCM_OK) return st;
+    }
+  }
+  timer.mark(4);
   st = read_ints(h, &gctl->error, 1, s);
   if (st != RCM_OK) return st;
+  if (h[0]) report_device_error(gctl, s);
   if (h[0] == RCM_ERR_NOT_SYMMETRIC) return RCM_ERR_NOT_SYMMETRIC;
   if (h[0]) return RCM_ERR_ABORTED;
-  timer.mark();
   // 6. result statistics
   HIP_TRY(launch_bw_after(g, perm_out, iperm, beta, segstats, s));
   HIP_TRY(launch_comp_stats(g, ncomp, seeds, results, comp_seg_off, segstats, s));
@@ -325,7 +400,7 @@ rcm_status run(const Graph& gin, const int32_t* seg_off_host, const Opts& opt, c
   } else {
     HIP_TRY(hipStreamSynchronize(s));
   }
-  timer.mark();
+  timer.mark(5);
   return RCM_OK;
 }
 

@@ -52,13 +52,35 @@ struct Team {
   GlobalCtl* g;
   int W;
   int wid;
+  int comp;                 // index of the component being ordered (diagnostics)
   unsigned long long nbar;  // barrier arrivals expected so far (thread 0 only)
   unsigned long long woke;  // narrow episodes seen (thread 0 only)
   bool aborted;
 };
 
+// LDS state of the single-work-group level engine (narrow levels).
+constexpr int kNarrowCap = 1024;        // frontier records held in LDS
+constexpr int kHashBits = 11;
+constexpr int kHash = 1 << kHashBits;   // slots per next-level table
+constexpr int32_t kEmpty = -1;
+
+struct NarrowLds {
+  int32_t lev[2][kNarrowCap][4];   // frontier records (vertex, row begin, row end, degree)
+  int32_t key[2][kHash];           // next-level tables: vertex ...
+  uint32_t val[2][kHash];          // ... and its smallest claiming label
+  int32_t cnt[3];                  // size of the level being discovered (mod 3)
+  int32_t rows[3];                 // its total row length (mod 3)
+  int32_t maxrow[3];               // its longest row (mod 3)
+  unsigned long long kmin[3];      // its minimum (degree << 32 | id) (mod 3)
+};
+
+union SharedBuf {
+  int32_t srec[kStageCap][4];      // append stage of the team levels
+  NarrowLds nw;
+};
+
 struct Shared {
-  int4 srec[kStageCap];
+  SharedBuf u;
   int scan[17];
   long long red[16];
   int32_t cnt;
@@ -73,11 +95,16 @@ struct Shared {
 // Record the first error of the launch (RCM_ERR_ABORTED for a wait that timed
 // out, RCM_ERR_NOT_SYMMETRIC when a traversal leaves its component's block,
 // which only an asymmetric pattern can cause).
-__device__ __forceinline__ void flag_error(GlobalCtl* g, int code) {
+__device__ __forceinline__ void flag_error(GlobalCtl* g, int code, int site = 0, int comp = 0,
+                                           int pass = 0, int level = 0, int cur_b = 0,
+                                           int cur_e = 0, int end = 0) {
   int32_t expected = 0;
-  __hip_atomic_compare_exchange_strong(&g->error, &expected, static_cast<int32_t>(code),
-                                       __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
+  if (__hip_atomic_compare_exchange_strong(&g->error, &expected, static_cast<int32_t>(code),
+                                           __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT)) {
+    const int32_t d[7] = {site, comp, pass, level, cur_b, cur_e, end};
+    for (int i = 0; i < 7; ++i) st_relaxed(&g->diag[i], d[i]);
+  }
 }
 
 // Wait (thread 0) until *ctr >= target, giving up after the wall-clock limit
@@ -120,10 +147,14 @@ __device__ __forceinline__ void team_barrier(Team& t, Shared& S, bool solo) {
 
 // Narrow mode hand-over.  Work-group 0 publishes the pass state and wakes
 // the others; they read it back.
-__device__ __forceinline__ void narrow_publish(Team& t, const int32_t* st) {
+__device__ __forceinline__ void narrow_publish(Team& t, int32_t cur_b, int32_t cur_e,
+                                               int32_t level, bool done) {
   __syncthreads();
   if (threadIdx.x == 0) {
-    for (int i = 0; i < 8; ++i) st_relaxed(&t.ctl->narrow_state[i], st[i]);
+    st_relaxed(&t.ctl->narrow_state[0], cur_b);
+    st_relaxed(&t.ctl->narrow_state[1], cur_e);
+    st_relaxed(&t.ctl->narrow_state[2], level);
+    st_relaxed(&t.ctl->narrow_state[3], done ? 1 : 0);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __hip_atomic_fetch_add(&t.ctl->wake, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
@@ -135,7 +166,8 @@ __device__ __forceinline__ void narrow_wait(Team& t, Shared& S) {
     t.woke += 1;
     const bool ok = wait_at_least(t, &t.ctl->wake, t.woke, true);
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    for (int i = 0; i < 8; ++i) S.state[i] = ld_relaxed(&t.ctl->narrow_state[i]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) S.state[i] = ld_relaxed(&t.ctl->narrow_state[i]);
     S.flag = ok ? 0 : 1;
   }
   __syncthreads();
@@ -212,7 +244,7 @@ __device__ __forceinline__ void bfs_expand(const BfsParams& P, Shared& S, int32_
         if (!(mask >> j & 1u)) continue;
         const int4 r = record(nb[j], inf[j]);
         if (idx < kStageCap) {
-          S.srec[idx] = r;
+          reinterpret_cast<int4*>(S.u.srec)[idx] = r;
         } else {
           const int32_t at = atomicAdd(tail_slot, 1);
           if (cur_e + at < end) P.qi[cur_e + at] = r;
@@ -223,13 +255,240 @@ __device__ __forceinline__ void bfs_expand(const BfsParams& P, Shared& S, int32_
   }
 }
 
+__device__ __forceinline__ uint32_t hslot(int32_t v) {
+  return (static_cast<uint32_t>(v) * 2654435761u) >> (32 - kHashBits);
+}
+
+// Insert v into an LDS table (open addressing); returns its slot and sets
+// *fresh when this call inserted it.  The engine keeps every table at most
+// half full, so a free slot is always found.
+__device__ __forceinline__ int h_insert(int32_t* key, int32_t v, bool* fresh) {
+  uint32_t h = hslot(v);
+  for (int i = 0; i < kHash; ++i) {
+    int32_t k = key[h];
+    if (k == kEmpty) {
+      k = atomicCAS(&key[h], kEmpty, v);
+      if (k == kEmpty) {
+        *fresh = true;
+        return static_cast<int>(h);
+      }
+    }
+    if (k == v) {
+      *fresh = false;
+      return static_cast<int>(h);
+    }
+    h = (h + 1) & (kHash - 1);
+  }
+  *fresh = false;
+  return -1;
+}
+
+__device__ __forceinline__ int4 lds_rec(const NarrowLds& N, int buf, int i) {
+  return make_int4(N.lev[buf][i][0], N.lev[buf][i][1], N.lev[buf][i][2], N.lev[buf][i][3]);
+}
+__device__ __forceinline__ void lds_put(NarrowLds& N, int buf, int i, int4 r) {
+  N.lev[buf][i][0] = r.x;
+  N.lev[buf][i][1] = r.y;
+  N.lev[buf][i][2] = r.z;
+  N.lev[buf][i][3] = r.w;
+}
+
+// Unlabelled levels in one work-group with the frontier in LDS.  A neighbour
+// is new when its visited stamp is older than this pass and this work-group
+// is the first to insert it into the next level's LDS table (no global
+// atomics).  Runs from the frontier qi[cur_b, cur_e) at `level` until the
+// pass ends, the next level no longer fits (more than kNarrowCap vertices or
+// more than kHash / 2 row entries), or it reaches stop_width vertices.
+// Returns false, having done nothing, when the current frontier does not fit.
+// On return the global key / tail slots are as the team levels expect them.
+__device__ __forceinline__ bool lds_bfs_levels(const BfsParams& P, Team& t, Shared& S, int32_t end, int32_t epoch,
+                               int32_t* tail, unsigned long long* minkey, int32_t& cur_b,
+                               int32_t& cur_e, int32_t& level, bool& done, int32_t stop_width) {
+  NarrowLds& N = S.u.nw;
+  const int B = blockDim.x;
+  int32_t len = cur_e - cur_b;
+  if (len > kNarrowCap) return false;
+  const long long c0 = wall_clock64();
+  long long rs = 0;
+  for (int32_t i = threadIdx.x; i < len; i += B) {
+    const int4 r = P.qi[cur_b + i];
+    lds_put(N, level & 1, i, r);
+    rs += r.z - r.y;
+  }
+  rs = block_sum_i64(rs, S.red);
+  if (rs > kHash / 2) return false;
+  for (int i = threadIdx.x; i < 2 * kHash; i += B) (&N.key[0][0])[i] = kEmpty;
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < 3; ++i) {
+      N.cnt[i] = 0;
+      N.rows[i] = 0;
+      N.kmin[i] = kMaxKey;
+    }
+    N.kmin[level % 3] = ld_relaxed(minkey + level % 3);
+  }
+  __syncthreads();
+  int32_t nlev = 0;
+  while (true) {
+    const int nx = (level + 1) % 3;
+    int32_t* key_ins = N.key[(level + 1) & 1];
+    int32_t* key_clr = N.key[level & 1];
+    for (int i = threadIdx.x; i < kHash; i += B) key_clr[i] = kEmpty;  // used again at level + 2
+    if (threadIdx.x == 0) {
+      N.cnt[(level + 2) % 3] = 0;
+      N.rows[(level + 2) % 3] = 0;
+      N.kmin[(level + 2) % 3] = kMaxKey;
+    }
+    uint64_t mykey = kMaxKey;
+    for (int32_t i = threadIdx.x; i < len; i += B) {
+      const int4 e = lds_rec(N, level & 1, i);
+      const int32_t u = e.x;
+      for (int32_t k0 = e.y; k0 < e.z; k0 += kRB) {
+        int32_t nb[kRB];
+        load_batch(P.colidx, k0, e.z, u, nb);
+        int32_t vs[kRB];
+        int4 inf[kRB];
+#pragma unroll
+        for (int j = 0; j < kRB; ++j) vs[j] = P.visit[nb[j]];
+#pragma unroll
+        for (int j = 0; j < kRB; ++j) inf[j] = P.vinfo[nb[j]];
+#pragma unroll
+        for (int j = 0; j < kRB; ++j) {
+          if (nb[j] == u || vs[j] == epoch) continue;
+          bool fresh = false;
+          if (h_insert(key_ins, nb[j], &fresh) < 0) continue;  // cannot happen (half full)
+          if (!fresh) continue;
+          const int32_t idx = atomicAdd(&N.cnt[nx], 1);
+          atomicAdd(&N.rows[nx], inf[j].y - inf[j].x);
+          const int4 r = record(nb[j], inf[j]);
+          if (cur_e + idx < end) P.qi[cur_e + idx] = r;
+          if (idx < kNarrowCap) lds_put(N, (level + 1) & 1, idx, r);
+          P.visit[nb[j]] = epoch;
+          const uint64_t kv = pack_key(inf[j].z, nb[j]);
+          mykey = kv < mykey ? kv : mykey;
+        }
+      }
+    }
+    mykey = wave_min_u64(mykey);
+    if ((threadIdx.x & 63) == 0 && mykey != kMaxKey) atomicMin(&N.kmin[nx], mykey);
+    __syncthreads();
+    const int32_t cnt = N.cnt[nx];
+    const int32_t rows = N.rows[nx];
+    ++nlev;
+    if (cnt == 0) {
+      done = true;
+      break;
+    }
+    cur_b = cur_e;
+    cur_e += cnt;
+    ++level;
+    len = cnt;
+    if (cur_e > end) {
+      if (threadIdx.x == 0)
+        flag_error(t.g, RCM_ERR_NOT_SYMMETRIC, 6, t.comp, epoch, level, cur_b, cur_e, end);
+      done = true;
+      break;
+    }
+    if (cnt > kNarrowCap || rows > kHash / 2 || cnt >= stop_width) break;
+  }
+  if (threadIdx.x == 0) {
+    // as the team levels leave them: the frontier's minimum key, an empty
+    // slot for the next level, a zero append counter
+    __hip_atomic_store(minkey + level % 3, N.kmin[level % 3], __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(minkey + (level + 1) % 3, kMaxKey, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+    st_relaxed(tail + level % 3, 0);
+    st_relaxed(tail + (level + 1) % 3, 0);
+    t.ctl->clk[8] += wall_clock64() - c0;
+    t.ctl->clk[9] += nlev;
+  }
+  __syncthreads();
+  return true;
+}
+
+// One unlabelled level with the global frontier: the whole team (solo =
+// false) or one work-group (solo = true).  Advances cur_b / cur_e / level;
+// sets done when the level was the last one.
+__device__ __forceinline__ void global_bfs_level(const BfsParams& P, Team& t, Shared& S, int32_t end,
+                                 int32_t epoch, int32_t* tail, unsigned long long* minkey,
+                                 bool solo, int32_t& cur_b, int32_t& cur_e, int32_t& level,
+                                 bool& done) {
+  const int B = blockDim.x;
+  const int W = solo ? 1 : t.W;
+  const int wid = solo ? 0 : t.wid;
+  const int l3 = level % 3;
+  if (threadIdx.x == 0) {
+    S.cnt = 0;
+    S.key = kMaxKey;
+  }
+  __syncthreads();
+  int32_t lo, hi;
+  my_chunk(cur_b, cur_e, W, wid, lo, hi);
+  uint64_t mykey = kMaxKey;
+  const long long ta = wall_clock64();
+  bfs_expand(P, S, lo, hi, cur_e, end, epoch, tail + l3, mykey);
+  mykey = wave_min_u64(mykey);
+  if ((threadIdx.x & 63) == 0 && mykey != kMaxKey) atomicMin(&S.key, mykey);
+  __syncthreads();
+  const long long tb = wall_clock64();
+  if (threadIdx.x == 0) {
+    const int32_t ns = S.cnt < kStageCap ? S.cnt : kStageCap;
+    S.base = ns > 0 ? atomicAdd(tail + l3, ns) : 0;
+    if (S.key != kMaxKey) atomicMin(minkey + (level + 1) % 3, S.key);
+    if (wid == 0) {
+      // slots of the level after next; nobody reads them any more
+      st_relaxed(tail + (level + 1) % 3, 0);
+      __hip_atomic_store(minkey + (level + 2) % 3, kMaxKey, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+  __syncthreads();
+  const long long tc = wall_clock64();
+  {
+    const int32_t ns = S.cnt < kStageCap ? S.cnt : kStageCap;
+    const int4* stage = reinterpret_cast<const int4*>(S.u.srec);
+    for (int32_t i = threadIdx.x; i < ns; i += B) {
+      const int32_t at = cur_e + S.base + i;
+      if (at < end) P.qi[at] = stage[i];
+    }
+  }
+  team_barrier(t, S, solo);
+  if (t.aborted) return;
+  const int32_t cnt = ld_relaxed(tail + l3);
+  if (t.wid == 0 && threadIdx.x == 0) {
+    const long long td = wall_clock64();
+    if (solo) {
+      t.ctl->clk[10] += td - ta;
+      t.ctl->clk[11] += 1;
+    } else {
+      t.ctl->clk[4] += tb - ta;
+      t.ctl->clk[5] += tc - tb;
+      t.ctl->clk[6] += td - tc;
+      t.ctl->clk[7] += 1;
+    }
+  }
+  if (cnt == 0) {
+    done = true;
+    return;
+  }
+  cur_b = cur_e;
+  cur_e += cnt;
+  ++level;
+  if (cur_e > end) {  // left the component: the pattern is not symmetric
+    if (threadIdx.x == 0)
+      flag_error(t.g, RCM_ERR_NOT_SYMMETRIC, 1, t.comp, epoch, level, cur_b, cur_e, end);
+    done = true;
+  }
+}
+
 // One level structure (Section II-A) of the component whose label block is
 // [o, end), rooted at `root`.  Vertices are written level by level into qi.
 // Returns the eccentricity of root and the minimum (degree << 32 | id) over
-// the last level.
-__device__ void bfs_pass(const BfsParams& P, Team& t, Shared& S, int32_t o, int32_t end,
+// the last level.  With found_end, the block end is unknown (end bounds it)
+// and the pass reports where the component ended.
+__device__ __forceinline__ void bfs_pass(const BfsParams& P, Team& t, Shared& S, int32_t o, int32_t end,
                          int32_t root, int32_t epoch, int parity, int32_t& ecc,
-                         uint64_t& lastkey) {
+                         uint64_t& lastkey, int32_t* found_end) {
   const long long clk0 = wall_clock64();
   int32_t* tail = t.ctl->tail + parity * 3;
   unsigned long long* minkey = t.ctl->minkey + parity * 3;
@@ -246,12 +505,11 @@ __device__ void bfs_pass(const BfsParams& P, Team& t, Shared& S, int32_t o, int3
   team_barrier(t, S, false);
   if (t.aborted) return;
   int32_t cur_b = o, cur_e = o + 1, level = 0;
-  const int B = blockDim.x;
   bool done = false;
   while (!done) {
-    // narrow episode: work-group 0 alone while the frontier stays narrow
     const bool narrow = t.W > 1 && (cur_e - cur_b) < P.narrow_cutoff;
     if (narrow && t.wid != 0) {
+      // sleep until work-group 0 has walked the narrow stretch
       narrow_wait(t, S);
       if (t.aborted) return;
       cur_b = S.state[0];
@@ -260,84 +518,49 @@ __device__ void bfs_pass(const BfsParams& P, Team& t, Shared& S, int32_t o, int3
       done = S.state[3] != 0;
       continue;
     }
-    const bool solo = narrow || t.W == 1;
-    const int W = solo ? 1 : t.W;
-    const int wid = solo ? 0 : t.wid;
-    while (true) {
-      const int l3 = level % 3;
-      if (threadIdx.x == 0) {
-        S.cnt = 0;
-        S.key = kMaxKey;
-      }
-      __syncthreads();
-      int32_t lo, hi;
-      my_chunk(cur_b, cur_e, W, wid, lo, hi);
-      uint64_t mykey = kMaxKey;
-      const long long ta = wall_clock64();
-      bfs_expand(P, S, lo, hi, cur_e, end, epoch, tail + l3, mykey);
-      mykey = wave_min_u64(mykey);
-      if ((threadIdx.x & 63) == 0 && mykey != kMaxKey) atomicMin(&S.key, mykey);
-      __syncthreads();
-      const long long tb = wall_clock64();
-      if (threadIdx.x == 0) {
-        const int32_t ns = S.cnt < kStageCap ? S.cnt : kStageCap;
-        S.base = ns > 0 ? atomicAdd(tail + l3, ns) : 0;
-        if (S.key != kMaxKey) atomicMin(minkey + (level + 1) % 3, S.key);
-        if (wid == 0) {
-          // slots of the level after next; nobody reads them any more
-          st_relaxed(tail + (level + 1) % 3, 0);
-          __hip_atomic_store(minkey + (level + 2) % 3, kMaxKey, __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_AGENT);
+    if (narrow || t.W == 1) {
+      // one work-group: the LDS engine where the frontier fits, else one
+      // global level at a time
+      const int32_t stop = narrow ? P.narrow_cutoff : 0x7fffffff;
+      int skip = 0;
+      while (!done && (cur_e - cur_b) < stop) {
+        bool ran = false;
+        if (skip == 0) {
+          ran = lds_bfs_levels(P, t, S, end, epoch, tail, minkey, cur_b, cur_e, level, done,
+                               stop);
+          if (!ran) skip = 8;
+        } else {
+          --skip;
         }
+        if (!ran) global_bfs_level(P, t, S, end, epoch, tail, minkey, true, cur_b, cur_e, level,
+                                   done);
+        if (t.aborted) return;
       }
-      __syncthreads();
-      const long long tc = wall_clock64();
-      {
-        const int32_t ns = S.cnt < kStageCap ? S.cnt : kStageCap;
-        for (int32_t i = threadIdx.x; i < ns; i += B) {
-          const int32_t at = cur_e + S.base + i;
-          if (at < end) P.qi[at] = S.srec[i];
-        }
+      if (narrow) {
+        narrow_publish(t, cur_b, cur_e, level, done);
       }
-      team_barrier(t, S, solo);
-      if (t.aborted) return;
-      const int32_t cnt = ld_relaxed(tail + l3);
-      if (t.wid == 0 && threadIdx.x == 0) {
-        const long long td = wall_clock64();
-        const int slot = solo && t.W > 1 ? 8 : 4;
-        t.ctl->clk[slot + 0] += tb - ta;
-        t.ctl->clk[slot + 1] += tc - tb;
-        t.ctl->clk[slot + 2] += td - tc;
-        t.ctl->clk[slot + 3] += 1;
-      }
-      if (cnt == 0) {
-        done = true;
-        break;
-      }
-      cur_b = cur_e;
-      cur_e += cnt;
-      ++level;
-      if (cur_e > end) {  // left the component: the pattern is not symmetric
-        if (threadIdx.x == 0) flag_error(t.g, RCM_ERR_NOT_SYMMETRIC);
-        done = true;
-        break;
-      }
-      // a narrow episode ends when the frontier widens, a wide one when it
-      // narrows
-      if (narrow && (cur_e - cur_b) >= P.narrow_cutoff) break;
-      if (!narrow && t.W > 1 && (cur_e - cur_b) < P.narrow_cutoff) break;
+      continue;
     }
-    if (narrow) {
-      // hand the pass state back to the sleeping work-groups
-      const int32_t st[8] = {cur_b, cur_e, level, done ? 1 : 0, 0, 0, 0, 0};
-      narrow_publish(t, st);
+    // wide levels: the whole team
+    while (!done && (cur_e - cur_b) >= P.narrow_cutoff) {
+      global_bfs_level(P, t, S, end, epoch, tail, minkey, false, cur_b, cur_e, level, done);
+      if (t.aborted) return;
     }
   }
-  if (cur_e != end) {
-    if (threadIdx.x == 0 && t.wid == 0) flag_error(t.g, RCM_ERR_NOT_SYMMETRIC);
+  if (cur_e > end) {  // flagged inside already
     t.aborted = true;
     return;
   }
+  if (found_end != nullptr) {
+    // size discovery: the component is whatever this pass reached
+    *found_end = cur_e;
+  } else if (cur_e != end) {
+    if (threadIdx.x == 0 && t.wid == 0)
+      flag_error(t.g, RCM_ERR_NOT_SYMMETRIC, 2, t.comp, epoch, level, cur_b, cur_e, end);
+    t.aborted = true;
+    return;
+  }
+  __syncthreads();
   // the last level's slot is stable until the next pass of the same parity
   ecc = level;
   lastkey = ld_relaxed(minkey + level % 3);
@@ -379,6 +602,7 @@ __device__ __forceinline__ void place_long_row(const BfsParams& P, int32_t p, in
     uint32_t cl[kRB];
 #pragma unroll
     for (int j = 0; j < kRB; ++j) cl[j] = P.claim[nb[j]];
+#pragma unroll
     for (int j = 0; j < kRB; ++j) {
       if (!(nb[j] != u && cl[j] == pl)) continue;
       const int4 inf = P.vinfo[nb[j]];
@@ -422,15 +646,282 @@ __device__ __forceinline__ int count_long_row(const BfsParams& P, int32_t p, int
   return c;
 }
 
-// The labelled BFS of Algorithm 3 from `root`; labels are the positions in
-// qi[o, end).  Per level: (B) each parent counts its children -- the
+// Labelled levels in one work-group with the frontier in LDS (one parent per
+// thread, rows of at most kRB entries).  (1) Every parent loads its row and
+// the claim words and records of its neighbours; an unlabelled neighbour
+// (claim word not below cur_b) is entered into the next level's LDS table
+// and takes the smallest claiming label there (the (select2nd, min) product
+// done with LDS atomics).  (2) The children of a parent are the neighbours
+// whose table entry holds its label; they are ranked by (degree, id), placed
+// after an LDS scan of the counts, and their claim words set to the parent's
+// label (which marks them labelled).  On leaving, the new frontier issues its
+// claims on global memory, as the team levels expect.  Returns false, having
+// done nothing, when the frontier does not fit.
+__device__ __forceinline__ bool lds_label_levels(const BfsParams& P, Team& t, Shared& S, int32_t end,
+                                 int32_t& cur_b, int32_t& cur_e, int32_t& levels, bool& done,
+                                 long long& my_m, int32_t stop_width) {
+  NarrowLds& N = S.u.nw;
+  const int B = blockDim.x;
+  int32_t len = cur_e - cur_b;
+  if (len > B || len > kNarrowCap) return false;
+  const long long c0 = wall_clock64();
+  long long mr = 0, rs = 0;
+  for (int32_t i = threadIdx.x; i < len; i += B) {
+    const int4 r = P.qi[cur_b + i];
+    lds_put(N, 0, i, r);
+    mr = (r.z - r.y) > mr ? (r.z - r.y) : mr;
+    rs += r.z - r.y;
+  }
+  mr = block_max_i64(mr, S.red);
+  rs = block_sum_i64(rs, S.red);
+  // one batch per row, and at most kHash / 2 row entries so that the next
+  // level's table stays at most half full
+  if (mr > kRB || rs > kHash / 2) return false;
+  for (int i = threadIdx.x; i < 2 * kHash; i += B) {
+    (&N.key[0][0])[i] = kEmpty;
+    (&N.val[0][0])[i] = kUnclaimed;
+  }
+  if (threadIdx.x == 0)
+    for (int i = 0; i < 3; ++i) {
+      N.maxrow[i] = 0;
+      N.rows[i] = 0;
+    }
+  __syncthreads();
+  int lv = 0;
+  int32_t nlev = 0;
+  while (true) {
+    int32_t* key_ins = N.key[lv & 1];
+    uint32_t* val_ins = N.val[lv & 1];
+    int32_t* key_clr = N.key[(lv + 1) & 1];
+    uint32_t* val_clr = N.val[(lv + 1) & 1];
+    const int mx = (lv + 1) % 3;
+    if (threadIdx.x == 0) {
+      N.maxrow[(lv + 2) % 3] = 0;
+      N.rows[(lv + 2) % 3] = 0;
+    }
+    // (1) claims in LDS
+    const bool active = static_cast<int32_t>(threadIdx.x) < len;
+    const int32_t p = cur_b + static_cast<int32_t>(threadIdx.x);
+    const uint32_t pl = static_cast<uint32_t>(p);
+    int4 e = make_int4(0, 0, 0, 0);
+    int32_t nb[kRB];
+    int4 inf[kRB];
+    int slot[kRB];
+    unsigned unl = 0;
+    if (active) {
+      e = lds_rec(N, lv & 1, threadIdx.x);
+      if (e.z > e.y) {
+        load_batch(P.colidx, e.y, e.z, e.x, nb);
+        uint32_t cl[kRB];
+#pragma unroll
+        for (int j = 0; j < kRB; ++j) cl[j] = P.claim[nb[j]];
+#pragma unroll
+        for (int j = 0; j < kRB; ++j) inf[j] = P.vinfo[nb[j]];
+#pragma unroll
+        for (int j = 0; j < kRB; ++j) {
+          slot[j] = -1;
+          if (nb[j] == e.x || cl[j] < static_cast<uint32_t>(cur_b)) continue;
+          bool fresh = false;
+          slot[j] = h_insert(key_ins, nb[j], &fresh);
+          if (slot[j] < 0) continue;  // cannot happen: the table is at most half full
+          atomicMin(&val_ins[slot[j]], pl);
+          unl |= 1u << j;
+        }
+      }
+    }
+    // the other table was last used two levels ago
+    for (int i = threadIdx.x; i < kHash; i += B) {
+      key_clr[i] = kEmpty;
+      val_clr[i] = kUnclaimed;
+    }
+    __syncthreads();
+    // (2) children of p, their ranks and labels
+    unsigned ch = 0;
+#pragma unroll
+    for (int j = 0; j < kRB; ++j)
+      if ((unl >> j & 1u) && val_ins[slot[j]] == pl) ch |= 1u << j;
+    const int c = __popc(ch);
+    int total;
+    const int ex = block_excl_scan(c, S.scan, &total);
+    if (total == 0) {
+      done = true;
+      ++nlev;
+      break;
+    }
+    if (c > 0) {
+      uint64_t key[kRB];
+#pragma unroll
+      for (int j = 0; j < kRB; ++j) key[j] = (ch >> j & 1u) ? pack_key(inf[j].z, nb[j]) : kMaxKey;
+      const int32_t base = cur_e + ex;
+#pragma unroll
+      for (int j = 0; j < kRB; ++j) {
+        if (!(ch >> j & 1u)) continue;
+        int rank = 0;
+#pragma unroll
+        for (int i = 0; i < kRB; ++i) rank += key[i] < key[j] ? 1 : 0;
+        const int32_t at = base + rank;
+        const int4 r = record(nb[j], inf[j]);
+        if (at < end) P.qi[at] = r;
+        if (at - cur_e < kNarrowCap) lds_put(N, (lv + 1) & 1, at - cur_e, r);
+        P.claim[nb[j]] = pl;
+        my_m += inf[j].z;
+        atomicMax(&N.maxrow[mx], inf[j].y - inf[j].x);
+        atomicAdd(&N.rows[mx], inf[j].y - inf[j].x);
+      }
+    }
+    __syncthreads();
+    ++nlev;
+    cur_b = cur_e;
+    cur_e += total;
+    ++levels;
+    ++lv;
+    len = total;
+    if (cur_e > end) {
+      if (threadIdx.x == 0)
+        flag_error(t.g, RCM_ERR_NOT_SYMMETRIC, 7, t.comp, 0, levels, cur_b, cur_e, end);
+      done = true;
+      break;
+    }
+    if (len > B || len > kNarrowCap || N.maxrow[mx] > kRB || N.rows[mx] > kHash / 2 ||
+        len >= stop_width)
+      break;
+  }
+  if (!done) {
+    // the team levels expect the frontier's claims on the next level
+    for (int32_t i = threadIdx.x; i < len; i += B) {
+      const int4 r = P.qi[cur_b + i];
+      claim_row(P, r.x, make_int4(r.y, r.z, r.w, 0), static_cast<uint32_t>(cur_b + i));
+    }
+  }
+  if (threadIdx.x == 0) {
+    t.ctl->clk[14] += wall_clock64() - c0;
+    t.ctl->clk[15] += nlev;
+  }
+  __syncthreads();
+  return true;
+}
+
+// One labelled level with the global frontier, by the whole team (solo =
+// false) or one work-group.  (B) each parent counts its children -- the
 // neighbours whose claim equals its label -- keeping them in registers when
 // its row fits one batch; barrier; (C) a scan of the counts in label order
 // gives every parent its first child label, children are placed by their
 // (degree, id) rank, and each placed child immediately claims its own
-// neighbours for the next level; barrier.  Returns the number of levels;
-// *msum = sum of degrees.
-__device__ int32_t label_pass(const BfsParams& P, Team& t, Shared& S, int32_t o, int32_t end,
+// neighbours for the next level; barrier.
+__device__ __forceinline__ void global_label_level(const BfsParams& P, Team& t, Shared& S, int32_t end, bool solo,
+                                   int32_t& cur_b, int32_t& cur_e, int32_t& levels, bool& done,
+                                   long long& my_m) {
+  const int B = blockDim.x;
+  const int W = solo ? 1 : t.W;
+  const int wid = solo ? 0 : t.wid;
+  int32_t lo, hi;
+  my_chunk(cur_b, cur_e, W, wid, lo, hi);
+  const long long ta = wall_clock64();
+  const bool one_round = hi - lo <= B;
+  bool captured = false;
+  int c_mine = 0;
+  int32_t cnb[kRB];
+  int4 cinf[kRB];
+  unsigned cmask = 0;
+  int wg_total = 0;
+  for (int32_t p = lo + threadIdx.x; p < hi; p += B) {
+    const int4 e = P.qi[p];
+    const int32_t u = e.x;
+    const uint32_t pl = static_cast<uint32_t>(p);
+    int c;
+    if (one_round && e.z - e.y <= kRB) {
+      if (e.z > e.y) {
+        load_batch(P.colidx, e.y, e.z, u, cnb);
+        uint32_t cl[kRB];
+#pragma unroll
+        for (int j = 0; j < kRB; ++j) cl[j] = P.claim[cnb[j]];
+#pragma unroll
+        for (int j = 0; j < kRB; ++j) cinf[j] = P.vinfo[cnb[j]];
+#pragma unroll
+        for (int j = 0; j < kRB; ++j) cmask |= (cnb[j] != u && cl[j] == pl ? 1u : 0u) << j;
+      }
+      captured = true;
+      c = __popc(cmask);
+    } else {
+      c = count_long_row(P, p, u, e.y, e.z);
+      P.tmp[p] = c;
+    }
+    c_mine = c;
+    wg_total += c;
+  }
+  {
+    const long long tot = block_sum_i64(wg_total, S.red);
+    if (threadIdx.x == 0) st_relaxed(&t.ctl->wg_sum[wid], static_cast<int32_t>(tot));
+  }
+  team_barrier(t, S, solo);
+  if (t.aborted) return;
+  if (threadIdx.x < W) S.wsum[threadIdx.x] = ld_relaxed(&t.ctl->wg_sum[threadIdx.x]);
+  __syncthreads();
+  int32_t prefix = 0, total = 0;
+  for (int w = 0; w < W; ++w) {
+    prefix += w < wid ? S.wsum[w] : 0;
+    total += S.wsum[w];
+  }
+  if (total == 0) {
+    done = true;
+    return;
+  }
+  int32_t run = cur_e + prefix;
+  for (int32_t r0 = lo; r0 < hi; r0 += B) {
+    const int32_t p = r0 + threadIdx.x;
+    const int c = p < hi ? (one_round ? c_mine : P.tmp[p]) : 0;
+    int rtot;
+    const int ex = block_excl_scan(c, S.scan, &rtot);
+    if (c > 0) {
+      const int32_t base = run + ex;
+      if (captured) {
+        uint64_t key[kRB];
+#pragma unroll
+        for (int j = 0; j < kRB; ++j)
+          key[j] = (cmask >> j & 1u) ? pack_key(cinf[j].z, cnb[j]) : kMaxKey;
+        int32_t at[kRB];
+#pragma unroll
+        for (int j = 0; j < kRB; ++j) {
+          int rank = 0;
+#pragma unroll
+          for (int i = 0; i < kRB; ++i) rank += key[i] < key[j] ? 1 : 0;
+          at[j] = base + rank;
+        }
+#pragma unroll
+        for (int j = 0; j < kRB; ++j) {
+          if (!(cmask >> j & 1u)) continue;
+          if (at[j] < end) P.qi[at[j]] = record(cnb[j], cinf[j]);
+          my_m += cinf[j].z;
+        }
+#pragma unroll
+        for (int j = 0; j < kRB; ++j)
+          if (cmask >> j & 1u) claim_row(P, cnb[j], cinf[j], static_cast<uint32_t>(at[j]));
+      } else {
+        const int4 e = P.qi[p];
+        place_long_row(P, p, e.x, e.y, e.z, base, end, my_m);
+      }
+    }
+    run += rtot;
+  }
+  team_barrier(t, S, solo);
+  if (t.aborted) return;
+  if (t.wid == 0 && threadIdx.x == 0 && !solo) {
+    t.ctl->clk[12] += wall_clock64() - ta;
+    t.ctl->clk[13] += 1;
+  }
+  cur_b = cur_e;
+  cur_e += total;
+  ++levels;
+  if (cur_e > end) {
+    if (threadIdx.x == 0)
+      flag_error(t.g, RCM_ERR_NOT_SYMMETRIC, 3, t.comp, 0, levels, cur_b, cur_e, end);
+    done = true;
+  }
+}
+
+// The labelled BFS of Algorithm 3 from `root`; labels are the positions in
+// qi[o, end).  Returns the number of levels; *msum = sum of degrees.
+__device__ __forceinline__ int32_t label_pass(const BfsParams& P, Team& t, Shared& S, int32_t o, int32_t end,
                               int32_t root, long long* msum) {
   const long long clk0 = wall_clock64();
   const int B = blockDim.x;
@@ -462,123 +953,33 @@ __device__ int32_t label_pass(const BfsParams& P, Team& t, Shared& S, int32_t o,
       done = S.state[3] != 0;
       continue;
     }
-    const bool solo = narrow || t.W == 1;
-    const int W = solo ? 1 : t.W;
-    const int wid = solo ? 0 : t.wid;
-    while (true) {
-      int32_t lo, hi;
-      my_chunk(cur_b, cur_e, W, wid, lo, hi);
-      const long long ta = wall_clock64();
-      // B: count (and capture) the children of every parent
-      const bool one_round = hi - lo <= B;
-      bool captured = false;
-      int c_mine = 0;
-      int32_t cnb[kRB];
-      int4 cinf[kRB];
-      unsigned cmask = 0;
-      int wg_total = 0;
-      for (int32_t p = lo + threadIdx.x; p < hi; p += B) {
-        const int4 e = P.qi[p];
-        const int32_t u = e.x;
-        const uint32_t pl = static_cast<uint32_t>(p);
-        int c;
-        if (one_round && e.z - e.y <= kRB) {
-          if (e.z > e.y) {
-            load_batch(P.colidx, e.y, e.z, u, cnb);
-            uint32_t cl[kRB];
-#pragma unroll
-            for (int j = 0; j < kRB; ++j) cl[j] = P.claim[cnb[j]];
-#pragma unroll
-            for (int j = 0; j < kRB; ++j) cinf[j] = P.vinfo[cnb[j]];
-#pragma unroll
-            for (int j = 0; j < kRB; ++j) cmask |= (cnb[j] != u && cl[j] == pl ? 1u : 0u) << j;
-          }
-          captured = true;
-          c = __popc(cmask);
+    if (narrow || t.W == 1) {
+      const int32_t stop = narrow ? P.narrow_cutoff : 0x7fffffff;
+      int skip = 0;
+      while (!done && (cur_e - cur_b) < stop) {
+        bool ran = false;
+        if (skip == 0) {
+          ran = lds_label_levels(P, t, S, end, cur_b, cur_e, levels, done, my_m, stop);
+          if (!ran) skip = 8;
         } else {
-          c = count_long_row(P, p, u, e.y, e.z);
-          P.tmp[p] = c;
+          --skip;
         }
-        c_mine = c;
-        wg_total += c;
+        if (!ran) global_label_level(P, t, S, end, true, cur_b, cur_e, levels, done, my_m);
+        if (t.aborted) return 0;
       }
-      {
-        const long long tot = block_sum_i64(wg_total, S.red);
-        if (threadIdx.x == 0) st_relaxed(&t.ctl->wg_sum[wid], static_cast<int32_t>(tot));
+      if (narrow) {
+        narrow_publish(t, cur_b, cur_e, levels, done);
       }
-      team_barrier(t, S, solo);
-      if (t.aborted) return 0;
-      const long long tb = wall_clock64();
-      if (threadIdx.x < W) S.wsum[threadIdx.x] = ld_relaxed(&t.ctl->wg_sum[threadIdx.x]);
-      __syncthreads();
-      int32_t prefix = 0, total = 0;
-      for (int w = 0; w < W; ++w) {
-        prefix += w < wid ? S.wsum[w] : 0;
-        total += S.wsum[w];
-      }
-      if (total == 0) {
-        done = true;
-        break;
-      }
-      // C: place the children, then claim for the next level
-      int32_t run = cur_e + prefix;
-      for (int32_t r0 = lo; r0 < hi; r0 += B) {
-        const int32_t p = r0 + threadIdx.x;
-        const int c = p < hi ? (one_round ? c_mine : P.tmp[p]) : 0;
-        int rtot;
-        const int ex = block_excl_scan(c, S.scan, &rtot);
-        if (c > 0) {
-          const int32_t base = run + ex;
-          if (captured) {
-            uint64_t key[kRB];
-#pragma unroll
-            for (int j = 0; j < kRB; ++j)
-              key[j] = (cmask >> j & 1u) ? pack_key(cinf[j].z, cnb[j]) : kMaxKey;
-            for (int j = 0; j < kRB; ++j) {
-              if (!(cmask >> j & 1u)) continue;
-              int rank = 0;
-#pragma unroll
-              for (int i = 0; i < kRB; ++i) rank += key[i] < key[j] ? 1 : 0;
-              const int32_t at = base + rank;
-              if (at < end) P.qi[at] = record(cnb[j], cinf[j]);
-              my_m += cinf[j].z;
-              claim_row(P, cnb[j], cinf[j], static_cast<uint32_t>(at));
-            }
-          } else {
-            const int4 e = P.qi[p];
-            place_long_row(P, p, e.x, e.y, e.z, base, end, my_m);
-          }
-        }
-        run += rtot;
-      }
-      const long long tc = wall_clock64();
-      team_barrier(t, S, solo);
-      if (t.aborted) return 0;
-      if (t.wid == 0 && threadIdx.x == 0 && !solo) {
-        const long long td = wall_clock64();
-        t.ctl->clk[12] += tb - ta;
-        t.ctl->clk[13] += tc - tb;
-        t.ctl->clk[14] += td - tc;
-        t.ctl->clk[15] += 1;
-      }
-      cur_b = cur_e;
-      cur_e += total;
-      ++levels;
-      if (cur_e > end) {
-        if (threadIdx.x == 0) flag_error(t.g, RCM_ERR_NOT_SYMMETRIC);
-        done = true;
-        break;
-      }
-      if (narrow && (cur_e - cur_b) >= P.narrow_cutoff) break;
-      if (!narrow && t.W > 1 && (cur_e - cur_b) < P.narrow_cutoff) break;
+      continue;
     }
-    if (narrow) {
-      const int32_t st[8] = {cur_b, cur_e, levels, done ? 1 : 0, 0, 0, 0, 0};
-      narrow_publish(t, st);
+    while (!done && (cur_e - cur_b) >= P.narrow_cutoff) {
+      global_label_level(P, t, S, end, false, cur_b, cur_e, levels, done, my_m);
+      if (t.aborted) return 0;
     }
   }
   if (cur_e != end) {
-    if (threadIdx.x == 0 && t.wid == 0) flag_error(t.g, RCM_ERR_NOT_SYMMETRIC);
+    if (threadIdx.x == 0 && t.wid == 0)
+      flag_error(t.g, RCM_ERR_NOT_SYMMETRIC, 4, t.comp, 0, levels, cur_b, cur_e, end);
     t.aborted = true;
     return 0;
   }
@@ -595,22 +996,30 @@ __device__ int32_t label_pass(const BfsParams& P, Team& t, Shared& S, int32_t o,
   return levels;
 }
 
-__device__ void order_component(const BfsParams& P, Team& t, Shared& S, const CompTask& task) {
+__device__ __forceinline__ void order_component(const BfsParams& P, Team& t, Shared& S, const CompTask& task) {
   const int32_t o = task.offset;
-  const int32_t end = o + task.size;
+  // a task of unknown size (the component of vertex 0) learns it from the
+  // first level structure, which visits the whole component
+  int32_t size = task.size;
+  int32_t end = size >= 0 ? o + size : P.n;
   // Algorithm 2: start at the component's lowest id
   int32_t ecc = 0;
   uint64_t lastkey = 0;
   int32_t nbfs = 1;
-  bfs_pass(P, t, S, o, end, task.seed, 1, 0, ecc, lastkey);
+  int32_t found = end;
+  bfs_pass(P, t, S, o, end, task.seed, 1, 0, ecc, lastkey, size >= 0 ? nullptr : &found);
   if (t.aborted) return;
+  if (size < 0) {
+    size = found - o;
+    end = found;
+  }
   int32_t r = task.seed;
   int32_t nlvl = ecc - 1;
   while (ecc > nlvl) {
     nlvl = ecc;
     const int32_t v = static_cast<int32_t>(lastkey & 0xffffffffu);  // min degree, last level
     ++nbfs;
-    bfs_pass(P, t, S, o, end, v, nbfs, (nbfs - 1) & 1, ecc, lastkey);
+    bfs_pass(P, t, S, o, end, v, nbfs, (nbfs - 1) & 1, ecc, lastkey, nullptr);
     if (t.aborted) return;
     r = v;
   }
@@ -623,13 +1032,15 @@ __device__ void order_component(const BfsParams& P, Team& t, Shared& S, const Co
     res->root = root;
     res->nbfs = nbfs;
     res->levels = levels;
+    res->size = size;
     res->m = m;
   }
   // reversal: Cuthill-McKee label t of this component goes to anchor - t
+  const int32_t anchor = task.anchor >= 0 ? task.anchor : o + size - 1;
   const int32_t nthreads = t.W * blockDim.x;
-  for (int32_t i = t.wid * blockDim.x + threadIdx.x; i < task.size; i += nthreads) {
+  for (int32_t i = t.wid * blockDim.x + threadIdx.x; i < size; i += nthreads) {
     const int32_t v = P.qi[o + i].x;
-    const int32_t pos = task.anchor - i;
+    const int32_t pos = anchor - i;
     P.perm[pos] = v;
     if (v >= 0 && v < P.n) P.iperm[v] = pos;
   }
@@ -659,6 +1070,7 @@ __global__ void __launch_bounds__(512) k_order(BfsParams P) {
     }
     if (ti >= P.ntasks) break;
     const CompTask task = P.tasks[ti];
+    t.comp = task.index;
     order_component(P, t, S, task);
     if (t.aborted) break;
   }

@@ -22,10 +22,11 @@ constexpr long long kWaitLimitTicks = 30ll * 100000000ll;
 // ---------------------------------------------------------------------------
 struct CompTask {
   int32_t seed;    // lowest vertex id of the component = start vertex
-  int32_t size;    // number of vertices
+  int32_t size;    // number of vertices; -1 = unknown, found by the first BFS
   int32_t offset;  // first position of the component's label block
   int32_t index;   // component index (ascending seed order)
-  int32_t anchor;  // Cuthill-McKee label t of the component lands at position anchor - t
+  int32_t anchor;  // Cuthill-McKee label t of the component lands at position
+                   // anchor - t; -1 = offset + size - 1 (size found by the BFS)
 };
 
 struct CompResult {
@@ -33,6 +34,8 @@ struct CompResult {
   int32_t nbfs;    // level structures computed by the search
   int32_t levels;  // levels of the labelled BFS
   int32_t seg;     // graph (segment) the component belongs to
+  int32_t size;    // number of vertices
+  int32_t pad;
   int64_t m;       // sum of degrees over the component
 };
 
@@ -60,8 +63,10 @@ struct alignas(128) TeamCtl {
 // Global control shared by all teams of one launch.
 struct alignas(128) GlobalCtl {
   int32_t queue;                 // next task for single-WG teams
-  int32_t error;                 // set to RCM_ERR_ABORTED by a timed-out wait
-  int32_t pad[30];
+  int32_t error;                 // first error of the launch (rcm_status)
+  int32_t diag[8];               // where it was detected: site, component index,
+                                 // pass (0 = labelled), level, cur_b, cur_e, end
+  int32_t pad[22];
 };
 
 // Per-segment (per-graph) accumulators filled by the device.
@@ -208,14 +213,19 @@ struct Graph {
 hipError_t launch_validate_scan(const Graph& g, int4* vinfo, int32_t* beta, SegStats* seg,
                                 int32_t* err, hipStream_t s);
 hipError_t launch_full_check(const Graph& g, int32_t* err_dup, int32_t* err_sym, hipStream_t s);
-hipError_t launch_components(const Graph& g, int32_t* parent, int32_t* csize, int32_t* flags,
-                             int32_t* scan_tmp, int32_t* seeds, int32_t* num_comps,
-                             hipStream_t s);
+// Components of the vertices with skip[v] == 0 (skip may be null: all).
+hipError_t launch_components(const Graph& g, const int32_t* skip, int32_t* parent, int32_t* csize,
+                             int32_t* flags, int32_t* scan_tmp, int32_t* seeds,
+                             int32_t* num_comps, int32_t* err_asym, hipStream_t s);
+// Tasks for ncomp components whose seeds are seeds[0..ncomp); their label
+// blocks start at offset_base and their indices at index_base.  counts[0..2]
+// receive the numbers of isolated / small / large tasks, counts[3] the
+// total number of vertices covered.
 hipError_t launch_tasks(const Graph& g, int32_t ncomp, const int32_t* seeds, const int32_t* csize,
-                        int32_t small_cutoff, int32_t reverse_mode, CompTask* tasks_single,
-                        CompTask* tasks_small, CompTask* tasks_big, int32_t* counts,
-                        int32_t* sizes, int32_t* offs, int32_t* scan_blk, CompResult* results,
-                        hipStream_t s);
+                        int32_t small_cutoff, int32_t reverse_mode, int32_t offset_base,
+                        int32_t index_base, CompTask* tasks_single, CompTask* tasks_small,
+                        CompTask* tasks_big, int32_t* counts, int32_t* sizes, int32_t* offs,
+                        int32_t* scan_blk, CompResult* results, hipStream_t s);
 hipError_t launch_singletons(const CompTask* tasks, int32_t count, int32_t* perm, int32_t* iperm,
                              CompResult* results, hipStream_t s);
 hipError_t launch_bw_after(const Graph& g, const int32_t* perm, const int32_t* iperm,

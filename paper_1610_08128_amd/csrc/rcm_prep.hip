@@ -156,10 +156,18 @@ __global__ void k_cc_init(int32_t n, int32_t* __restrict__ parent) {
 }
 
 __global__ void k_cc_hook(int32_t n, const int32_t* __restrict__ rowptr,
-                          const int32_t* __restrict__ colidx, int32_t* parent) {
+                          const int32_t* __restrict__ colidx, const int32_t* __restrict__ skip,
+                          int32_t* parent, int32_t* __restrict__ err) {
   for (int32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += gridDim.x * blockDim.x) {
+    if (skip && skip[u] != 0) continue;
     for (int32_t k = rowptr[u]; k < rowptr[u + 1]; ++k) {
       const int32_t v = colidx[k];
+      // a skipped (already ordered) component is closed under adjacency in a
+      // symmetric pattern, so an edge into it means (u, v) lacks (v, u)
+      if (skip && skip[v] != 0) {
+        atomicOr(err, 1);
+        continue;
+      }
       if (v >= u) continue;  // each undirected edge once
       int32_t a = uf_find(parent, u);
       int32_t b = uf_find(parent, v);
@@ -177,24 +185,40 @@ __global__ void k_cc_hook(int32_t n, const int32_t* __restrict__ rowptr,
   }
 }
 
-__global__ void k_cc_compress(int32_t n, int32_t* parent, int32_t* __restrict__ flags) {
+// Root of x without writing anything on the way.  The compression below must
+// not halve paths: a halving store into parent[i] from another thread could
+// land after i's own root store and leave i pointing at a non-root.
+__device__ __forceinline__ int32_t uf_root(const int32_t* parent, int32_t x) {
+  while (true) {
+    const int32_t p = ld_relaxed(parent + x);
+    if (p == x) return x;
+    x = p;
+  }
+}
+
+// After hooking: every parent[i] becomes its root (the only store into
+// parent[i] is this one, by the thread that owns i; concurrent readers see
+// either the old parent or the root, both ancestors of i).
+__global__ void k_cc_compress(int32_t n, int32_t* parent, const int32_t* __restrict__ skip,
+                              int32_t* __restrict__ flags) {
   for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    const int32_t r = uf_find(parent, i);
-    parent[i] = r;
-    flags[i] = (r == i);
+    const int32_t r = uf_root(parent, i);
+    __hip_atomic_store(parent + i, r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    flags[i] = (r == i) && !(skip && skip[i] != 0);
   }
 }
 
 // Component sizes: histogram of roots with a small LDS hash per block, so a
 // giant component costs one global atomic per block.
 __global__ void k_cc_sizes(int32_t n, const int32_t* __restrict__ parent,
-                           int32_t* __restrict__ csize) {
+                           const int32_t* __restrict__ skip, int32_t* __restrict__ csize) {
   constexpr int H = 256;
   __shared__ int32_t keys[H];
   __shared__ int32_t cnts[H];
   for (int h = threadIdx.x; h < H; h += blockDim.x) { keys[h] = -1; cnts[h] = 0; }
   __syncthreads();
   for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    if (skip && skip[i] != 0) continue;
     const int32_t r = parent[i];
     uint32_t h = (static_cast<uint32_t>(r) * 2654435761u) >> 24;
     bool done = false;
@@ -291,14 +315,15 @@ __device__ __forceinline__ void append_task(CompTask* list, int32_t* counter, co
 __global__ void k_build_tasks(int32_t ncomp, const int32_t* __restrict__ seeds,
                               const int32_t* __restrict__ sizes, const int32_t* __restrict__ offs,
                               const int32_t* __restrict__ seg_off, int nseg, int32_t small_cutoff,
-                              int32_t reverse_mode, CompTask* tasks_single, CompTask* tasks_small,
-                              CompTask* tasks_big, int32_t* counts, CompResult* results) {
+                              int32_t reverse_mode, int32_t offset_base, int32_t index_base,
+                              CompTask* tasks_single, CompTask* tasks_small, CompTask* tasks_big,
+                              int32_t* counts, CompResult* results) {
   for (int32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < ncomp; c += gridDim.x * blockDim.x) {
     CompTask t;
     t.seed = seeds[c];
     t.size = sizes[c];
-    t.offset = offs[c];
-    t.index = c;
+    t.offset = offset_base + offs[c];
+    t.index = index_base + c;
     const int s = find_segment(seg_off, nseg, t.seed);
     // label t of the component (0-based, Cuthill-McKee order) lands at
     // position anchor - t after reversal
@@ -309,8 +334,10 @@ __global__ void k_build_tasks(int32_t ncomp, const int32_t* __restrict__ seeds,
     r.nbfs = 0;
     r.levels = 0;
     r.seg = s;
+    r.size = t.size;
+    r.pad = 0;
     r.m = 0;
-    results[c] = r;
+    results[t.index] = r;
     if (t.size == 1)
       append_task(tasks_single, counts + 0, t);
     else if (t.size <= small_cutoff)
@@ -331,6 +358,7 @@ __global__ void k_singletons(const CompTask* __restrict__ tasks, int32_t count,
     results[t.index].root = t.seed;
     results[t.index].nbfs = 2;
     results[t.index].levels = 1;
+    results[t.index].size = 1;
     results[t.index].m = 0;
   }
 }
@@ -437,16 +465,16 @@ hipError_t launch_full_check(const Graph& g, int32_t* err_dup, int32_t* err_sym,
   return hipGetLastError();
 }
 
-hipError_t launch_components(const Graph& g, int32_t* parent, int32_t* csize, int32_t* flags,
-                             int32_t* scan_tmp, int32_t* seeds, int32_t* num_comps,
-                             hipStream_t s) {
+hipError_t launch_components(const Graph& g, const int32_t* skip, int32_t* parent, int32_t* csize,
+                             int32_t* flags, int32_t* scan_tmp, int32_t* seeds,
+                             int32_t* num_comps, int32_t* err_asym, hipStream_t s) {
   const int nb = grid_for(g.n, kThreads);
   k_cc_init<<<nb, kThreads, 0, s>>>(g.n, parent);
-  k_cc_hook<<<nb, kThreads, 0, s>>>(g.n, g.rowptr, g.colidx, parent);
-  k_cc_compress<<<nb, kThreads, 0, s>>>(g.n, parent, flags);
+  k_cc_hook<<<nb, kThreads, 0, s>>>(g.n, g.rowptr, g.colidx, skip, parent, err_asym);
+  k_cc_compress<<<nb, kThreads, 0, s>>>(g.n, parent, skip, flags);
   hipError_t e = hipMemsetAsync(csize, 0, sizeof(int32_t) * static_cast<size_t>(g.n), s);
   if (e != hipSuccess) return e;
-  k_cc_sizes<<<grid_for(g.n, kThreads, 2048), kThreads, 0, s>>>(g.n, parent, csize);
+  k_cc_sizes<<<grid_for(g.n, kThreads, 2048), kThreads, 0, s>>>(g.n, parent, skip, csize);
   // positions of seeds in ascending id order; reuse seeds as the scan output
   // then scatter into seeds' final slots (scan output lives in scan_tmp tail)
   int32_t* pos = scan_tmp;
@@ -458,19 +486,19 @@ hipError_t launch_components(const Graph& g, int32_t* parent, int32_t* csize, in
 }
 
 hipError_t launch_tasks(const Graph& g, int32_t ncomp, const int32_t* seeds, const int32_t* csize,
-                        int32_t small_cutoff, int32_t reverse_mode, CompTask* tasks_single,
-                        CompTask* tasks_small, CompTask* tasks_big, int32_t* counts,
-                        int32_t* sizes, int32_t* offs, int32_t* scan_blk, CompResult* results,
-                        hipStream_t s) {
+                        int32_t small_cutoff, int32_t reverse_mode, int32_t offset_base,
+                        int32_t index_base, CompTask* tasks_single, CompTask* tasks_small,
+                        CompTask* tasks_big, int32_t* counts, int32_t* sizes, int32_t* offs,
+                        int32_t* scan_blk, CompResult* results, hipStream_t s) {
   const int nb = grid_for(ncomp, kThreads);
   k_gather_sizes<<<nb, kThreads, 0, s>>>(ncomp, seeds, csize, sizes);
-  hipError_t e = launch_exclusive_scan(sizes, offs, ncomp, scan_blk, nullptr, s);
+  hipError_t e = launch_exclusive_scan(sizes, offs, ncomp, scan_blk, counts + 3, s);
   if (e != hipSuccess) return e;
   e = hipMemsetAsync(counts, 0, 3 * sizeof(int32_t), s);
   if (e != hipSuccess) return e;
   k_build_tasks<<<nb, kThreads, 0, s>>>(ncomp, seeds, sizes, offs, g.seg_off, g.nseg,
-                                        small_cutoff, reverse_mode, tasks_single, tasks_small,
-                                        tasks_big, counts, results);
+                                        small_cutoff, reverse_mode, offset_base, index_base,
+                                        tasks_single, tasks_small, tasks_big, counts, results);
   return hipGetLastError();
 }
 

@@ -126,6 +126,24 @@ def test_strip_32x500000():
     check(g)
 
 
+@pytest.mark.parametrize("case", range(4))
+def test_head_component_shapes(case):
+    """The component of vertex 0 is ordered before the component search;
+    cover it being isolated, small, the largest, and the only component."""
+    if case == 0:
+        g = I.disjoint_union([I.path(1), I.grid2d(40, 50, seed=3), I.complete(5)])
+    elif case == 1:
+        g = I.disjoint_union([I.path(3), I.grid3d(12, 12, 12, seed=4), I.path(1), I.cycle(9)])
+    elif case == 2:
+        g = I.disjoint_union([I.grid2d(60, 70, seed=5), I.path(1), I.path(1), I.star(7)])
+    else:
+        g = I.grid2d(33, 65, seed=6)
+    g.name = f"head{case}"
+    check(g)
+    check(g, reverse_mode=1, pp_variant=1)
+    check(g, small_cutoff=1, team_size=4)
+
+
 def test_repeated_runs_identical():
     g = I.config(0, seed=11)
     first = gpu_order(g)[0]
