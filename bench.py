@@ -36,10 +36,33 @@ WORKLOADS = {
     "strip_32x500000_drop1pct": (2, "2D 5-point 32x500,000 strip, 1% edges dropped, relabelled (seed 3)"),
 }
 
-# rocprofv3 FETCH_SIZE/WRITE_SIZE of the ordering kernel on the default
-# workload, per launch (KiB), scaled by the copy-kernel calibration factor
-# (see profiles/); None until measured for the current kernel.
-MEASURED_TRAFFIC_BYTES = None
+# HBM bytes per launch of the ordering kernel from two rocprofv3 counter runs
+# (FETCH_SIZE, WRITE_SIZE), each scaled by what the same counter read for a
+# 256 MiB device copy; keyed by workload and by a hash of the kernel's
+# sources at the time of the measurement, so a changed kernel reports null.
+# Summaries with the commands: profiles/k_order_<workload>_hbm_counters.md.
+MEASURED_TRAFFIC = {
+    "grid3d_128x128x128": ("ea59fc784c683595", 7813973480),
+}
+KERNEL_SOURCES = ("paper_1610_08128_amd/csrc/rcm_bfs.hip",
+                  "paper_1610_08128_amd/csrc/rcm_common.hpp")
+
+
+def kernel_sources_hash() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str):
+    entry = MEASURED_TRAFFIC.get(workload)
+    if entry is None or entry[0] != kernel_sources_hash():
+        return None
+    return entry[1]
 
 
 def order_kernel_bytes(n: int, m: int, k_pp: int) -> int:
@@ -160,7 +183,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 5),
-            "traffic": MEASURED_TRAFFIC_BYTES,
+            "traffic": measured_traffic(args.workload),
             "algorithmic_bytes_per_launch": kbytes,
             "avg_launch_ms": round(kavg_s * 1000.0, 4),
             "whole_call_hbm_frac": round(
