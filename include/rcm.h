@@ -98,11 +98,16 @@ typedef struct {
                             team; 0 = auto (512); 256 or 512                   */
   int32_t small_cutoff;  /* components with at most this many vertices are
                             ordered by a single work-group each, many in
-                            parallel; 0 = auto                                 */
+                            parallel, largest first; larger ones by teams of
+                            team_size work-groups; 0 = auto (262144)          */
   int32_t narrow_cutoff; /* levels narrower than this are expanded by one
                             work-group of the team without grid-wide barriers;
                             0 = auto (256), -1 = never                         */
-  int32_t reserved[9];
+  int32_t small_threads; /* threads per work-group of the single-work-group
+                            teams; 0 = auto (256); 256 or 512                  */
+  int32_t max_teams;     /* most large-component teams run at once; 0 = auto
+                            (8), at most 8                                     */
+  int32_t reserved[7];
 } rcm_options;
 
 /* Human-readable name of a status code (static string). */

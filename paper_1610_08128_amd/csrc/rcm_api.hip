@@ -36,8 +36,9 @@ struct Opts {
   int team_size = 32;
   int threads = 512;
   int small_threads = 256;
-  int small_cutoff = 1 << 14;
+  int small_cutoff = 1 << 18;
   int narrow_cutoff = 256;
+  int max_teams = 8;
 };
 
 bool parse_options(const rcm_options* o, Opts* out) {
@@ -51,6 +52,9 @@ bool parse_options(const rcm_options* o, Opts* out) {
       return false;
     if (o->small_cutoff < 0) return false;
     if (o->narrow_cutoff < -1) return false;
+    if (o->small_threads != 0 && o->small_threads != 256 && o->small_threads != 512)
+      return false;
+    if (o->max_teams < 0 || o->max_teams > kMaxConcurrentTeams) return false;
     r.pp_variant = o->pp_variant;
     r.reverse_mode = o->reverse_mode;
     r.check_full = o->check_full;
@@ -58,6 +62,8 @@ bool parse_options(const rcm_options* o, Opts* out) {
     if (o->block_threads) r.threads = o->block_threads;
     if (o->small_cutoff) r.small_cutoff = o->small_cutoff;
     if (o->narrow_cutoff) r.narrow_cutoff = o->narrow_cutoff;
+    if (o->small_threads) r.small_threads = o->small_threads;
+    if (o->max_teams) r.max_teams = o->max_teams;
   }
   *out = r;
   return true;
@@ -67,7 +73,7 @@ bool parse_options(const rcm_options* o, Opts* out) {
 struct Layout {
   size_t vinfo, beta, parent, flags, pos, csize, seeds, visit, claim, qi, tmp, iperm;
   size_t sizes, offs, results, t_single, t_small, t_big, scan_blk;
-  size_t seg_off, comp_seg_off, segstats, gctl, teams, small_ctl, misc;
+  size_t seg_off, comp_seg_off, segstats, gctl, teams, small_ctl, misc, sched;
   size_t rowptr_g, colidx_g;
   size_t total;
 };
@@ -104,9 +110,10 @@ Layout make_layout(int64_t n, int64_t nnz, int64_t nseg, bool batched, int teams
   L.comp_seg_off = take(4 * static_cast<size_t>(nseg + 1));
   L.segstats = take(sizeof(SegStats) * static_cast<size_t>(nseg));
   L.gctl = take(sizeof(GlobalCtl));
-  L.teams = take(sizeof(TeamCtl) * kMaxTeam);
+  L.teams = take(sizeof(TeamCtl) * kMaxConcurrentTeams);
   L.small_ctl = take(sizeof(TeamCtl) * static_cast<size_t>(teams_small));
   L.misc = take(256);
+  L.sched = take(128 * sizeof(int32_t));
   if (batched) {
     L.rowptr_g = take(4 * (N + 1));
     L.colidx_g = take(4 * static_cast<size_t>(nnz));
@@ -241,6 +248,7 @@ rcm_status run(const Graph& gin, const int32_t* seg_off_host, const Opts& opt, c
   TeamCtl* teams = reinterpret_cast<TeamCtl*>(ws + L.teams);
   TeamCtl* small_ctl = reinterpret_cast<TeamCtl*>(ws + L.small_ctl);
   int32_t* misc = reinterpret_cast<int32_t*>(ws + L.misc);  // [0..2] errors, [4] ncomp, [8..10] counts
+  int32_t* sched = reinterpret_cast<int32_t*>(ws + L.sched);
 
   HIP_TRY(hipMemcpyAsync(seg_off, seg_off_host, sizeof(int32_t) * (g.nseg + 1),
                          hipMemcpyHostToDevice, s));
@@ -289,9 +297,12 @@ rcm_status run(const Graph& gin, const int32_t* seg_off_host, const Opts& opt, c
     P.ntasks = count;
     P.teams = teams;
     P.team_size = opt.team_size;
-    HIP_TRY(hipMemsetAsync(teams, 0, sizeof(TeamCtl), s));
+    // at most max_teams teams, and only as many as fit on the device at once
+    const int resident = max_team_blocks(opt.threads) / opt.team_size;
+    const int nteams = std::max(1, std::min({count, opt.max_teams, resident}));
+    HIP_TRY(hipMemsetAsync(teams, 0, sizeof(TeamCtl) * nteams, s));
     if (timed) timer.kmark(1, true);
-    HIP_TRY(launch_order_big(P, opt.threads, s));
+    HIP_TRY(launch_order_big(P, opt.threads, nteams, s));
     if (timed) timer.kmark(1, false);
     if (timed && timer.on) {
       HIP_TRY(hipMemcpyAsync(timer.clk, teams[0].clk, sizeof(timer.clk), hipMemcpyDeviceToHost,
@@ -341,7 +352,7 @@ rcm_status run(const Graph& gin, const int32_t* seg_off_host, const Opts& opt, c
     ncomp += nrest;
     HIP_TRY(launch_tasks(g, nrest, seeds_rest, csize, opt.small_cutoff, opt.reverse_mode,
                          head_size, head ? 1 : 0, t_single, t_small, t_big, misc + 8, sizes, offs,
-                         scan_blk, results, s));
+                         scan_blk, results, sched, s));
     st = read_ints(h, misc + 8, 4, s);
     if (st != RCM_OK) return st;
     // every vertex must belong to exactly one component (only an asymmetric

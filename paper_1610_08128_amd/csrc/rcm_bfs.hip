@@ -7,8 +7,9 @@
 // component at a time and walks its levels; between levels the team meets at
 // a barrier (a monotone arrival counter with device-scope release/acquire
 // fences; for W = 1 the barrier is just __syncthreads).  Two launch shapes:
-//   - large components: one team of W co-resident work-groups (cooperative
-//     launch), default W = 8 so the team spans the 8 XCDs once;
+//   - large components: teams of W co-resident work-groups (cooperative
+//     launch; default W = 32, four work-groups on each of the 8 XCDs), one
+//     team per large component at a time;
 //   - small components: many single-work-group teams pulling components from
 //     an atomic queue.
 // Narrow levels (fewer vertices than the narrow cutoff) are expanded by the
@@ -1099,13 +1100,15 @@ hipError_t launch_order_small(const BfsParams& p, int32_t nblocks, int32_t threa
   return hipGetLastError();
 }
 
-hipError_t launch_order_big(const BfsParams& p, int32_t threads, hipStream_t s) {
+// nteams teams of p.team_size co-resident work-groups; team i takes tasks
+// i, i + nteams, ... of the (largest-first) list.
+hipError_t launch_order_big(const BfsParams& p, int32_t threads, int32_t nteams, hipStream_t s) {
   if (p.ntasks <= 0) return hipSuccess;
   BfsParams q = p;
   q.use_queue = 0;
   void* args[] = {&q};
-  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_order), dim3(q.team_size),
-                                    dim3(threads), args, 0, s);
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_order),
+                                    dim3(q.team_size * nteams), dim3(threads), args, 0, s);
 }
 
 }  // namespace rcm

@@ -11,7 +11,8 @@ namespace rcm {
 
 constexpr uint32_t kUnclaimed = 0xFFFFFFFFu;
 constexpr uint64_t kMaxKey = ~0ull;
-constexpr int kMaxTeam = 64;
+constexpr int kMaxTeam = 64;             // work-groups per team
+constexpr int kMaxConcurrentTeams = 8;   // large-component teams per launch
 // A device-side wait gives up (and flags RCM_ERR_ABORTED) after 30 s of the
 // 100 MHz constant-rate clock read by wall_clock64(): far beyond any
 // legitimate wait, short enough to end a broken run cleanly.
@@ -225,7 +226,8 @@ hipError_t launch_tasks(const Graph& g, int32_t ncomp, const int32_t* seeds, con
                         int32_t small_cutoff, int32_t reverse_mode, int32_t offset_base,
                         int32_t index_base, CompTask* tasks_single, CompTask* tasks_small,
                         CompTask* tasks_big, int32_t* counts, int32_t* sizes, int32_t* offs,
-                        int32_t* scan_blk, CompResult* results, hipStream_t s);
+                        int32_t* scan_blk, CompResult* results, int32_t* sched,
+                        hipStream_t s);
 hipError_t launch_singletons(const CompTask* tasks, int32_t count, int32_t* perm, int32_t* iperm,
                              CompResult* results, hipStream_t s);
 hipError_t launch_bw_after(const Graph& g, const int32_t* perm, const int32_t* iperm,
@@ -261,7 +263,7 @@ struct BfsParams {
 
 hipError_t launch_order_small(const BfsParams& p, int32_t nblocks, int32_t threads,
                               hipStream_t s);
-hipError_t launch_order_big(const BfsParams& p, int32_t threads, hipStream_t s);
+hipError_t launch_order_big(const BfsParams& p, int32_t threads, int32_t nteams, hipStream_t s);
 int max_team_blocks(int32_t threads);
 
 }  // namespace rcm

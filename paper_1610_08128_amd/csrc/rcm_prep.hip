@@ -312,12 +312,27 @@ __device__ __forceinline__ void append_task(CompTask* list, int32_t* counter, co
   list[at] = t;
 }
 
+// Size class of a component for largest-first ordering: floor(log2(size)).
+__device__ __forceinline__ int size_class(int32_t size) { return 31 - __clz(size); }
+
+// Task lists.  Pass 0 writes the per-component results, appends the
+// singletons and counts the other components per (list, size class); pass 1
+// places them at cursors that k_class_scan laid out in decreasing size-class
+// order, so that teams pulling tasks in list order take the largest
+// components first (longest-processing-time-first scheduling).
+// sched[0..63]: counts of (list l, class c) at l * 32 + c; sched[64..127]:
+// the cursors.
 __global__ void k_build_tasks(int32_t ncomp, const int32_t* __restrict__ seeds,
                               const int32_t* __restrict__ sizes, const int32_t* __restrict__ offs,
                               const int32_t* __restrict__ seg_off, int nseg, int32_t small_cutoff,
                               int32_t reverse_mode, int32_t offset_base, int32_t index_base,
                               CompTask* tasks_single, CompTask* tasks_small, CompTask* tasks_big,
-                              int32_t* counts, CompResult* results) {
+                              int32_t* counts, CompResult* results, int32_t* sched, int pass) {
+  __shared__ int32_t hist[64];
+  if (pass == 0) {
+    for (int i = threadIdx.x; i < 64; i += blockDim.x) hist[i] = 0;
+    __syncthreads();
+  }
   for (int32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < ncomp; c += gridDim.x * blockDim.x) {
     CompTask t;
     t.seed = seeds[c];
@@ -329,21 +344,45 @@ __global__ void k_build_tasks(int32_t ncomp, const int32_t* __restrict__ seeds,
     // position anchor - t after reversal
     t.anchor = reverse_mode == 0 ? t.offset + t.size - 1
                                  : seg_off[s] + seg_off[s + 1] - 1 - t.offset;
-    CompResult r;
-    r.root = t.seed;
-    r.nbfs = 0;
-    r.levels = 0;
-    r.seg = s;
-    r.size = t.size;
-    r.pad = 0;
-    r.m = 0;
-    results[t.index] = r;
-    if (t.size == 1)
-      append_task(tasks_single, counts + 0, t);
-    else if (t.size <= small_cutoff)
-      append_task(tasks_small, counts + 1, t);
-    else
-      append_task(tasks_big, counts + 2, t);
+    const int list = t.size <= small_cutoff ? 0 : 1;
+    const int slot = list * 32 + size_class(t.size);
+    if (pass == 0) {
+      CompResult r;
+      r.root = t.seed;
+      r.nbfs = 0;
+      r.levels = 0;
+      r.seg = s;
+      r.size = t.size;
+      r.pad = 0;
+      r.m = 0;
+      results[t.index] = r;
+      if (t.size == 1)
+        append_task(tasks_single, counts + 0, t);
+      else
+        atomicAdd(&hist[slot], 1);
+    } else if (t.size > 1) {
+      const int32_t at = atomicAdd(&sched[64 + slot], 1);
+      (list == 0 ? tasks_small : tasks_big)[at] = t;
+    }
+  }
+  if (pass == 0) {
+    __syncthreads();
+    for (int i = threadIdx.x; i < 64; i += blockDim.x)
+      if (hist[i] != 0) atomicAdd(&sched[i], hist[i]);
+  }
+}
+
+// One thread: cursors of each list in decreasing size class; list totals
+// into counts[1] (small) and counts[2] (big).
+__global__ void k_class_scan(int32_t* sched, int32_t* counts) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  for (int l = 0; l < 2; ++l) {
+    int32_t run = 0;
+    for (int c = 31; c >= 0; --c) {
+      sched[64 + l * 32 + c] = run;
+      run += sched[l * 32 + c];
+    }
+    counts[1 + l] = run;
   }
 }
 
@@ -489,16 +528,22 @@ hipError_t launch_tasks(const Graph& g, int32_t ncomp, const int32_t* seeds, con
                         int32_t small_cutoff, int32_t reverse_mode, int32_t offset_base,
                         int32_t index_base, CompTask* tasks_single, CompTask* tasks_small,
                         CompTask* tasks_big, int32_t* counts, int32_t* sizes, int32_t* offs,
-                        int32_t* scan_blk, CompResult* results, hipStream_t s) {
+                        int32_t* scan_blk, CompResult* results, int32_t* sched, hipStream_t s) {
   const int nb = grid_for(ncomp, kThreads);
   k_gather_sizes<<<nb, kThreads, 0, s>>>(ncomp, seeds, csize, sizes);
   hipError_t e = launch_exclusive_scan(sizes, offs, ncomp, scan_blk, counts + 3, s);
   if (e != hipSuccess) return e;
   e = hipMemsetAsync(counts, 0, 3 * sizeof(int32_t), s);
   if (e != hipSuccess) return e;
-  k_build_tasks<<<nb, kThreads, 0, s>>>(ncomp, seeds, sizes, offs, g.seg_off, g.nseg,
-                                        small_cutoff, reverse_mode, offset_base, index_base,
-                                        tasks_single, tasks_small, tasks_big, counts, results);
+  e = hipMemsetAsync(sched, 0, 128 * sizeof(int32_t), s);
+  if (e != hipSuccess) return e;
+  for (int pass = 0; pass < 2; ++pass) {
+    k_build_tasks<<<nb, kThreads, 0, s>>>(ncomp, seeds, sizes, offs, g.seg_off, g.nseg,
+                                          small_cutoff, reverse_mode, offset_base, index_base,
+                                          tasks_single, tasks_small, tasks_big, counts, results,
+                                          sched, pass);
+    if (pass == 0) k_class_scan<<<1, 64, 0, s>>>(sched, counts);
+  }
   return hipGetLastError();
 }
 

@@ -72,7 +72,9 @@ class Options(ctypes.Structure):
         ("block_threads", ctypes.c_int32),
         ("small_cutoff", ctypes.c_int32),
         ("narrow_cutoff", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 9),
+        ("small_threads", ctypes.c_int32),
+        ("max_teams", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 7),
     ]
 
 
@@ -133,7 +135,8 @@ def status_string(status: int) -> str:
 
 
 def make_options(*, pp_variant=0, reverse_mode=0, check_full=False, team_size=0,
-                 block_threads=0, small_cutoff=0, narrow_cutoff=0) -> Options:
+                 block_threads=0, small_cutoff=0, narrow_cutoff=0, small_threads=0,
+                 max_teams=0) -> Options:
     o = Options()
     o.pp_variant = int(pp_variant)
     o.reverse_mode = int(reverse_mode)
@@ -142,6 +145,8 @@ def make_options(*, pp_variant=0, reverse_mode=0, check_full=False, team_size=0,
     o.block_threads = int(block_threads)
     o.small_cutoff = int(small_cutoff)
     o.narrow_cutoff = int(narrow_cutoff)
+    o.small_threads = int(small_threads)
+    o.max_teams = int(max_teams)
     return o
 
 

@@ -236,6 +236,17 @@ def test_batched_small():
     _check_batch(graphs, small_cutoff=1, team_size=4)
 
 
+def test_batched_concurrent_teams():
+    # several large-component teams in one cooperative launch, tasks taken
+    # largest first; single-work-group teams with 512 threads
+    graphs = [I.grid2d(20 + 3 * i, 30, seed=300 + i) for i in range(11)]
+    graphs += [I.rgg_patches(3000, seed=77), I.path(2)]
+    _check_batch(graphs, small_cutoff=500, team_size=4, max_teams=8)
+    _check_batch(graphs, small_cutoff=500, team_size=32, max_teams=3, narrow_cutoff=16)
+    _check_batch(graphs, small_threads=512)
+    _check_batch(graphs, small_cutoff=1 << 30, small_threads=512)
+
+
 def test_batched_512():
     graphs = I.batch_graphs(512, seed=4)
     _check_batch(graphs)
