@@ -18,13 +18,14 @@ INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(PKG, "librcm.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["rcm_prep.hip", "rcm_bfs.hip", "rcm_api.hip"]
+SOURCES = ["rcm_prep.hip", "rcm_bfs.hip", "rcm_api.hip", "rcm_server.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",
     "-O3",
     "-std=c++17",
     "-fPIC",
+    "-pthread",
     "-Wall",
     # compile packed fp32 arithmetic out of device code entirely
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -59,7 +60,7 @@ def build_library(verbose: bool = False) -> str:
     with concurrent.futures.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
         objs = list(ex.map(compile_one, SOURCES))
     tmp = OUT + ".tmp"
-    cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
+    cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", "-o", tmp, *objs]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"link failed:\n{res.stdout}\n{res.stderr}")

@@ -59,15 +59,20 @@ __global__ void k_validate_scan(int32_t n, int32_t nnz, const int32_t* __restric
 }
 
 // For graphs made of several segments (batched calls), an entry must stay
-// inside its row's segment.
-__global__ void k_check_segments(int32_t n, const int32_t* __restrict__ rowptr,
+// inside its row's segment.  Rows whose bounds are invalid are left to
+// k_validate_scan's error (this kernel runs before the host reads it, so it
+// must not follow them).
+__global__ void k_check_segments(int32_t n, int32_t nnz, const int32_t* __restrict__ rowptr,
                                  const int32_t* __restrict__ colidx,
                                  const int32_t* __restrict__ seg_off, int nseg,
                                  int32_t* __restrict__ err) {
   for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     const int s = find_segment(seg_off, nseg, i);
     const int32_t lo = seg_off[s], hi = seg_off[s + 1];
-    for (int32_t k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+    const int32_t a = rowptr[i];
+    const int32_t b = rowptr[i + 1];
+    if (a < 0 || b < a || b > nnz) continue;
+    for (int32_t k = a; k < b; ++k) {
       const int32_t c = colidx[k];
       if (c < lo || c >= hi) { atomicOr(err, 1); break; }
     }
@@ -490,7 +495,7 @@ hipError_t launch_validate_scan(const Graph& g, int4* vinfo, int32_t* beta, SegS
   k_validate_scan<<<grid_for(g.n, kThreads), kThreads, 0, s>>>(g.n, g.nnz, g.rowptr, g.colidx,
                                                                 vinfo, beta, err);
   if (g.nseg > 1)
-    k_check_segments<<<grid_for(g.n, kThreads), kThreads, 0, s>>>(g.n, g.rowptr, g.colidx,
+    k_check_segments<<<grid_for(g.n, kThreads), kThreads, 0, s>>>(g.n, g.nnz, g.rowptr, g.colidx,
                                                                    g.seg_off, g.nseg, err);
   constexpr int32_t chunk = 8192;
   const int nb = (g.n + chunk - 1) / chunk;

@@ -12,10 +12,11 @@ from paper_1610_08128_amd import rcm
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "rcm.h")
+SERVER_HEADER = os.path.join(ROOT, "include", "rcm_server.h")
 
 
-def _declared_functions():
-    text = open(HEADER).read()
+def _declared_functions(path=HEADER):
+    text = open(path).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     names = re.findall(r"\b(rcm_[a-z_]+)\s*\(", text)
     return sorted(set(names))
@@ -25,14 +26,38 @@ def test_header_declares_the_documented_entry_points():
     assert _declared_functions() == sorted(rcm.EXPORTED)
 
 
+def test_server_header_declares_the_documented_entry_points():
+    from paper_1610_08128_amd import serve
+
+    assert _declared_functions(SERVER_HEADER) == sorted(serve.SERVER_EXPORTED)
+
+
 def test_library_exports_every_declared_symbol():
     L = rcm.lib()
-    for name in _declared_functions():
+    declared = _declared_functions() + _declared_functions(SERVER_HEADER)
+    for name in declared:
         assert hasattr(L, name), name
     out = subprocess.run(["nm", "-D", "--defined-only", rcm.LIB_PATH], capture_output=True,
                          text=True, check=True).stdout
     exported = set(re.findall(r" T (rcm_[a-z_]+)", out))
-    assert set(_declared_functions()) <= exported
+    assert set(declared) <= exported
+
+
+def test_server_config_checks_need_no_gpu():
+    from paper_1610_08128_amd import serve
+
+    with pytest.raises(rcm.RcmError) as e:
+        serve.Server(executors=9)
+    assert e.value.status == rcm.ERR_INVALID_ARGUMENT
+    with pytest.raises(rcm.RcmError) as e:
+        serve.Server(max_batch=-1)
+    assert e.value.status == rcm.ERR_INVALID_ARGUMENT
+    with pytest.raises(rcm.RcmError) as e:
+        serve.Server(pp_variant=3)
+    assert e.value.status == rcm.ERR_INVALID_ARGUMENT
+    # footprint grows with the request
+    assert 0 == serve.request_bytes(0, 0)
+    assert 0 < serve.request_bytes(100, 500) < serve.request_bytes(1000, 5000)
 
 
 def test_status_strings():
