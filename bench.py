@@ -103,12 +103,267 @@ def cpu_baseline(g, budget_s: float):
     }, r
 
 
+def _pool_oracle(graphs, budget_s: float):
+    """The oracle over a list of graphs on a thread pool (the oracle's C
+    calls release the interpreter lock), largest first, until the list or
+    the time budget is exhausted.  Returns (orderings/s, threads, done)."""
+    import concurrent.futures
+    import oracle
+
+    threads = max(1, min(16, len(os.sched_getaffinity(0))))
+    order = sorted(range(len(graphs)), key=lambda i: -graphs[i].nnz)
+    t0 = time.perf_counter()
+    done = 0
+
+    def one(i):
+        if time.perf_counter() - t0 > budget_s:
+            return 0
+        g = graphs[i]
+        r = oracle.rcm(g.n, g.rowptr, g.colidx)
+        assert r.status == oracle.OK
+        return 1
+
+    with concurrent.futures.ThreadPoolExecutor(max_workers=threads) as ex:
+        done = sum(ex.map(one, order))
+    dt = time.perf_counter() - t0
+    return done / dt, threads, done, dt
+
+
+def batch_bytes(graphs, stats) -> int:
+    """Algorithmic bytes of the ordering kernel over a batch: per graph,
+    8 bytes per traversed entry plus, per vertex, 20 bytes for each
+    unlabelled pass (the graph's mean pass count per component) and 60 for
+    the labelled pass and the reversal."""
+    total = 0
+    for g, st in zip(graphs, stats):
+        comps = max(st["num_components"], 1)
+        total += 8 * st["edges_traversed"] + int((20 * st["num_bfs"] / comps + 60) * g.n)
+    return total
+
+
+def run_batched(args):
+    import numpy as np
+    import torch
+
+    from paper_1610_08128_amd import inputs, rcm
+
+    graphs = inputs.batch_graphs(512, seed=4)
+    vo, no, rp, ci = inputs.concat_batch(graphs)
+    dev = torch.device("cuda", 0)
+    rpd = torch.from_numpy(rp).to(dev)
+    cid = torch.from_numpy(ci).to(dev)
+    G = len(graphs)
+    ws = torch.empty(rcm.batched_workspace_bytes(G, int(vo[-1]), int(no[-1])), dtype=torch.uint8,
+                     device=dev)
+    stream = torch.cuda.Stream(device=dev)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        for _ in range(args.warmup):
+            perm, stats = rcm.order_batched(vo, no, rpd, cid, workspace=ws, stream=stream)
+        torch.cuda.synchronize()
+        kern_ms = []
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            perm, stats = rcm.order_batched(vo, no, rpd, cid, workspace=ws, stream=stream)
+            tm = rcm.last_timings()
+            kern_ms.append(tm["small_kernel_ms"] + tm["team_kernel_ms"])
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+    phases = rcm.last_timings()
+    edges = sum(st["edges_traversed"] for st in stats)
+    kbytes = batch_bytes(graphs, stats)
+    kavg = float(np.mean(kern_ms)) / 1000.0
+    check = None
+    cpu = None
+    if args.cpu_budget > 0:
+        value, threads, done, cdt = _pool_oracle(graphs, args.cpu_budget)
+        cpu = {"value": value, "unit": "orderings/s", "cores": threads, "kind": "oracle",
+               "sample": f"{done} of the 512 graphs, largest first, one oracle call per graph "
+                         f"on a {threads}-thread pool, {cdt:.1f} s"}
+    if not args.no_check:
+        import oracle
+
+        pc = perm.cpu().numpy()
+        sample = list(range(0, G, 16))
+        check = all(np.array_equal(pc[vo[i]:vo[i + 1]],
+                                   oracle.rcm(graphs[i].n, graphs[i].rowptr,
+                                              graphs[i].colidx).perm) for i in sample)
+    out = {
+        "metric": "RCM orderings/s",
+        "value": round(G * args.steps / dt, 2),
+        "unit": "orderings/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(dt * 1000.0 / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": "batch_512: 512 graphs in one call, sizes log-uniform in "
+                               "[1e3, 2e5] vertices, round-robin 2D grid / 3D grid / random "
+                               "geometric patches (seed 4)",
+                   "graphs": G, "n": int(vo[-1]), "nnz": int(no[-1])},
+        "teps": round(edges * args.steps / dt, 1),
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_order (single-work-group teams, largest component first)",
+            "achieved": round(kbytes / kavg / 1e9, 2),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(kbytes / kavg / 1e9 / HBM_PEAK_GBS, 5),
+            "traffic": None,
+            "algorithmic_bytes_per_launch": kbytes,
+            "avg_launch_ms": round(kavg * 1000.0, 4),
+        },
+        "phases_ms_last_step": {k: (round(v, 4) if isinstance(v, float) else v)
+                                for k, v in phases.items()},
+        "cpu_baseline": cpu,
+        "matches_oracle_sampled": check,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def _percentile(xs, q):
+    import numpy as np
+
+    return float(np.percentile(np.asarray(xs), q)) if len(xs) else None
+
+
+def run_serve(args):
+    """Serving sweep: X1 = saturated throughput of one call per request
+    (first come first served, one stream, host CSR copied in per request);
+    then Poisson streams at fractions of X1 through the serving engine."""
+    import threading
+
+    import numpy as np
+    import torch
+
+    from paper_1610_08128_amd import inputs, rcm
+    from paper_1610_08128_amd.serve import Server
+
+    desc = inputs.request_stream(args.serve_pool, 1.0)
+    t0 = time.perf_counter()
+    pool = [inputs.request_graph(kind, n_t, seed) for (_, kind, n_t, seed) in desc]
+    gen_s = time.perf_counter() - t0
+    dev = torch.device("cuda", 0)
+    torch.cuda.synchronize()
+
+    # X1: one call per request, inputs copied from the host each time
+    def one_call(g):
+        rp = torch.from_numpy(g.rowptr).to(dev)
+        ci = torch.from_numpy(g.colidx).to(dev)
+        perm, _ = rcm.order(rp, ci)
+        return perm.cpu().numpy()
+
+    for g in pool[:4]:
+        one_call(g)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    lat1 = []
+    for g in pool:
+        a = time.perf_counter()
+        one_call(g)
+        lat1.append(time.perf_counter() - a)
+    x1 = len(pool) / (time.perf_counter() - t)
+
+    budget = 8 << 30
+    rows = []
+    for frac in (0.5, 0.75, 1.0, 1.5, 2.0, 3.0):
+        rate = frac * x1
+        arrivals = inputs.request_stream(args.serve_requests, rate, seed_sizes=5, seed_arrivals=6)
+        with Server(mem_budget_bytes=budget, executors=4, max_batch=64) as srv:
+            tickets = [None] * len(arrivals)
+            start = time.perf_counter()
+
+            def producer():
+                for i, (at, *_rest) in enumerate(arrivals):
+                    delay = at - (time.perf_counter() - start)
+                    if delay > 0:
+                        time.sleep(delay)
+                    g = pool[i % len(pool)]
+                    tickets[i] = srv.submit(g.rowptr, g.colidx)
+
+            th = threading.Thread(target=producer)
+            th.start()
+            th.join()
+            lat, done_at, first = [], [], None
+            for i, tk in enumerate(tickets):
+                perm, info = srv.wait(tk)
+                assert info["status"] == 0, info
+                lat.append(info["latency_s"])
+                done_at.append(info["t_done"])
+                first = info["t_submit"] if first is None else min(first, info["t_submit"])
+            c = srv.counters()
+        span = max(done_at) - first
+        rows.append({"offered_per_s": round(rate, 2), "served_per_s": round(len(lat) / span, 2),
+                     "p50_ms": round(_percentile(lat, 50) * 1e3, 2),
+                     "p99_ms": round(_percentile(lat, 99) * 1e3, 2),
+                     "batches": c["batches"], "max_batch": c["max_batch_seen"]})
+        print(f"# rate {rate:.1f}/s: {rows[-1]}", file=sys.stderr, flush=True)
+    best = max(rows, key=lambda r: r["served_per_s"])
+    cpu = None
+    if args.cpu_budget > 0:
+        value, threads, done, cdt = _pool_oracle(pool, args.cpu_budget)
+        cpu = {"value": value, "unit": "orderings/s", "cores": threads, "kind": "oracle",
+               "sample": f"{done} of the {len(pool)} pooled requests, largest first, one oracle "
+                         f"call per request on a {threads}-thread pool, {cdt:.1f} s"}
+    if not args.no_check:
+        import oracle
+
+        srv_check = None
+        with Server(mem_budget_bytes=budget) as srv:
+            ts = [srv.submit(g.rowptr, g.colidx) for g in pool[:8]]
+            srv_check = all(np.array_equal(srv.wait(t)[0], oracle.rcm(g.n, g.rowptr,
+                                                                      g.colidx).perm)
+                            for g, t in zip(pool[:8], ts))
+    else:
+        srv_check = None
+    out = {
+        "metric": "served RCM orderings/s",
+        "value": best["served_per_s"],
+        "unit": "orderings/s",
+        "n_gpus": 1,
+        "steps": len(rows) * args.serve_requests,
+        "warmup": 4,
+        "ms_per_step": round(1000.0 / best["served_per_s"], 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": f"request stream: Poisson arrivals (seed 6), nnz log-uniform in "
+                               f"[1e4, 2e7] (seed 5), kinds uniform over 2D grid / 3D grid / "
+                               f"random geometric patches; {args.serve_pool} distinct requests "
+                               f"reused cyclically, {args.serve_requests} per rate",
+                   "pool_nnz_mean": int(np.mean([g.nnz for g in pool])),
+                   "mem_budget_bytes": budget, "executors": 4, "max_batch": 64},
+        "one_call_per_request": {"orderings_per_s": round(x1, 2),
+                                 "p50_ms": round(_percentile(lat1, 50) * 1e3, 2),
+                                 "p99_ms": round(_percentile(lat1, 99) * 1e3, 2)},
+        "sweep": rows,
+        "best": best,
+        "generation_s": round(gen_s, 1),
+        "cpu_baseline": cpu,
+        "matches_oracle_sampled": srv_check,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--mode", default="single", choices=["single", "batched", "serve"],
+                    help="single: one graph per call (default); batched: the 512-graph batch "
+                         "in one call; serve: Poisson request stream through the serving engine")
     ap.add_argument("--workload", default="grid3d_128x128x128", choices=sorted(WORKLOADS))
+    ap.add_argument("--serve-requests", type=int, default=120,
+                    help="requests per arrival rate in --mode serve")
+    ap.add_argument("--serve-pool", type=int, default=32,
+                    help="distinct request graphs generated for --mode serve (reused cyclically)")
     ap.add_argument("--team-size", type=int, default=0)
     ap.add_argument("--block-threads", type=int, default=0)
     ap.add_argument("--cpu-budget", type=float, default=12.0,
@@ -120,11 +375,15 @@ def main():
                          "command has a kernel of known traffic to scale by")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build runs on a single MI355X "
-              "(no multi-GPU path); use --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the library orders on a single MI355X "
+              "and has no multi-GPU path; use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     os.environ["RCM_TIMING"] = "1"
+    if args.mode == "batched":
+        return run_batched(args)
+    if args.mode == "serve":
+        return run_serve(args)
     import numpy as np
     import torch
 
