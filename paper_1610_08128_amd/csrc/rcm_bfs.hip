@@ -591,11 +591,24 @@ __device__ __forceinline__ void claim_row(const BfsParams& P, int32_t v, int4 in
   }
 }
 
+// A placed child whose claims the work-group issues after placement: it goes
+// to the work-group's LDS list (index = its label - list_base) when it fits,
+// else it claims its neighbours at once.
+__device__ __forceinline__ void defer_claims(const BfsParams& P, Shared& S, int32_t v, int4 inf,
+                                             int32_t at, int32_t list_base) {
+  const int32_t i = at - list_base;
+  if (i >= 0 && i < kStageCap) {
+    reinterpret_cast<int4*>(S.u.srec)[i] = make_int4(v, inf.x, inf.y, at);
+  } else {
+    claim_row(P, v, inf, static_cast<uint32_t>(at));
+  }
+}
+
 // Children of parent p (vertex u, row [a, b)) ranked by (degree, id) among
 // the siblings, for rows longer than a register batch.
-__device__ __forceinline__ void place_long_row(const BfsParams& P, int32_t p, int32_t u,
+__device__ __forceinline__ void place_long_row(const BfsParams& P, Shared& S, int32_t p, int32_t u,
                                                int32_t a, int32_t b, int32_t base, int32_t end,
-                                               long long& my_m) {
+                                               int32_t list_base, long long& my_m) {
   const uint32_t pl = static_cast<uint32_t>(p);
   for (int32_t k0 = a; k0 < b; k0 += kRB) {
     int32_t nb[kRB];
@@ -625,7 +638,7 @@ __device__ __forceinline__ void place_long_row(const BfsParams& P, int32_t p, in
       const int32_t at = base + rank;
       if (at < end) P.qi[at] = record(nb[j], inf);
       my_m += inf.z;
-      claim_row(P, nb[j], inf, static_cast<uint32_t>(at));
+      defer_claims(P, S, nb[j], inf, at, list_base);
     }
   }
 }
@@ -868,6 +881,11 @@ __device__ __forceinline__ void global_label_level(const BfsParams& P, Team& t, 
     return;
   }
   int32_t run = cur_e + prefix;
+  // this work-group's children are the labels [run, run + S.wsum[wid]):
+  // their records are collected in LDS and their claims issued after
+  // placement, one child per thread
+  const int32_t list_base = run;
+  const int32_t list_len = S.wsum[wid] < kStageCap ? S.wsum[wid] : kStageCap;
   for (int32_t r0 = lo; r0 < hi; r0 += B) {
     const int32_t p = r0 + threadIdx.x;
     const int c = p < hi ? (one_round ? c_mine : P.tmp[p]) : 0;
@@ -896,13 +914,19 @@ __device__ __forceinline__ void global_label_level(const BfsParams& P, Team& t, 
         }
 #pragma unroll
         for (int j = 0; j < kRB; ++j)
-          if (cmask >> j & 1u) claim_row(P, cnb[j], cinf[j], static_cast<uint32_t>(at[j]));
+          if (cmask >> j & 1u) defer_claims(P, S, cnb[j], cinf[j], at[j], list_base);
       } else {
         const int4 e = P.qi[p];
-        place_long_row(P, p, e.x, e.y, e.z, base, end, my_m);
+        place_long_row(P, S, p, e.x, e.y, e.z, base, end, list_base, my_m);
       }
     }
     run += rtot;
+  }
+  // (A) for the next level: every listed child claims its neighbours
+  __syncthreads();
+  for (int32_t i = threadIdx.x; i < list_len; i += B) {
+    const int4 c = reinterpret_cast<const int4*>(S.u.srec)[i];
+    claim_row(P, c.x, make_int4(c.y, c.z, 0, 0), static_cast<uint32_t>(c.w));
   }
   team_barrier(t, S, solo);
   if (t.aborted) return;
