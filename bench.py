@@ -9,7 +9,10 @@ HBM, through the library's C ABI.  The default workload is the 128^3 3D
 relabelled with seed 2.
 
 Prints one JSON line.  Besides the throughput it reports:
-  - teps: edges traversed per second (the entries scanned by every BFS pass);
+  - teps: edges traversed per second, counting every BFS pass of the method
+    (Algorithm 2's searches and Algorithm 3's labelled BFS; the kernel runs
+    the last search as the labelled BFS, so it scans one pass fewer than
+    this count when the search takes three or more passes);
   - roofline: the dominant kernel (the persistent ordering kernel), its
     algorithmic bytes per launch over its average duration measured with HIP
     events recorded by the library on the launch stream (RCM_TIMING=1);
@@ -65,6 +68,14 @@ def measured_traffic(workload: str):
     return entry[1]
 
 
+def unlabelled_passes(k_pp: int) -> int:
+    """Level structures the kernel computes without labels: from the third
+    search on, a search pass is run as the labelled BFS itself (both start
+    at the same root), so a search of k_pp >= 3 passes costs k_pp - 1
+    unlabelled passes plus the labelled one."""
+    return k_pp - 1 if k_pp >= 3 else k_pp
+
+
 def order_kernel_bytes(n: int, m: int, k_pp: int) -> int:
     """Algorithmic HBM bytes of one launch of the ordering kernel for a
     component of n vertices and m directed off-diagonal entries:
@@ -72,7 +83,7 @@ def order_kernel_bytes(n: int, m: int, k_pp: int) -> int:
         gather 4m, visited write 4n, frontier write + read 8n);
       the labelled BFS: 8m + 48n (adds claims, degrees, labels);
       the reversal: 12n (read the order, write perm and iperm)."""
-    return k_pp * (8 * m + 20 * n) + (8 * m + 48 * n) + 12 * n
+    return unlabelled_passes(k_pp) * (8 * m + 20 * n) + (8 * m + 48 * n) + 12 * n
 
 
 def whole_call_bytes(n: int, nnz: int, m: int, k_pp: int) -> int:
@@ -137,7 +148,10 @@ def batch_bytes(graphs, stats) -> int:
     total = 0
     for g, st in zip(graphs, stats):
         comps = max(st["num_components"], 1)
-        total += 8 * st["edges_traversed"] + int((20 * st["num_bfs"] / comps + 60) * g.n)
+        k = st["num_bfs"] / comps
+        kp = unlabelled_passes(int(round(k)))
+        m = st["edges_traversed"] / (k + 1) if k >= 0 else 0
+        total += int(8 * m * (kp + 1) + (20 * kp + 60) * g.n)
     return total
 
 

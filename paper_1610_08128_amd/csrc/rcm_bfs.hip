@@ -945,9 +945,11 @@ __device__ __forceinline__ void global_label_level(const BfsParams& P, Team& t, 
 }
 
 // The labelled BFS of Algorithm 3 from `root`; labels are the positions in
-// qi[o, end).  Returns the number of levels; *msum = sum of degrees.
+// qi[o, end).  Returns the number of levels; *msum = sum of degrees.  With
+// lastkey, it also reports the minimum (degree << 32 | id) over its last
+// level, so that it can stand in for a level structure of the search.
 __device__ __forceinline__ int32_t label_pass(const BfsParams& P, Team& t, Shared& S, int32_t o, int32_t end,
-                              int32_t root, long long* msum) {
+                              int32_t root, long long* msum, uint64_t* lastkey) {
   const long long clk0 = wall_clock64();
   const int B = blockDim.x;
   const int4 rinf = P.vinfo[root];
@@ -956,6 +958,7 @@ __device__ __forceinline__ int32_t label_pass(const BfsParams& P, Team& t, Share
     __hip_atomic_store(&P.claim[root], static_cast<uint32_t>(o), __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_AGENT);
     __hip_atomic_store(&t.ctl->msum, 0ll, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&t.ctl->lastkey, kMaxKey, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   // the root's claims, spread over the whole team (its row may be long)
   for (int32_t k = rinf.x + t.wid * B + threadIdx.x; k < rinf.y; k += t.W * B) {
@@ -1008,11 +1011,26 @@ __device__ __forceinline__ int32_t label_pass(const BfsParams& P, Team& t, Share
     t.aborted = true;
     return 0;
   }
+  if (lastkey != nullptr) {
+    // the last level is qi[cur_b, cur_e): its records carry the degree
+    int32_t lo, hi;
+    my_chunk(cur_b, cur_e, t.W, t.wid, lo, hi);
+    uint64_t k = kMaxKey;
+    for (int32_t p = lo + threadIdx.x; p < hi; p += B) {
+      const int4 r = P.qi[p];
+      const uint64_t kv = pack_key(r.w, r.x);
+      k = kv < k ? kv : k;
+    }
+    k = wave_min_u64(k);
+    if ((threadIdx.x & 63) == 0 && k != kMaxKey) atomicMin(&t.ctl->lastkey, k);
+  }
   const long long tot_m = block_sum_i64(my_m, S.red);
   if (threadIdx.x == 0 && tot_m != 0)
     __hip_atomic_fetch_add(&t.ctl->msum, tot_m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   team_barrier(t, S, false);
   *msum = __hip_atomic_load(&t.ctl->msum, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (lastkey != nullptr)
+    *lastkey = __hip_atomic_load(&t.ctl->lastkey, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (t.wid == 0 && threadIdx.x == 0) {
     t.ctl->clk[1] += wall_clock64() - clk0;
     t.ctl->clk[3] += levels;
@@ -1040,18 +1058,40 @@ __device__ __forceinline__ void order_component(const BfsParams& P, Team& t, Sha
   }
   int32_t r = task.seed;
   int32_t nlvl = ecc - 1;
+  long long m = 0;
+  int32_t levels = 0;
+  bool labelled = false;
   while (ecc > nlvl) {
     nlvl = ecc;
     const int32_t v = static_cast<int32_t>(lastkey & 0xffffffffu);  // min degree, last level
     ++nbfs;
-    bfs_pass(P, t, S, o, end, v, nbfs, (nbfs - 1) & 1, ecc, lastkey, nullptr);
-    if (t.aborted) return;
     r = v;
+    if (P.pp_variant == 0 && nbfs >= 3) {
+      // Algorithm 2 returns the root of its last search and Algorithm 3
+      // starts there, so from the third search on the search is run as the
+      // labelled BFS itself: if the eccentricity does not grow, the search
+      // ends and the labelling is already done; otherwise the claims of the
+      // component are cleared and the search goes on.
+      if (labelled) {
+        for (int32_t i = t.wid * blockDim.x + threadIdx.x; i < size; i += t.W * blockDim.x)
+          P.claim[P.qi[o + i].x] = kUnclaimed;
+        team_barrier(t, S, false);
+        if (t.aborted) return;
+      }
+      levels = label_pass(P, t, S, o, end, v, &m, &lastkey);
+      if (t.aborted) return;
+      ecc = levels - 1;
+      labelled = true;
+    } else {
+      bfs_pass(P, t, S, o, end, v, nbfs, (nbfs - 1) & 1, ecc, lastkey, nullptr);
+      if (t.aborted) return;
+    }
   }
   const int32_t root = P.pp_variant == 1 ? static_cast<int32_t>(lastkey & 0xffffffffu) : r;
-  long long m = 0;
-  const int32_t levels = label_pass(P, t, S, o, end, root, &m);
-  if (t.aborted) return;
+  if (!labelled) {
+    levels = label_pass(P, t, S, o, end, root, &m, nullptr);
+    if (t.aborted) return;
+  }
   if (t.wid == 0 && threadIdx.x == 0) {
     CompResult* res = P.results + task.index;
     res->root = root;

@@ -55,6 +55,8 @@ struct alignas(128) TeamCtl {
   int32_t pad4[24];
   int32_t wg_sum[kMaxTeam];      // per-WG counts of the current level
   long long msum;                // sum of degrees of the current component
+  unsigned long long lastkey;    // min (deg << 32 | id) over the last level of a
+                                 // labelled pass that also serves the search
   long long clk[16];             // work-group 0's clock (diagnostics): [0] pp ticks,
                                  // [1] labelled ticks, [2] pp levels, [3] labelled
                                  // levels, [4..15] per-phase ticks
