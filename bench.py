@@ -489,8 +489,8 @@ def main():
             "nnz": g.nnz,
             "pseudo_diameter": st["pseudo_diameter"],
             "bfs_passes": st["num_bfs"] + 1,
-            "team_size": args.team_size or 32,
-            "block_threads": args.block_threads or 512,
+            "team_size": args.team_size or 64,
+            "block_threads": args.block_threads or 256,
         },
         "teps": round(teps, 1),
         "nnz_per_s": round(g.nnz * args.steps / dt, 1),

@@ -33,9 +33,9 @@ struct Opts {
   int pp_variant = 0;
   int reverse_mode = 0;
   int check_full = 0;
-  int team_size = 32;
-  int threads = 512;
-  int small_threads = 256;
+  int team_size = 64;
+  int threads = 256;
+  int small_threads = 512;
   int small_cutoff = 1 << 18;
   int narrow_cutoff = 256;
   int max_teams = 8;

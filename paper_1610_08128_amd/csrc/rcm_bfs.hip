@@ -210,10 +210,12 @@ __device__ __forceinline__ int4 record(int32_t v, int4 info) {
 // Expand qi[lo, hi) (this work-group's share of the level).  A neighbour is
 // new when atomicMax(visit, epoch) returns an older stamp; past-the-row lanes
 // hit the parent's own stamp, which already equals epoch.  New vertices go
-// to the LDS stage or, when it is full, straight to qi[cur_e + ...].
+// to the LDS stage or, when it is full, straight to qi[cur_e + ...] (at a
+// slot reserved on the team's tail counter, or, for a work-group alone, at
+// its own index in the level).
 __device__ __forceinline__ void bfs_expand(const BfsParams& P, Shared& S, int32_t lo, int32_t hi,
                                            int32_t cur_e, int32_t end, int32_t epoch,
-                                           int32_t* tail_slot, uint64_t& mykey) {
+                                           int32_t* tail_slot, bool solo, uint64_t& mykey) {
   const int B = blockDim.x;
   for (int32_t p = lo + threadIdx.x; p < hi; p += B) {
     const int4 e = P.qi[p];
@@ -247,7 +249,7 @@ __device__ __forceinline__ void bfs_expand(const BfsParams& P, Shared& S, int32_
         if (idx < kStageCap) {
           reinterpret_cast<int4*>(S.u.srec)[idx] = r;
         } else {
-          const int32_t at = atomicAdd(tail_slot, 1);
+          const int32_t at = solo ? idx : atomicAdd(tail_slot, 1);
           if (cur_e + at < end) P.qi[cur_e + at] = r;
         }
         ++idx;
@@ -427,15 +429,25 @@ __device__ __forceinline__ void global_bfs_level(const BfsParams& P, Team& t, Sh
   my_chunk(cur_b, cur_e, W, wid, lo, hi);
   uint64_t mykey = kMaxKey;
   const long long ta = wall_clock64();
-  bfs_expand(P, S, lo, hi, cur_e, end, epoch, tail + l3, mykey);
+  bfs_expand(P, S, lo, hi, cur_e, end, epoch, tail + l3, solo, mykey);
   mykey = wave_min_u64(mykey);
   if ((threadIdx.x & 63) == 0 && mykey != kMaxKey) atomicMin(&S.key, mykey);
   __syncthreads();
   const long long tb = wall_clock64();
+  // final here; read now, since the next level resets it after fewer
+  // barriers than separate this read from the end of the level
+  const int32_t own_cnt = S.cnt;
   if (threadIdx.x == 0) {
-    const int32_t ns = S.cnt < kStageCap ? S.cnt : kStageCap;
-    S.base = ns > 0 ? atomicAdd(tail + l3, ns) : 0;
-    if (S.key != kMaxKey) atomicMin(minkey + (level + 1) % 3, S.key);
+    const int32_t ns = own_cnt < kStageCap ? own_cnt : kStageCap;
+    if (solo) {
+      // alone: the level is this work-group's own count, nothing to reserve
+      S.base = 0;
+      __hip_atomic_store(minkey + (level + 1) % 3, S.key, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      S.base = ns > 0 ? atomicAdd(tail + l3, ns) : 0;
+      if (S.key != kMaxKey) atomicMin(minkey + (level + 1) % 3, S.key);
+    }
     if (wid == 0) {
       // slots of the level after next; nobody reads them any more
       st_relaxed(tail + (level + 1) % 3, 0);
@@ -455,7 +467,7 @@ __device__ __forceinline__ void global_bfs_level(const BfsParams& P, Team& t, Sh
   }
   team_barrier(t, S, solo);
   if (t.aborted) return;
-  const int32_t cnt = ld_relaxed(tail + l3);
+  const int32_t cnt = solo ? own_cnt : ld_relaxed(tail + l3);
   if (t.wid == 0 && threadIdx.x == 0) {
     const long long td = wall_clock64();
     if (solo) {

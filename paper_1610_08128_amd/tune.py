@@ -1,0 +1,188 @@
+"""Autotuner for the ordering's launch parameters.
+
+The ordering's results do not depend on its launch parameters; only the time
+does. Those parameters are:
+
+- the team shape: work-groups per team and threads per work-group;
+- the narrow-level cutoff below which one work-group walks the levels alone;
+- the component-size cutoff below which a component gets a single
+  work-group;
+- the threads of those single-work-group teams;
+- how many large-component teams run at once.
+
+The tuner times candidate settings on caller-supplied representative graphs
+(or batches) and keeps the fastest per size class in a JSON table. It checks
+that every candidate returned the same permutation.
+
+Usage::
+
+    table = autotune_single([g1, g2])            # inputs.Graph objects
+    table.save("rcm_tuning.json")
+    opts = TuningTable.load("rcm_tuning.json").options_for(n, nnz)
+    perm, stats = rcm.order(rowptr, colidx, **opts)
+"""
+
+from __future__ import annotations
+
+import json
+import math
+import time
+from dataclasses import dataclass, field
+from typing import Dict, Iterable, List, Optional, Sequence
+
+import numpy as np
+
+from . import rcm
+
+SINGLE_CANDIDATES: List[Dict[str, int]] = [
+    dict(team_size=w, block_threads=b, narrow_cutoff=nc)
+    for (w, b) in ((16, 512), (32, 512), (32, 256), (64, 256), (64, 512))
+    for nc in (64, 256, 1024)
+]
+
+BATCH_CANDIDATES: List[Dict[str, int]] = [
+    dict(small_cutoff=sc, small_threads=st, team_size=w, max_teams=8)
+    for sc in (1 << 15, 1 << 17, 1 << 20)
+    for st in (256, 512)
+    for w in (4, 16)
+]
+
+
+def size_class(n: int, nnz: int, graphs: int = 1) -> str:
+    """Key of a tuning entry: call kind, log2 of the vertex count, and the
+    rounded mean row length."""
+    kind = "batch" if graphs > 1 else "single"
+    lg = int(math.log2(max(n, 1)))
+    deg = int(round(nnz / max(n, 1)))
+    return f"{kind}:n2^{lg}:d{deg}"
+
+
+@dataclass
+class TuningTable:
+    entries: Dict[str, Dict[str, int]] = field(default_factory=dict)
+    timings: Dict[str, Dict[str, float]] = field(default_factory=dict)
+
+    def options_for(self, n: int, nnz: int, graphs: int = 1) -> Dict[str, int]:
+        """Options of the exact size class, else of the nearest class of the
+        same kind and row length, else of the nearest of the same kind,
+        else {} (the library's defaults)."""
+        key = size_class(n, nnz, graphs)
+        if key in self.entries:
+            return dict(self.entries[key])
+        kind, lg, deg = key.split(":")
+        lg_v, deg_v = int(lg[3:]), int(deg[1:])
+        best, best_d = None, None
+        for k in self.entries:
+            k_kind, k_lg, k_deg = k.split(":")
+            if k_kind != kind:
+                continue
+            d = abs(int(k_lg[3:]) - lg_v) + 4 * abs(int(k_deg[1:]) - deg_v)
+            if best_d is None or d < best_d:
+                best, best_d = k, d
+        return dict(self.entries[best]) if best is not None else {}
+
+    def save(self, path: str) -> None:
+        with open(path, "w") as f:
+            json.dump({"entries": self.entries, "timings": self.timings}, f, indent=1,
+                      sort_keys=True)
+
+    @classmethod
+    def load(cls, path: str) -> "TuningTable":
+        with open(path) as f:
+            d = json.load(f)
+        return cls(entries=d.get("entries", {}), timings=d.get("timings", {}))
+
+
+def _time_calls(call, reps: int) -> float:
+    import torch
+
+    call()
+    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        call()
+        torch.cuda.synchronize()
+        best = min(best, time.perf_counter() - t0)
+    return best
+
+
+def autotune_single(graphs: Iterable, candidates: Optional[Sequence[Dict[str, int]]] = None,
+                    reps: int = 3, table: Optional[TuningTable] = None) -> TuningTable:
+    """Time every candidate on every graph (one call per graph, device
+    resident, caller-sized workspace); the fastest candidate of each size
+    class is kept.  Raises if two candidates disagree on a permutation."""
+    import torch
+
+    cands = list(candidates or SINGLE_CANDIDATES)
+    table = table or TuningTable()
+    per_class: Dict[str, Dict[int, float]] = {}
+    for g in graphs:
+        rp = torch.from_numpy(np.ascontiguousarray(g.rowptr)).cuda()
+        ci = torch.from_numpy(np.ascontiguousarray(g.colidx)).cuda()
+        ws = torch.empty(max(rcm.workspace_bytes(g.n, g.nnz), 1), dtype=torch.uint8,
+                         device=rp.device)
+        ref = None
+        key = size_class(g.n, g.nnz)
+        for i, opts in enumerate(cands):
+            out = {}
+
+            def call(opts=opts, out=out):
+                out["perm"], _ = rcm.order(rp, ci, workspace=ws, **opts)
+
+            t = _time_calls(call, reps)
+            perm = out["perm"].cpu().numpy()
+            if ref is None:
+                ref = perm
+            elif not np.array_equal(ref, perm):
+                raise RuntimeError(f"candidate {opts} changed the permutation of {g.name}")
+            per_class.setdefault(key, {}).setdefault(i, 0.0)
+            per_class[key][i] += t
+    for key, times in per_class.items():
+        best = min(times, key=times.get)
+        table.entries[key] = dict(cands[best])
+        table.timings[key] = {json.dumps(cands[i], sort_keys=True): round(t * 1e3, 4)
+                              for i, t in times.items()}
+    return table
+
+
+def autotune_batched(batches: Iterable, candidates: Optional[Sequence[Dict[str, int]]] = None,
+                     reps: int = 2, table: Optional[TuningTable] = None) -> TuningTable:
+    """Like autotune_single for batched calls; each batch is a list of
+    graphs ordered in one rcm_order_batched call."""
+    import torch
+
+    from . import inputs
+
+    cands = list(candidates or BATCH_CANDIDATES)
+    table = table or TuningTable()
+    per_class: Dict[str, Dict[int, float]] = {}
+    for graphs in batches:
+        vo, no, rp_h, ci_h = inputs.concat_batch(graphs)
+        rp = torch.from_numpy(rp_h).cuda()
+        ci = torch.from_numpy(ci_h).cuda()
+        G, N, NNZ = len(graphs), int(vo[-1]), int(no[-1])
+        ws = torch.empty(max(rcm.batched_workspace_bytes(G, N, NNZ), 1), dtype=torch.uint8,
+                         device=rp.device)
+        ref = None
+        key = size_class(N, NNZ, G)
+        for i, opts in enumerate(cands):
+            out = {}
+
+            def call(opts=opts, out=out):
+                out["perm"], _ = rcm.order_batched(vo, no, rp, ci, workspace=ws, **opts)
+
+            t = _time_calls(call, reps)
+            perm = out["perm"].cpu().numpy()
+            if ref is None:
+                ref = perm
+            elif not np.array_equal(ref, perm):
+                raise RuntimeError(f"candidate {opts} changed a batched permutation")
+            per_class.setdefault(key, {}).setdefault(i, 0.0)
+            per_class[key][i] += t
+    for key, times in per_class.items():
+        best = min(times, key=times.get)
+        table.entries[key] = dict(cands[best])
+        table.timings[key] = {json.dumps(cands[i], sort_keys=True): round(t * 1e3, 4)
+                              for i, t in times.items()}
+    return table
