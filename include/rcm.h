@@ -106,7 +106,7 @@ typedef struct {
   int32_t small_threads; /* threads per work-group of the single-work-group
                             teams; 0 = auto (512); 256 or 512                  */
   int32_t max_teams;     /* most large-component teams run at once; 0 = auto
-                            (8), at most 8                                     */
+                            (16), at most 64                                   */
   int32_t reserved[7];
 } rcm_options;
 

@@ -38,7 +38,7 @@ struct Opts {
   int small_threads = 512;
   int small_cutoff = 1 << 18;
   int narrow_cutoff = 256;
-  int max_teams = 8;
+  int max_teams = 16;
 };
 
 bool parse_options(const rcm_options* o, Opts* out) {
@@ -292,19 +292,45 @@ rcm_status run(const Graph& gin, const int32_t* seg_off_host, const Opts& opt, c
   P.pp_variant = opt.pp_variant;
   P.reverse_mode = opt.reverse_mode;
   P.narrow_cutoff = opt.narrow_cutoff;
-  auto run_team = [&](const CompTask* tasks, int32_t count, bool timed) -> rcm_status {
-    P.tasks = tasks;
-    P.ntasks = count;
-    P.teams = teams;
-    P.team_size = opt.team_size;
-    // at most max_teams teams, and only as many as fit on the device at once
-    const int resident = max_team_blocks(opt.threads) / opt.team_size;
-    const int nteams = std::max(1, std::min({count, opt.max_teams, resident}));
-    HIP_TRY(hipMemsetAsync(teams, 0, sizeof(TeamCtl) * nteams, s));
-    if (timed) timer.kmark(1, true);
-    HIP_TRY(launch_order_big(P, opt.threads, nteams, s));
-    if (timed) timer.kmark(1, false);
-    if (timed && timer.on) {
+  P.teams = teams;
+  P.small_teams = small_ctl;
+  P.queues = misc + 16;
+  P.team_size = opt.team_size;
+  // One launch of the ordering kernel: teams of team_size work-groups take
+  // the large components, largest first, and single-work-group blocks the
+  // small ones; team work-groups join the small list once the large one is
+  // empty.  With large components the launch is cooperative, so it is sized
+  // to what is resident at once, half of it left to single-work-group blocks
+  // when there are small components too.
+  auto launch = [&](const CompTask* big, int32_t n_big, const CompTask* small, int32_t n_small,
+                    int kslot, bool copy_clk) -> rcm_status {
+    P.big_tasks = big;
+    P.n_big = n_big;
+    P.tasks = small;
+    P.ntasks = n_small;
+    int blocks = 0, threads = 0, nteams = 0;
+    if (n_big > 0) {
+      threads = opt.threads;
+      const int resident = max_team_blocks(threads);
+      if (resident < opt.team_size) return RCM_ERR_HIP;
+      const int room = n_small > 0 ? std::max(resident / 2, opt.team_size) : resident;
+      nteams = std::max(1, std::min({n_big, opt.max_teams, room / opt.team_size}));
+      P.big_blocks = nteams * opt.team_size;
+      const int extra = n_small > 0 ? std::min(n_small, resident - P.big_blocks) : 0;
+      blocks = std::min(P.big_blocks + std::max(extra, 0), kSmallTeams);
+    } else {
+      threads = opt.small_threads;
+      P.big_blocks = 0;
+      blocks = std::min(n_small, kSmallTeams);
+    }
+    if (blocks <= 0) return RCM_OK;
+    HIP_TRY(hipMemsetAsync(P.queues, 0, 2 * sizeof(int32_t), s));
+    if (nteams > 0) HIP_TRY(hipMemsetAsync(teams, 0, sizeof(TeamCtl) * nteams, s));
+    if (n_small > 0) HIP_TRY(hipMemsetAsync(small_ctl, 0, sizeof(TeamCtl) * blocks, s));
+    timer.kmark(kslot, true);
+    HIP_TRY(launch_order(P, blocks, threads, s));
+    timer.kmark(kslot, false);
+    if (copy_clk && timer.on) {
       HIP_TRY(hipMemcpyAsync(timer.clk, teams[0].clk, sizeof(timer.clk), hipMemcpyDeviceToHost,
                              s));
       HIP_TRY(hipStreamSynchronize(s));
@@ -324,7 +350,7 @@ rcm_status run(const Graph& gin, const int32_t* seg_off_host, const Opts& opt, c
     HIP_TRY(hipMemcpyAsync(t_big, &ht, sizeof(ht), hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(results, &hr, sizeof(hr), hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemsetAsync(seeds, 0, sizeof(int32_t), s));
-    st = run_team(t_big, 1, true);
+    st = launch(t_big, 1, nullptr, 0, 1, true);
     if (st != RCM_OK) return st;
     int32_t hres[8];
     HIP_TRY(hipMemcpyAsync(hres, results, sizeof(CompResult), hipMemcpyDeviceToHost, s));
@@ -366,21 +392,8 @@ rcm_status run(const Graph& gin, const int32_t* seg_off_host, const Opts& opt, c
     timer.mark(3);
     const int32_t n_single = h[0], n_small = h[1], n_big = h[2];
     HIP_TRY(launch_singletons(t_single, n_single, perm_out, iperm, results, s));
-    if (n_small > 0) {
-      P.tasks = t_small;
-      P.ntasks = n_small;
-      P.teams = small_ctl;
-      P.team_size = 1;
-      const int nb = std::min(n_small, kSmallTeams);
-      HIP_TRY(hipMemsetAsync(small_ctl, 0, sizeof(TeamCtl) * nb, s));
-      timer.kmark(0, true);
-      HIP_TRY(launch_order_small(P, nb, opt.small_threads, s));
-      timer.kmark(0, false);
-    }
-    if (n_big > 0) {
-      st = run_team(t_big, n_big, !head);
-      if (st != RCM_OK) return st;
-    }
+    st = launch(t_big, n_big, t_small, n_small, 0, false);
+    if (st != RCM_OK) return st;
   }
   timer.mark(4);
   st = read_ints(h, &gctl->error, 1, s);

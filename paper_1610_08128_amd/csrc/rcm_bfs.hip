@@ -6,12 +6,13 @@
 // One persistent kernel does all of it.  A "team" of W work-groups owns one
 // component at a time and walks its levels; between levels the team meets at
 // a barrier (a monotone arrival counter with device-scope release/acquire
-// fences; for W = 1 the barrier is just __syncthreads).  Two launch shapes:
+// fences; for W = 1 the barrier is just __syncthreads).  In one launch:
 //   - large components: teams of W co-resident work-groups (cooperative
-//     launch; default W = 32, four work-groups on each of the 8 XCDs), one
-//     team per large component at a time;
-//   - small components: many single-work-group teams pulling components from
-//     an atomic queue.
+//     launch; default W = 64, eight work-groups on each of the 8 XCDs) take
+//     them from a queue, largest first;
+//   - small components: single-work-group teams take them from a second
+//     queue, largest first; team work-groups join them once the large
+//     queue is empty.
 // Narrow levels (fewer vertices than the narrow cutoff) are expanded by the
 // team's first work-group alone, level after level with only __syncthreads,
 // while the others sleep until the frontier widens again or the pass ends.
@@ -1123,33 +1124,56 @@ __device__ __forceinline__ void order_component(const BfsParams& P, Team& t, Sha
   }
 }
 
+// Blocks [0, big_blocks) form teams of team_size work-groups that take large
+// components from a queue (largest first); every other block, and the team
+// blocks once that queue is empty, orders small components alone, also
+// largest first.
 __global__ void __launch_bounds__(512) k_order(BfsParams P) {
   __shared__ Shared S;
   Team t;
-  t.W = P.team_size;
-  t.wid = blockIdx.x % P.team_size;
-  const int team = blockIdx.x / P.team_size;
-  const int nteams = gridDim.x / P.team_size;
-  t.ctl = P.teams + team;
   t.g = P.gctl;
   t.nbar = 0;
   t.woke = 0;
   t.aborted = false;
-  for (int iter = 0;; ++iter) {
-    int ti;
-    if (P.use_queue) {
-      if (threadIdx.x == 0) S.task = atomicAdd(&P.gctl->queue, 1);
-      __syncthreads();
-      ti = S.task;
-      __syncthreads();
-    } else {
-      ti = team + iter * nteams;
+  if (static_cast<int32_t>(blockIdx.x) < P.big_blocks) {
+    t.W = P.team_size;
+    t.wid = blockIdx.x % P.team_size;
+    t.ctl = P.teams + blockIdx.x / P.team_size;
+    while (true) {
+      if (t.wid == 0 && threadIdx.x == 0)
+        st_relaxed(&t.ctl->task, atomicAdd(&P.queues[0], 1));
+      team_barrier(t, S, false);
+      if (t.aborted) return;
+      const int32_t ti = ld_relaxed(&t.ctl->task);
+      if (ti >= P.n_big) break;
+      const CompTask task = P.big_tasks[ti];
+      t.comp = task.index;
+      order_component(P, t, S, task);
+      if (t.aborted) return;
     }
-    if (ti >= P.ntasks) break;
-    const CompTask task = P.tasks[ti];
-    t.comp = task.index;
-    order_component(P, t, S, task);
-    if (t.aborted) break;
+  }
+  if (P.ntasks <= 0) return;
+  t.W = 1;
+  t.wid = 0;
+  t.ctl = P.small_teams + blockIdx.x;
+  t.nbar = 0;
+  t.woke = 0;
+  // the small list first, then whatever the teams have not taken yet of
+  // the large one
+  for (int q = 1; q >= 0; --q) {
+    const CompTask* list = q == 1 ? P.tasks : P.big_tasks;
+    const int32_t count = q == 1 ? P.ntasks : P.n_big;
+    while (true) {
+      if (threadIdx.x == 0) S.task = atomicAdd(&P.queues[q], 1);
+      __syncthreads();
+      const int32_t ti = S.task;
+      __syncthreads();
+      if (ti >= count) break;
+      const CompTask task = list[ti];
+      t.comp = task.index;
+      order_component(P, t, S, task);
+      if (t.aborted) return;
+    }
   }
 }
 
@@ -1166,25 +1190,16 @@ int max_team_blocks(int32_t threads) {
   return per_cu * cus;
 }
 
-hipError_t launch_order_small(const BfsParams& p, int32_t nblocks, int32_t threads,
-                              hipStream_t s) {
-  if (p.ntasks <= 0) return hipSuccess;
+hipError_t launch_order(const BfsParams& p, int32_t blocks, int32_t threads, hipStream_t s) {
+  if (blocks <= 0 || (p.n_big <= 0 && p.ntasks <= 0)) return hipSuccess;
   BfsParams q = p;
-  q.team_size = 1;
-  q.use_queue = 1;
-  k_order<<<nblocks, threads, 0, s>>>(q);
+  if (q.big_blocks > 0 && q.team_size > 1) {
+    void* args[] = {&q};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_order), dim3(blocks),
+                                      dim3(threads), args, 0, s);
+  }
+  k_order<<<blocks, threads, 0, s>>>(q);
   return hipGetLastError();
-}
-
-// nteams teams of p.team_size co-resident work-groups; team i takes tasks
-// i, i + nteams, ... of the (largest-first) list.
-hipError_t launch_order_big(const BfsParams& p, int32_t threads, int32_t nteams, hipStream_t s) {
-  if (p.ntasks <= 0) return hipSuccess;
-  BfsParams q = p;
-  q.use_queue = 0;
-  void* args[] = {&q};
-  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_order),
-                                    dim3(q.team_size * nteams), dim3(threads), args, 0, s);
 }
 
 }  // namespace rcm

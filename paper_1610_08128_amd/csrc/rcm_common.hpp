@@ -12,7 +12,7 @@ namespace rcm {
 constexpr uint32_t kUnclaimed = 0xFFFFFFFFu;
 constexpr uint64_t kMaxKey = ~0ull;
 constexpr int kMaxTeam = 64;             // work-groups per team
-constexpr int kMaxConcurrentTeams = 8;   // large-component teams per launch
+constexpr int kMaxConcurrentTeams = 64;  // large-component teams per launch
 // A device-side wait gives up (and flags RCM_ERR_ABORTED) after 30 s of the
 // 100 MHz constant-rate clock read by wall_clock64(): far beyond any
 // legitimate wait, short enough to end a broken run cleanly.
@@ -57,6 +57,7 @@ struct alignas(128) TeamCtl {
   long long msum;                // sum of degrees of the current component
   unsigned long long lastkey;    // min (deg << 32 | id) over the last level of a
                                  // labelled pass that also serves the search
+  int32_t task;                  // large-component task handed to the team
   long long clk[16];             // work-group 0's clock (diagnostics): [0] pp ticks,
                                  // [1] labelled ticks, [2] pp levels, [3] labelled
                                  // levels, [4..15] per-phase ticks
@@ -250,22 +251,26 @@ struct BfsParams {
   int32_t* tmp;
   int32_t* perm;
   int32_t* iperm;
-  const CompTask* tasks;
+  const CompTask* big_tasks;  // components for multi-work-group teams, largest first
+  int32_t n_big;
+  int32_t big_blocks;         // blocks [0, big_blocks) form teams of team_size
+  const CompTask* tasks;      // components for single-work-group teams, largest first
   int32_t ntasks;
   CompResult* results;
-  TeamCtl* teams;
+  TeamCtl* teams;             // one per multi-work-group team
+  TeamCtl* small_teams;       // one per block in single-work-group mode
+  int32_t* queues;            // [0] next large task, [1] next small task (zeroed per launch)
   GlobalCtl* gctl;
   int32_t n;
   int32_t team_size;
   int32_t pp_variant;
   int32_t reverse_mode;
   int32_t narrow_cutoff;
-  int32_t use_queue;
 };
 
-hipError_t launch_order_small(const BfsParams& p, int32_t nblocks, int32_t threads,
-                              hipStream_t s);
-hipError_t launch_order_big(const BfsParams& p, int32_t threads, int32_t nteams, hipStream_t s);
+// One launch of the ordering kernel over the task lists in p; cooperative
+// (all blocks co-resident) whenever p has multi-work-group teams.
+hipError_t launch_order(const BfsParams& p, int32_t blocks, int32_t threads, hipStream_t s);
 int max_team_blocks(int32_t threads);
 
 }  // namespace rcm

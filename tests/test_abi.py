@@ -92,7 +92,7 @@ def test_invalid_arguments_need_no_gpu():
     bad = rcm.make_options(small_threads=128)
     status, _ = rcm.order_raw(0, 0, 0, 0, options=bad)
     assert status == rcm.ERR_INVALID_ARGUMENT
-    bad = rcm.make_options(max_teams=9)
+    bad = rcm.make_options(max_teams=65)
     status, _ = rcm.order_raw(0, 0, 0, 0, options=bad)
     assert status == rcm.ERR_INVALID_ARGUMENT
     bad = rcm.make_options(team_size=65)
