@@ -289,6 +289,7 @@ rcm_status run(const Graph& gin, const int32_t* seg_off_host, const Opts& opt, c
   P.results = results;
   P.gctl = gctl;
   P.n = g.n;
+  P.nnz = g.nnz;
   P.pp_variant = opt.pp_variant;
   P.reverse_mode = opt.reverse_mode;
   P.narrow_cutoff = opt.narrow_cutoff;

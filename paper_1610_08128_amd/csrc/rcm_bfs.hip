@@ -128,16 +128,29 @@ __device__ __forceinline__ bool wait_at_least(Team& t, unsigned long long* ctr,
   return true;
 }
 
+// Every wave of the work-group waits until its own memory operations (loads,
+// stores, atomics, also fire-and-forget ones) have completed.
+__device__ __forceinline__ void drain_memory_ops() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
 // Team barrier; `solo` = only this work-group is active (narrow mode or W=1).
+// What one work-group hands to another across it is written with atomics or
+// device-scope stores, so arriving needs only every wave's own operations
+// to have completed (no L2 write-back); leaving invalidates this CU's caches
+// (an agent-scope acquire) so that plain loads see the other work-groups'
+// data.
 __device__ __forceinline__ void team_barrier(Team& t, Shared& S, bool solo) {
   if (solo || t.W == 1) {
     __syncthreads();
     return;
   }
+  drain_memory_ops();
   __syncthreads();
   if (threadIdx.x == 0) {
     t.nbar += static_cast<unsigned long long>(t.W);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __hip_atomic_fetch_add(&t.ctl->bar, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const bool ok = wait_at_least(t, &t.ctl->bar, t.nbar, false);
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
@@ -151,6 +164,9 @@ __device__ __forceinline__ void team_barrier(Team& t, Shared& S, bool solo) {
 // the others; they read it back.
 __device__ __forceinline__ void narrow_publish(Team& t, int32_t cur_b, int32_t cur_e,
                                                int32_t level, bool done) {
+  // work-group 0 wrote the stretch's records and stamps with plain stores:
+  // every wave completes them, then one release writes them back
+  drain_memory_ops();
   __syncthreads();
   if (threadIdx.x == 0) {
     st_relaxed(&t.ctl->narrow_state[0], cur_b);
@@ -204,6 +220,31 @@ __device__ __forceinline__ int4 record(int32_t v, int4 info) {
   return make_int4(v, info.x, info.y, info.z);
 }
 
+// Store a frontier record that other work-groups read after a team barrier.
+// The two halves are device-scope stores, which reach the point of
+// coherence of all XCDs by themselves, so the team barrier needs no L2
+// write-back (every wave waits for its stores before arriving).
+__device__ __forceinline__ void st_rec(int4* p, int4 r) {
+  unsigned long long* q = reinterpret_cast<unsigned long long*>(p);
+  const unsigned long long lo =
+      static_cast<uint32_t>(r.x) | (static_cast<unsigned long long>(static_cast<uint32_t>(r.y)) << 32);
+  const unsigned long long hi =
+      static_cast<uint32_t>(r.z) | (static_cast<unsigned long long>(static_cast<uint32_t>(r.w)) << 32);
+  __hip_atomic_store(q, lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(q + 1, hi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// A frontier record as read back, clamped into the graph (vertex in [0, n),
+// 0 <= row begin <= row end <= nnz), so that no read can leave the arrays
+// whatever a position held.
+__device__ __forceinline__ int4 ld_rec(const BfsParams& P, int32_t pos) {
+  int4 r = P.qi[pos];
+  r.x = min(max(r.x, 0), P.n - 1);
+  r.z = min(max(r.z, 0), P.nnz);
+  r.y = min(max(r.y, 0), r.z);
+  return r;
+}
+
 // ---------------------------------------------------------------------------
 // Unlabelled BFS (one level structure).
 // ---------------------------------------------------------------------------
@@ -219,7 +260,7 @@ __device__ __forceinline__ void bfs_expand(const BfsParams& P, Shared& S, int32_
                                            int32_t* tail_slot, bool solo, uint64_t& mykey) {
   const int B = blockDim.x;
   for (int32_t p = lo + threadIdx.x; p < hi; p += B) {
-    const int4 e = P.qi[p];
+    const int4 e = ld_rec(P, p);
     const int32_t u = e.x;
     for (int32_t k0 = e.y; k0 < e.z; k0 += kRB) {
       int32_t nb[kRB];
@@ -251,7 +292,7 @@ __device__ __forceinline__ void bfs_expand(const BfsParams& P, Shared& S, int32_
           reinterpret_cast<int4*>(S.u.srec)[idx] = r;
         } else {
           const int32_t at = solo ? idx : atomicAdd(tail_slot, 1);
-          if (cur_e + at < end) P.qi[cur_e + at] = r;
+          if (cur_e + at < end) st_rec(&P.qi[cur_e + at], r);
         }
         ++idx;
       }
@@ -315,7 +356,7 @@ __device__ __forceinline__ bool lds_bfs_levels(const BfsParams& P, Team& t, Shar
   const long long c0 = wall_clock64();
   long long rs = 0;
   for (int32_t i = threadIdx.x; i < len; i += B) {
-    const int4 r = P.qi[cur_b + i];
+    const int4 r = ld_rec(P, cur_b + i);
     lds_put(N, level & 1, i, r);
     rs += r.z - r.y;
   }
@@ -463,7 +504,7 @@ __device__ __forceinline__ void global_bfs_level(const BfsParams& P, Team& t, Sh
     const int4* stage = reinterpret_cast<const int4*>(S.u.srec);
     for (int32_t i = threadIdx.x; i < ns; i += B) {
       const int32_t at = cur_e + S.base + i;
-      if (at < end) P.qi[at] = stage[i];
+      if (at < end) st_rec(&P.qi[at], stage[i]);
     }
   }
   team_barrier(t, S, solo);
@@ -508,8 +549,8 @@ __device__ __forceinline__ void bfs_pass(const BfsParams& P, Team& t, Shared& S,
   unsigned long long* minkey = t.ctl->minkey + parity * 3;
   if (t.wid == 0 && threadIdx.x == 0) {
     const int4 ri = P.vinfo[root];
-    P.qi[o] = record(root, ri);
-    P.visit[root] = epoch;
+    st_rec(&P.qi[o], record(root, ri));
+    __hip_atomic_store(&P.visit[root], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     for (int i = 0; i < 3; ++i) st_relaxed(tail + i, 0);
     __hip_atomic_store(minkey + 0, pack_key(ri.z, root), __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_AGENT);
@@ -649,7 +690,7 @@ __device__ __forceinline__ void place_long_row(const BfsParams& P, Shared& S, in
           rank += (w[i] != u && cw[i] == pl && pack_key(dw[i], w[i]) < kv) ? 1 : 0;
       }
       const int32_t at = base + rank;
-      if (at < end) P.qi[at] = record(nb[j], inf);
+      if (at < end) st_rec(&P.qi[at], record(nb[j], inf));
       my_m += inf.z;
       defer_claims(P, S, nb[j], inf, at, list_base);
     }
@@ -694,7 +735,7 @@ __device__ __forceinline__ bool lds_label_levels(const BfsParams& P, Team& t, Sh
   const long long c0 = wall_clock64();
   long long mr = 0, rs = 0;
   for (int32_t i = threadIdx.x; i < len; i += B) {
-    const int4 r = P.qi[cur_b + i];
+    const int4 r = ld_rec(P, cur_b + i);
     lds_put(N, 0, i, r);
     mr = (r.z - r.y) > mr ? (r.z - r.y) : mr;
     rs += r.z - r.y;
@@ -816,7 +857,7 @@ __device__ __forceinline__ bool lds_label_levels(const BfsParams& P, Team& t, Sh
   if (!done) {
     // the team levels expect the frontier's claims on the next level
     for (int32_t i = threadIdx.x; i < len; i += B) {
-      const int4 r = P.qi[cur_b + i];
+      const int4 r = ld_rec(P, cur_b + i);
       claim_row(P, r.x, make_int4(r.y, r.z, r.w, 0), static_cast<uint32_t>(cur_b + i));
     }
   }
@@ -852,7 +893,7 @@ __device__ __forceinline__ void global_label_level(const BfsParams& P, Team& t, 
   unsigned cmask = 0;
   int wg_total = 0;
   for (int32_t p = lo + threadIdx.x; p < hi; p += B) {
-    const int4 e = P.qi[p];
+    const int4 e = ld_rec(P, p);
     const int32_t u = e.x;
     const uint32_t pl = static_cast<uint32_t>(p);
     int c;
@@ -922,14 +963,14 @@ __device__ __forceinline__ void global_label_level(const BfsParams& P, Team& t, 
 #pragma unroll
         for (int j = 0; j < kRB; ++j) {
           if (!(cmask >> j & 1u)) continue;
-          if (at[j] < end) P.qi[at[j]] = record(cnb[j], cinf[j]);
+          if (at[j] < end) st_rec(&P.qi[at[j]], record(cnb[j], cinf[j]));
           my_m += cinf[j].z;
         }
 #pragma unroll
         for (int j = 0; j < kRB; ++j)
           if (cmask >> j & 1u) defer_claims(P, S, cnb[j], cinf[j], at[j], list_base);
       } else {
-        const int4 e = P.qi[p];
+        const int4 e = ld_rec(P, p);
         place_long_row(P, S, p, e.x, e.y, e.z, base, end, list_base, my_m);
       }
     }
@@ -967,7 +1008,7 @@ __device__ __forceinline__ int32_t label_pass(const BfsParams& P, Team& t, Share
   const int B = blockDim.x;
   const int4 rinf = P.vinfo[root];
   if (t.wid == 0 && threadIdx.x == 0) {
-    P.qi[o] = record(root, rinf);
+    st_rec(&P.qi[o], record(root, rinf));
     __hip_atomic_store(&P.claim[root], static_cast<uint32_t>(o), __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_AGENT);
     __hip_atomic_store(&t.ctl->msum, 0ll, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1030,7 +1071,7 @@ __device__ __forceinline__ int32_t label_pass(const BfsParams& P, Team& t, Share
     my_chunk(cur_b, cur_e, t.W, t.wid, lo, hi);
     uint64_t k = kMaxKey;
     for (int32_t p = lo + threadIdx.x; p < hi; p += B) {
-      const int4 r = P.qi[p];
+      const int4 r = ld_rec(P, p);
       const uint64_t kv = pack_key(r.w, r.x);
       k = kv < k ? kv : k;
     }
@@ -1087,7 +1128,8 @@ __device__ __forceinline__ void order_component(const BfsParams& P, Team& t, Sha
       // component are cleared and the search goes on.
       if (labelled) {
         for (int32_t i = t.wid * blockDim.x + threadIdx.x; i < size; i += t.W * blockDim.x)
-          P.claim[P.qi[o + i].x] = kUnclaimed;
+          __hip_atomic_store(&P.claim[ld_rec(P, o + i).x], kUnclaimed, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
         team_barrier(t, S, false);
         if (t.aborted) return;
       }
@@ -1117,7 +1159,7 @@ __device__ __forceinline__ void order_component(const BfsParams& P, Team& t, Sha
   const int32_t anchor = task.anchor >= 0 ? task.anchor : o + size - 1;
   const int32_t nthreads = t.W * blockDim.x;
   for (int32_t i = t.wid * blockDim.x + threadIdx.x; i < size; i += nthreads) {
-    const int32_t v = P.qi[o + i].x;
+    const int32_t v = ld_rec(P, o + i).x;
     const int32_t pos = anchor - i;
     P.perm[pos] = v;
     if (v >= 0 && v < P.n) P.iperm[v] = pos;

@@ -262,6 +262,7 @@ struct BfsParams {
   int32_t* queues;            // [0] next large task, [1] next small task (zeroed per launch)
   GlobalCtl* gctl;
   int32_t n;
+  int32_t nnz;
   int32_t team_size;
   int32_t pp_variant;
   int32_t reverse_mode;
