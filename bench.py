@@ -284,10 +284,10 @@ def run_serve(args):
 
     budget = 8 << 30
     rows = []
-    for frac in (0.5, 0.75, 1.0, 1.5, 2.0, 3.0):
+    for frac in (0.5, 1.0, 2.0, 3.0, 4.0, 6.0):
         rate = frac * x1
         arrivals = inputs.request_stream(args.serve_requests, rate, seed_sizes=5, seed_arrivals=6)
-        with Server(mem_budget_bytes=budget, executors=4, max_batch=64) as srv:
+        with Server(mem_budget_bytes=budget) as srv:
             tickets = [None] * len(arrivals)
             start = time.perf_counter()
 
@@ -352,7 +352,8 @@ def run_serve(args):
                                f"random geometric patches; {args.serve_pool} distinct requests "
                                f"reused cyclically, {args.serve_requests} per rate",
                    "pool_nnz_mean": int(np.mean([g.nnz for g in pool])),
-                   "mem_budget_bytes": budget, "executors": 4, "max_batch": 64},
+                   "mem_budget_bytes": budget, "executors": 2, "max_batch": 32,
+                   "batch_nnz_limit": "none"},
         "one_call_per_request": {"orderings_per_s": round(x1, 2),
                                  "p50_ms": round(_percentile(lat1, 50) * 1e3, 2),
                                  "p99_ms": round(_percentile(lat1, 99) * 1e3, 2)},

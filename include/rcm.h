@@ -93,20 +93,22 @@ typedef struct {
                             asymmetric patterns (NOT_SYMMETRIC); costs
                             O(sum of squared row lengths)                      */
   int32_t team_size;     /* work-groups cooperating on one large component;
-                            0 = auto (64, eight per XCD); 1..64                 */
+                            0 = auto (64, eight per XCD; 8 in batched calls);
+                            1..64                                              */
   int32_t block_threads; /* threads per work-group of the large-component
                             team; 0 = auto (256); 256 or 512                   */
   int32_t small_cutoff;  /* components with at most this many vertices are
                             ordered by a single work-group each, many in
                             parallel, largest first; larger ones by teams of
-                            team_size work-groups; 0 = auto (262144)          */
+                            team_size work-groups; 0 = auto (262144; 65536 in
+                            batched calls)                                     */
   int32_t narrow_cutoff; /* levels narrower than this are expanded by one
                             work-group of the team without grid-wide barriers;
                             0 = auto (256), -1 = never                         */
   int32_t small_threads; /* threads per work-group of the single-work-group
                             teams; 0 = auto (512); 256 or 512                  */
   int32_t max_teams;     /* most large-component teams run at once; 0 = auto
-                            (16), at most 64                                   */
+                            (16; 32 in batched calls), at most 64              */
   int32_t reserved[7];
 } rcm_options;
 

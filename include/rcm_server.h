@@ -18,10 +18,11 @@
  *     footprint exceeds the whole budget fails alone with
  *     RCM_ERR_OUT_OF_MEMORY;
  *   - continuous batching: whenever an executor is free it takes the
- *     waiting requests from the head of the queue, as many small ones as
- *     fit (memory, max_batch, batch_nnz_limit), and orders them in one
- *     batched call (rcm_order_batched); a large request runs alone
- *     (rcm_order_ex);
+ *     waiting requests from the head of the queue, as many as fit (memory,
+ *     max_batch, batch_nnz_limit), and orders them in one batched call
+ *     (rcm_order_batched), whose single persistent launch runs the
+ *     components of all of them concurrently; a request above
+ *     batch_nnz_limit, or alone in the queue, runs by itself (rcm_order_ex);
  *   - several executors, each a host thread with its own HIP stream (default
  *     priority), so that one batch's host-to-device copies overlap another
  *     batch's kernels;
@@ -50,10 +51,13 @@ typedef struct rcm_server rcm_server;
 
 typedef struct {
   uint64_t mem_budget_bytes; /* device arena size; 0 = auto (1 GiB)                 */
-  int32_t max_batch;         /* most requests in one batched call; 0 = auto (64)     */
+  int32_t max_batch;         /* most requests in one batched call; 0 = auto (32)     */
   int32_t executors;         /* executor threads / streams; 0 = auto (2), at most 8 */
-  int64_t batch_nnz_limit;   /* requests with more CSR entries run alone;
-                                0 = auto (2^21)                                      */
+  int64_t batch_nnz_limit;   /* requests with more CSR entries run alone; 0 = auto
+                                (no limit: one persistent launch orders the
+                                components of all batched requests concurrently,
+                                which keeps the GPU busier than requests run one
+                                by one)                                              */
   rcm_options order_options; /* options of every ordering (see rcm.h)                */
 } rcm_server_config;
 

@@ -41,8 +41,16 @@ struct Opts {
   int max_teams = 16;
 };
 
-bool parse_options(const rcm_options* o, Opts* out) {
+// Auto values differ for batched calls: many components of many graphs share
+// one launch, so more, smaller teams take the larger ones (measured on the
+// 512-graph batch and on the request pool of the serving benchmark).
+bool parse_options(const rcm_options* o, Opts* out, bool batched = false) {
   Opts r;
+  if (batched) {
+    r.small_cutoff = 1 << 16;
+    r.team_size = 8;
+    r.max_teams = 32;
+  }
   if (o) {
     if (o->pp_variant != 0 && o->pp_variant != 1) return false;
     if (o->reverse_mode != 0 && o->reverse_mode != 1) return false;
@@ -558,7 +566,7 @@ rcm_status rcm_order_batched(int32_t num_graphs, const int64_t* vtx_offsets,
   if (num_graphs == 0) return RCM_OK;
   if (!vtx_offsets || !nnz_offsets) return RCM_ERR_INVALID_ARGUMENT;
   Opts o;
-  if (!parse_options(opts, &o)) return RCM_ERR_INVALID_ARGUMENT;
+  if (!parse_options(opts, &o, true)) return RCM_ERR_INVALID_ARGUMENT;
   if (vtx_offsets[0] != 0 || nnz_offsets[0] != 0) return RCM_ERR_INVALID_ARGUMENT;
   for (int g = 0; g < num_graphs; ++g)
     if (vtx_offsets[g + 1] < vtx_offsets[g] || nnz_offsets[g + 1] < nnz_offsets[g])

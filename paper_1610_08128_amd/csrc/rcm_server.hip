@@ -343,9 +343,9 @@ rcm_status rcm_server_create(const rcm_server_config* cfg_in, rcm_server** out) 
       cfg.batch_nnz_limit < 0)
     return RCM_ERR_INVALID_ARGUMENT;
   if (cfg.mem_budget_bytes == 0) cfg.mem_budget_bytes = 1ull << 30;
-  if (cfg.max_batch == 0) cfg.max_batch = 64;
+  if (cfg.max_batch == 0) cfg.max_batch = 32;
   if (cfg.executors == 0) cfg.executors = 2;
-  if (cfg.batch_nnz_limit == 0) cfg.batch_nnz_limit = 1ll << 21;
+  if (cfg.batch_nnz_limit == 0) cfg.batch_nnz_limit = (1ll << 31) - 1;
   // reject bad ordering options now rather than per request
   if (rcm_order_ex(0, nullptr, nullptr, nullptr, nullptr, nullptr, &cfg.order_options, nullptr, 0,
                    nullptr) != RCM_OK)
