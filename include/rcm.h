@@ -109,7 +109,11 @@ typedef struct {
                             teams; 0 = auto (512); 256 or 512                  */
   int32_t max_teams;     /* most large-component teams run at once; 0 = auto
                             (16; 32 in batched calls), at most 64              */
-  int32_t reserved[7];
+  int32_t rebalance_levels; /* wide unlabelled levels keep each work-group's
+                            share of the frontier in LDS and redistribute it
+                            evenly every this many levels; 0 = auto (8),
+                            1 = every level                                    */
+  int32_t reserved[6];
 } rcm_options;
 
 /* Human-readable name of a status code (static string). */

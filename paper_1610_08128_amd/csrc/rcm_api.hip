@@ -39,6 +39,7 @@ struct Opts {
   int small_cutoff = 1 << 18;
   int narrow_cutoff = 256;
   int max_teams = 16;
+  int rebalance = 8;
 };
 
 // Auto values differ for batched calls: many components of many graphs share
@@ -63,6 +64,7 @@ bool parse_options(const rcm_options* o, Opts* out, bool batched = false) {
     if (o->small_threads != 0 && o->small_threads != 256 && o->small_threads != 512)
       return false;
     if (o->max_teams < 0 || o->max_teams > kMaxConcurrentTeams) return false;
+    if (o->rebalance_levels < 0) return false;
     r.pp_variant = o->pp_variant;
     r.reverse_mode = o->reverse_mode;
     r.check_full = o->check_full;
@@ -72,6 +74,7 @@ bool parse_options(const rcm_options* o, Opts* out, bool batched = false) {
     if (o->narrow_cutoff) r.narrow_cutoff = o->narrow_cutoff;
     if (o->small_threads) r.small_threads = o->small_threads;
     if (o->max_teams) r.max_teams = o->max_teams;
+    if (o->rebalance_levels) r.rebalance = o->rebalance_levels;
   }
   *out = r;
   return true;
@@ -301,6 +304,7 @@ rcm_status run(const Graph& gin, const int32_t* seg_off_host, const Opts& opt, c
   P.pp_variant = opt.pp_variant;
   P.reverse_mode = opt.reverse_mode;
   P.narrow_cutoff = opt.narrow_cutoff;
+  P.rebalance = opt.rebalance;
   P.teams = teams;
   P.small_teams = small_ctl;
   P.queues = misc + 16;

@@ -76,8 +76,11 @@ struct NarrowLds {
   unsigned long long kmin[3];      // its minimum (degree << 32 | id) (mod 3)
 };
 
+constexpr int kOwnCap = 2048;  // own-frontier records per work-group and buffer
+
 union SharedBuf {
   int32_t srec[kStageCap][4];      // append stage of the team levels
+  int32_t own[2][kOwnCap][4];      // own frontier, current and next level
   NarrowLds nw;
 };
 
@@ -90,6 +93,14 @@ struct Shared {
   unsigned long long key;
   int flag;
   int task;
+  int32_t spill;                   // own-frontier level: records went to qi
+  int32_t total;                   // own-frontier level: next level size
+  int32_t nspill;                  // own-frontier level: records in qi
+  // counting barriers (used by thread 0): arrivals expected so far, and the
+  // word's value above them (spills + 2^12 x found, in units of 2^20) when
+  // it last completed
+  unsigned long long carr[2];
+  unsigned long long crest[2];
   int32_t wsum[kMaxTeam];
   int32_t state[8];
 };
@@ -536,6 +547,209 @@ __device__ __forceinline__ void global_bfs_level(const BfsParams& P, Team& t, Sh
   }
 }
 
+// Wide unlabelled levels with each work-group's share of the frontier in LDS:
+// a work-group expands the vertices it found itself at the previous level
+// (plus, at the first level and after a spill, its chunk of records in qi),
+// so records neither go to nor come back from qi.  The level's size travels
+// in the arrival atomic of a counting barrier (two words alternating by
+// level), and the next level's minimum key is issued after arriving (it is
+// only read once the pass ends, behind a full barrier).  Enters with the
+// frontier in qi[cur_b, cur_e); returns when the pass has ended (done) or
+// the frontier is narrower than the narrow cutoff, which is then written to
+// qi[cur_b, cur_e) for the narrow levels.
+__device__ __forceinline__ void own_bfs_levels(const BfsParams& P, Team& t, Shared& S,
+                                               int32_t end, int32_t epoch, int32_t* tail,
+                                               unsigned long long* minkey, int32_t& cur_b,
+                                               int32_t& cur_e, int32_t& level, bool& done) {
+  const int B = blockDim.x;
+  int cb = 0;                          // LDS buffer holding this work-group's frontier
+  int32_t own_n = 0;                   // records in it
+  int32_t g_b = cur_b, g_e = cur_e;    // records in qi expanded chunk-wise
+  int since = 0;                       // levels since the frontier was spread evenly
+  while (true) {
+    const int l3 = level % 3;
+    // Each work-group keeps what it found, so the shares drift apart from
+    // level to level; every `rebalance` levels the whole next level goes to
+    // qi (one reservation per work-group) and is chunked evenly again.
+    const bool spread = ++since >= P.rebalance;
+    if (spread) since = 0;
+    if (threadIdx.x == 0) {
+      S.cnt = 0;
+      S.key = kMaxKey;
+      S.spill = 0;
+    }
+    __syncthreads();
+    const long long ta = wall_clock64();
+    int32_t lo, hi;
+    my_chunk(g_b, g_e, t.W, t.wid, lo, hi);
+    const int32_t n_glob = hi - lo;
+    uint64_t mykey = kMaxKey;
+    for (int32_t i = threadIdx.x; i < n_glob + own_n; i += B) {
+      int4 e;
+      if (i < n_glob) {
+        e = ld_rec(P, lo + i);
+      } else {
+        const int32_t j = i - n_glob;
+        e = make_int4(S.u.own[cb][j][0], S.u.own[cb][j][1], S.u.own[cb][j][2], 0);
+      }
+      const int32_t u = e.x;
+      for (int32_t k0 = e.y; k0 < e.z; k0 += kRB) {
+        int32_t nb[kRB];
+        load_batch(P.colidx, k0, e.z, u, nb);
+        int4 inf[kRB];
+        int32_t old[kRB];
+#pragma unroll
+        for (int j = 0; j < kRB; ++j) inf[j] = P.vinfo[nb[j]];
+#pragma unroll
+        for (int j = 0; j < kRB; ++j) old[j] = atomicMax(&P.visit[nb[j]], epoch);
+        unsigned mask = 0;
+#pragma unroll
+        for (int j = 0; j < kRB; ++j) mask |= (old[j] < epoch ? 1u : 0u) << j;
+        if (mask == 0) continue;
+        int32_t idx = atomicAdd(&S.cnt, __popc(mask));
+#pragma unroll
+        for (int j = 0; j < kRB; ++j) {
+          if (!(mask >> j & 1u)) continue;
+          const uint64_t kv = pack_key(inf[j].z, nb[j]);
+          mykey = kv < mykey ? kv : mykey;
+          if (idx < kOwnCap) {
+            S.u.own[cb ^ 1][idx][0] = nb[j];
+            S.u.own[cb ^ 1][idx][1] = inf[j].x;
+            S.u.own[cb ^ 1][idx][2] = inf[j].y;
+            S.u.own[cb ^ 1][idx][3] = inf[j].z;
+          } else {
+            const int32_t at = atomicAdd(tail + l3, 1);
+            if (cur_e + at < end) st_rec(&P.qi[cur_e + at], record(nb[j], inf[j]));
+            S.spill = 1;
+          }
+          ++idx;
+        }
+      }
+    }
+    mykey = wave_min_u64(mykey);
+    if ((threadIdx.x & 63) == 0 && mykey != kMaxKey) atomicMin(&S.key, mykey);
+    __syncthreads();
+    const long long tb = wall_clock64();
+    const int32_t my_new = S.cnt;
+    const int32_t kept = my_new < kOwnCap ? my_new : kOwnCap;
+    if (spread) {
+      if (threadIdx.x == 0) {
+        S.base = kept > 0 ? atomicAdd(tail + l3, kept) : 0;
+        if (kept > 0) S.spill = 1;
+      }
+      __syncthreads();
+      for (int32_t i = threadIdx.x; i < kept; i += B) {
+        const int32_t at = cur_e + S.base + i;
+        if (at < end)
+          st_rec(&P.qi[at], make_int4(S.u.own[cb ^ 1][i][0], S.u.own[cb ^ 1][i][1],
+                                      S.u.own[cb ^ 1][i][2], S.u.own[cb ^ 1][i][3]));
+      }
+    }
+    const bool spilled = S.spill != 0;
+    if (spilled) {
+      // records in qi must be complete before this work-group arrives
+      drain_memory_ops();
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      const int w = level & 1;
+      if (t.wid == 0) {
+        // slots two levels ahead: free now, needed again after the next barrier
+        st_relaxed(tail + (level + 1) % 3, 0);
+        __hip_atomic_store(minkey + (level + 2) % 3, kMaxKey, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        drain_memory_ops();
+      }
+      // the word is the exact sum of every arrival's add = 1 + 2^20 spilled
+      // + 2^32 found; with the arrivals known, the rest gives this level's
+      // spills and vertices
+      S.carr[w] += static_cast<unsigned long long>(t.W);
+      const unsigned long long add = 1ull + (spilled ? (1ull << 20) : 0ull) +
+                                     (static_cast<unsigned long long>(my_new) << 32);
+      __hip_atomic_fetch_add(&t.ctl->cbar[w], add, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (S.key != kMaxKey) atomicMin(minkey + (level + 1) % 3, S.key);
+      long spins = 0;
+      const long long t0 = wall_clock64();
+      bool ok = true;
+      unsigned long long v;
+      while (true) {
+        v = __hip_atomic_load(&t.ctl->cbar[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (((v ^ S.carr[w]) & 0xFFFFFull) == 0) break;
+        if ((++spins & 255) == 0) {
+          if (ld_relaxed(&t.g->error) != 0) { ok = false; break; }
+          if (wall_clock64() - t0 > kWaitLimitTicks) {
+            flag_error(t.g, RCM_ERR_ABORTED);
+            ok = false;
+            break;
+          }
+        }
+      }
+      const unsigned long long rest = (v - S.carr[w]) >> 20;
+      const unsigned long long d = rest - S.crest[w];
+      S.crest[w] = rest;
+      const uint32_t nsp = static_cast<uint32_t>(d & 0xFFFull);   // < W spills per level
+      S.total = static_cast<int32_t>(static_cast<uint32_t>(d >> 12));
+      S.nspill = 0;
+      if (ok && nsp != 0) {
+        // some work-group spilled: its records are in qi
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        S.nspill = ld_relaxed(tail + l3);
+      }
+      S.flag = ok ? 0 : 1;
+    }
+    __syncthreads();
+    t.aborted = S.flag != 0;
+    if (t.aborted) return;
+    const int32_t total = S.total;
+    const int32_t nspill = S.nspill;
+    if (t.wid == 0 && threadIdx.x == 0) {
+      t.ctl->clk[4] += tb - ta;
+      t.ctl->clk[6] += wall_clock64() - tb;
+      t.ctl->clk[7] += 1;
+    }
+    if (total == 0) {
+      // the pass ended at this level: every minimum-key atomic is complete
+      // before anyone reads the last level's key
+      done = true;
+      team_barrier(t, S, false);
+      return;
+    }
+    cur_b = cur_e;
+    cur_e += total;
+    ++level;
+    if (cur_e > end) {  // left the component: the pattern is not symmetric
+      if (threadIdx.x == 0)
+        flag_error(t.g, RCM_ERR_NOT_SYMMETRIC, 8, t.comp, epoch, level, cur_b, cur_e, end);
+      done = true;
+      t.aborted = true;
+      return;
+    }
+    cb ^= 1;
+    own_n = spread ? 0 : kept;
+    g_b = cur_b;
+    g_e = cur_b + nspill;
+    if (total < P.narrow_cutoff) {
+      // hand the frontier to the narrow levels: own records after the
+      // spilled ones, in work-group order
+      if (threadIdx.x == 0) st_relaxed(&t.ctl->wg_sum[t.wid], own_n);
+      team_barrier(t, S, false);
+      if (t.aborted) return;
+      if (threadIdx.x < t.W) S.wsum[threadIdx.x] = ld_relaxed(&t.ctl->wg_sum[threadIdx.x]);
+      __syncthreads();
+      int32_t prefix = 0;
+      for (int w = 0; w < t.wid; ++w) prefix += S.wsum[w];
+      for (int32_t i = threadIdx.x; i < own_n; i += B) {
+        const int32_t at = g_e + prefix + i;
+        if (at < end)
+          st_rec(&P.qi[at], make_int4(S.u.own[cb][i][0], S.u.own[cb][i][1], S.u.own[cb][i][2],
+                                      S.u.own[cb][i][3]));
+      }
+      team_barrier(t, S, false);
+      return;
+    }
+  }
+}
+
 // One level structure (Section II-A) of the component whose label block is
 // [o, end), rooted at `root`.  Vertices are written level by level into qi.
 // Returns the eccentricity of root and the minimum (degree << 32 | id) over
@@ -597,8 +811,8 @@ __device__ __forceinline__ void bfs_pass(const BfsParams& P, Team& t, Shared& S,
       continue;
     }
     // wide levels: the whole team
-    while (!done && (cur_e - cur_b) >= P.narrow_cutoff) {
-      global_bfs_level(P, t, S, end, epoch, tail, minkey, false, cur_b, cur_e, level, done);
+    if (!done && (cur_e - cur_b) >= P.narrow_cutoff) {
+      own_bfs_levels(P, t, S, end, epoch, tail, minkey, cur_b, cur_e, level, done);
       if (t.aborted) return;
     }
   }
@@ -1176,6 +1390,8 @@ __global__ void __launch_bounds__(512) k_order(BfsParams P) {
   t.g = P.gctl;
   t.nbar = 0;
   t.woke = 0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < 2; ++i) S.carr[i] = S.crest[i] = 0;
   t.aborted = false;
   if (static_cast<int32_t>(blockIdx.x) < P.big_blocks) {
     t.W = P.team_size;

@@ -45,6 +45,11 @@ struct CompResult {
 struct alignas(128) TeamCtl {
   unsigned long long bar;        // barrier arrivals (monotone)
   unsigned long long pad0[15];
+  unsigned long long cbar[2];    // counting barriers of the own-frontier levels,
+                                 // alternating by level: bits 0..19 arrivals,
+                                 // 20..31 work-groups that spilled to qi, 32..63
+                                 // vertices found (all running sums, modular)
+  unsigned long long pad5[14];
   int32_t tail[6];               // append counters, [pass parity][level mod 3]
   int32_t pad1[26];
   unsigned long long minkey[6];  // min (deg << 32 | id) per level, same indexing
@@ -267,6 +272,7 @@ struct BfsParams {
   int32_t pp_variant;
   int32_t reverse_mode;
   int32_t narrow_cutoff;
+  int32_t rebalance;          // wide unlabelled levels between redistributions
 };
 
 // One launch of the ordering kernel over the task lists in p; cooperative
