@@ -57,7 +57,9 @@ typedef enum {
   RCM_ERR_INVALID_ARGUMENT = 1,    /* n < 0, NULL pointer with n > 0, bad option */
   RCM_ERR_BAD_CSR = 2,             /* rowptr[0] != 0, decreasing rowptr, colidx out of
                                       range, or (full check) a duplicate entry      */
-  RCM_ERR_NOT_SYMMETRIC = 3,       /* full check only: (i,j) present without (j,i)  */
+  RCM_ERR_NOT_SYMMETRIC = 3,       /* (i,j) present without (j,i): always when a
+                                      traversal leaves its component's label block,
+                                      exhaustively with check_full                  */
   RCM_ERR_WORKSPACE_TOO_SMALL = 4, /* caller workspace below rcm_workspace_bytes()  */
   RCM_ERR_OUT_OF_MEMORY = 5,       /* internal device allocation failed             */
   RCM_ERR_ABORTED = 6,             /* a device-side wait exceeded its spin limit    */
@@ -178,13 +180,15 @@ typedef struct {
   float team_label_ms;   /* device clock of that launch: labelled BFS */
   int32_t team_pp_levels;    /* levels expanded by the pseudo-peripheral passes */
   int32_t team_label_levels; /* levels of the labelled BFS */
-  int64_t phase_ticks[12];   /* diagnostics, 100 MHz device clock of work-group 0
+  int64_t phase_ticks[16];   /* diagnostics, 100 MHz device clock of work-group 0
                                 of the team launch: [0..3] wide unlabelled levels
                                 (expand, append, barrier ticks; level count);
                                 [4, 5] unlabelled levels of the LDS engine (ticks,
                                 count); [6, 7] one-work-group global unlabelled
                                 levels; [8, 9] wide labelled levels; [10, 11]
-                                labelled levels of the LDS engine               */
+                                labelled levels of the LDS engine; [12..15] wide
+                                labelled levels: count phase, first barrier,
+                                placement, claims and second barrier           */
 } rcm_timings;
 void rcm_last_timings(rcm_timings* out);
 

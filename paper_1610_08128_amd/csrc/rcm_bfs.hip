@@ -1135,8 +1135,10 @@ __device__ __forceinline__ void global_label_level(const BfsParams& P, Team& t, 
     const long long tot = block_sum_i64(wg_total, S.red);
     if (threadIdx.x == 0) st_relaxed(&t.ctl->wg_sum[wid], static_cast<int32_t>(tot));
   }
+  const long long t1 = wall_clock64();
   team_barrier(t, S, solo);
   if (t.aborted) return;
+  const long long t2 = wall_clock64();
   if (threadIdx.x < W) S.wsum[threadIdx.x] = ld_relaxed(&t.ctl->wg_sum[threadIdx.x]);
   __syncthreads();
   int32_t prefix = 0, total = 0;
@@ -1192,6 +1194,7 @@ __device__ __forceinline__ void global_label_level(const BfsParams& P, Team& t, 
   }
   // (A) for the next level: every listed child claims its neighbours
   __syncthreads();
+  const long long t3 = wall_clock64();
   for (int32_t i = threadIdx.x; i < list_len; i += B) {
     const int4 c = reinterpret_cast<const int4*>(S.u.srec)[i];
     claim_row(P, c.x, make_int4(c.y, c.z, 0, 0), static_cast<uint32_t>(c.w));
@@ -1199,8 +1202,13 @@ __device__ __forceinline__ void global_label_level(const BfsParams& P, Team& t, 
   team_barrier(t, S, solo);
   if (t.aborted) return;
   if (t.wid == 0 && threadIdx.x == 0 && !solo) {
-    t.ctl->clk[12] += wall_clock64() - ta;
+    const long long t4 = wall_clock64();
+    t.ctl->clk[12] += t4 - ta;
     t.ctl->clk[13] += 1;
+    t.ctl->clk[16] += t1 - ta;
+    t.ctl->clk[17] += t2 - t1;
+    t.ctl->clk[18] += t3 - t2;
+    t.ctl->clk[19] += t4 - t3;
   }
   cur_b = cur_e;
   cur_e += total;
