@@ -873,11 +873,57 @@ __device__ __forceinline__ void defer_claims(const BfsParams& P, Shared& S, int3
 }
 
 // Children of parent p (vertex u, row [a, b)) ranked by (degree, id) among
-// the siblings, for rows longer than a register batch.
+// the siblings, for rows longer than a register batch.  One pass over the row
+// collects the keys of up to four children in registers (placed by
+// predicated selects, no indexed register access); they are ranked there and
+// their records fetched together.  A parent with more children ranks each
+// one against the whole row.
 __device__ __forceinline__ void place_long_row(const BfsParams& P, Shared& S, int32_t p, int32_t u,
                                                int32_t a, int32_t b, int32_t base, int32_t end,
                                                int32_t list_base, long long& my_m) {
   const uint32_t pl = static_cast<uint32_t>(p);
+  constexpr int kKids = 4;  // children ranked in registers
+  uint64_t ck[kKids];
+#pragma unroll
+  for (int i = 0; i < kKids; ++i) ck[i] = kMaxKey;
+  int nc = 0;
+  for (int32_t k0 = a; k0 < b; k0 += kRB) {
+    int32_t nb[kRB];
+    load_batch(P.colidx, k0, b, u, nb);
+    uint32_t cl[kRB];
+    int32_t dg[kRB];
+#pragma unroll
+    for (int j = 0; j < kRB; ++j) cl[j] = P.claim[nb[j]];
+#pragma unroll
+    for (int j = 0; j < kRB; ++j) dg[j] = P.vinfo[nb[j]].z;
+#pragma unroll
+    for (int j = 0; j < kRB; ++j) {
+      const bool child = nb[j] != u && cl[j] == pl;
+      const uint64_t kv = pack_key(dg[j], nb[j]);
+#pragma unroll
+      for (int i = 0; i < kKids; ++i) ck[i] = (child && i == nc) ? kv : ck[i];
+      nc += child ? 1 : 0;
+    }
+  }
+  if (nc <= kKids) {
+    int4 inf[kKids];
+#pragma unroll
+    for (int i = 0; i < kKids; ++i)
+      inf[i] = P.vinfo[i < nc ? static_cast<int32_t>(ck[i] & 0xffffffffu) : u];
+#pragma unroll
+    for (int i = 0; i < kKids; ++i) {
+      if (i >= nc) continue;
+      int rank = 0;
+#pragma unroll
+      for (int x = 0; x < kKids; ++x) rank += ck[x] < ck[i] ? 1 : 0;
+      const int32_t v = static_cast<int32_t>(ck[i] & 0xffffffffu);
+      const int32_t at = base + rank;
+      if (at < end) st_rec(&P.qi[at], record(v, inf[i]));
+      my_m += inf[i].z;
+      defer_claims(P, S, v, inf[i], at, list_base);
+    }
+    return;
+  }
   for (int32_t k0 = a; k0 < b; k0 += kRB) {
     int32_t nb[kRB];
     load_batch(P.colidx, k0, b, u, nb);
