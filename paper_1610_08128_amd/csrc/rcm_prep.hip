@@ -155,9 +155,23 @@ __device__ __forceinline__ int32_t uf_find(int32_t* parent, int32_t x) {
   }
 }
 
-__global__ void k_cc_init(int32_t n, int32_t* __restrict__ parent) {
-  for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-    parent[i] = i;
+// Union-find start: every vertex points at the smallest of itself and its
+// neighbours (skipped vertices and edges into them excluded).  That is
+// already a forest inside the components -- every link goes to a smaller id
+// in the same component -- and most vertices start next to their root.
+__global__ void k_cc_init(int32_t n, const int32_t* __restrict__ rowptr,
+                          const int32_t* __restrict__ colidx, const int32_t* __restrict__ skip,
+                          int32_t* __restrict__ parent) {
+  for (int32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += gridDim.x * blockDim.x) {
+    int32_t m = u;
+    if (!(skip && skip[u] != 0)) {
+      for (int32_t k = rowptr[u]; k < rowptr[u + 1]; ++k) {
+        const int32_t v = colidx[k];
+        if (v < m && !(skip && skip[v] != 0)) m = v;
+      }
+    }
+    parent[u] = m;
+  }
 }
 
 __global__ void k_cc_hook(int32_t n, const int32_t* __restrict__ rowptr,
@@ -165,6 +179,8 @@ __global__ void k_cc_hook(int32_t n, const int32_t* __restrict__ rowptr,
                           int32_t* parent, int32_t* __restrict__ err) {
   for (int32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += gridDim.x * blockDim.x) {
     if (skip && skip[u] != 0) continue;
+    // root of u, found once and kept while it stays u's root
+    int32_t a = uf_find(parent, u);
     for (int32_t k = rowptr[u]; k < rowptr[u + 1]; ++k) {
       const int32_t v = colidx[k];
       // a skipped (already ordered) component is closed under adjacency in a
@@ -174,8 +190,9 @@ __global__ void k_cc_hook(int32_t n, const int32_t* __restrict__ rowptr,
         continue;
       }
       if (v >= u) continue;  // each undirected edge once
-      int32_t a = uf_find(parent, u);
       int32_t b = uf_find(parent, v);
+      if (a == b) continue;
+      a = uf_find(parent, a);  // a may have been hooked meanwhile
       while (a != b) {
         if (a < b) { const int32_t t = a; a = b; b = t; }
         // hook the larger root a under the smaller root b
@@ -410,17 +427,34 @@ __global__ void k_singletons(const CompTask* __restrict__ tasks, int32_t count,
 // ---------------------------------------------------------------------------
 // Result statistics.
 // ---------------------------------------------------------------------------
+// beta of the result, row by row in the input order (so rowptr and colidx
+// stream): the row of vertex u becomes row iperm[u]; its beta is that index
+// minus the smallest new index among u's neighbours (the diagonal counts as
+// present).  Rows are read in batches of eight with clamped loads so that the
+// batch's gathers of new indices are in flight together.
 __global__ void k_beta_after(int32_t n, const int32_t* __restrict__ rowptr,
-                             const int32_t* __restrict__ colidx, const int32_t* __restrict__ perm,
+                             const int32_t* __restrict__ colidx,
                              const int32_t* __restrict__ iperm, int32_t* __restrict__ beta) {
-  for (int32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
-    const int32_t v = perm[k];
-    int32_t f = k;
-    for (int32_t e = rowptr[v]; e < rowptr[v + 1]; ++e) {
-      const int32_t j = iperm[colidx[e]];
-      f = j < f ? j : f;
+  constexpr int R = 8;
+  for (int32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += gridDim.x * blockDim.x) {
+    const int32_t i = iperm[u];
+    const int32_t a = rowptr[u], b = rowptr[u + 1];
+    int32_t f = i;
+    for (int32_t k0 = a; k0 < b; k0 += R) {
+      int32_t c[R];
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        const int32_t k = k0 + j < b ? k0 + j : b - 1;
+        const int32_t v = colidx[k];
+        c[j] = k0 + j < b ? v : u;
+      }
+      int32_t x[R];
+#pragma unroll
+      for (int j = 0; j < R; ++j) x[j] = iperm[c[j]];
+#pragma unroll
+      for (int j = 0; j < R; ++j) f = x[j] < f ? x[j] : f;
     }
-    beta[k] = k - f;
+    beta[i] = i - f;
   }
 }
 
@@ -513,7 +547,7 @@ hipError_t launch_components(const Graph& g, const int32_t* skip, int32_t* paren
                              int32_t* flags, int32_t* scan_tmp, int32_t* seeds,
                              int32_t* num_comps, int32_t* err_asym, hipStream_t s) {
   const int nb = grid_for(g.n, kThreads);
-  k_cc_init<<<nb, kThreads, 0, s>>>(g.n, parent);
+  k_cc_init<<<nb, kThreads, 0, s>>>(g.n, g.rowptr, g.colidx, skip, parent);
   k_cc_hook<<<nb, kThreads, 0, s>>>(g.n, g.rowptr, g.colidx, skip, parent, err_asym);
   k_cc_compress<<<nb, kThreads, 0, s>>>(g.n, parent, skip, flags);
   hipError_t e = hipMemsetAsync(csize, 0, sizeof(int32_t) * static_cast<size_t>(g.n), s);
@@ -561,8 +595,8 @@ hipError_t launch_singletons(const CompTask* tasks, int32_t count, int32_t* perm
 
 hipError_t launch_bw_after(const Graph& g, const int32_t* perm, const int32_t* iperm,
                            int32_t* beta, SegStats* seg, hipStream_t s) {
-  k_beta_after<<<grid_for(g.n, kThreads), kThreads, 0, s>>>(g.n, g.rowptr, g.colidx, perm, iperm,
-                                                            beta);
+  (void)perm;
+  k_beta_after<<<grid_for(g.n, kThreads), kThreads, 0, s>>>(g.n, g.rowptr, g.colidx, iperm, beta);
   constexpr int32_t chunk = 8192;
   const int nb = (g.n + chunk - 1) / chunk;
   k_seg_reduce<<<nb, kThreads, 0, s>>>(beta, g.n, chunk, g.seg_off, g.nseg, seg, 1);
