@@ -201,3 +201,50 @@ def rcm(n, rowptr, colidx, *, pp_variant=0, reverse_mode=0, full_check=False,
     nn = n if status == OK else 0
     return OracleResult(int(status), perm[:nn].copy(), iperm[:nn].copy(), stats,
                         co[:nc].copy(), cr[:nc].copy(), cb[:nc].copy(), cl[:nc].copy())
+
+
+# ---------------------------------------------------------------------------
+# Applying an ordering (the reordered matrix and the product an iterative
+# solver spends its time in; the paper motivates the ordering by the data
+# locality it gives such solvers, Section I).  Plain definitions, in numpy.
+# ---------------------------------------------------------------------------
+
+def permute_csr(n, rowptr, colidx, perm, vals=None):
+    """B = P A P^T: row k of B is row perm[k] of A with every column j
+    renamed iperm[j] (iperm the inverse of perm), entries sorted by column.
+    Returns (rowptr_B, colidx_B, vals_B or None)."""
+    n = int(n)
+    rp = np.asarray(rowptr, dtype=np.int64)
+    ci = np.asarray(colidx, dtype=np.int64)
+    perm = np.asarray(perm, dtype=np.int64)
+    iperm = np.empty(n, dtype=np.int64)
+    iperm[perm] = np.arange(n, dtype=np.int64)
+    out_rp = np.zeros(n + 1, dtype=np.int64)
+    rows, vrows = [], []
+    for k in range(n):
+        v = perm[k]
+        cols = iperm[ci[rp[v]:rp[v + 1]]]
+        order = np.argsort(cols, kind="stable")
+        rows.append(cols[order])
+        if vals is not None:
+            vrows.append(np.asarray(vals, dtype=np.float64)[rp[v]:rp[v + 1]][order])
+        out_rp[k + 1] = out_rp[k] + cols.size
+    out_ci = np.concatenate(rows) if rows else np.zeros(0, np.int64)
+    out_v = (np.concatenate(vrows) if vrows else np.zeros(0)) if vals is not None else None
+    return out_rp.astype(np.int32), out_ci.astype(np.int32), out_v
+
+
+def spmv(n, rowptr, colidx, x, vals=None):
+    """y = A x in float64, each row summed in storage order (vals None:
+    every stored entry is 1)."""
+    n = int(n)
+    x = np.asarray(x, dtype=np.float64)
+    y = np.zeros(n, dtype=np.float64)
+    for i in range(n):
+        a, b = int(rowptr[i]), int(rowptr[i + 1])
+        w = np.ones(b - a) if vals is None else np.asarray(vals[a:b], dtype=np.float64)
+        s = 0.0
+        for t in range(b - a):
+            s += w[t] * x[int(colidx[a + t])]
+        y[i] = s
+    return y

@@ -1,0 +1,189 @@
+// Applying an ordering (rcm_apply.h): the permuted matrix B = P A P^T with
+// sorted rows, and y = A x as a probe of the locality an ordering buys.
+//
+// Permutation: new row degrees are gathered and scanned into B's row
+// pointer; every row of A is copied to its new place with its columns
+// renamed by iperm; each row is then sorted by a segmented radix sort
+// (rocPRIM) over only as many key bits as n needs.
+// Product: a group of eight lanes per row (rows of meshes hold 5 to 13
+// entries), each lane striding the row, then a reduction across the group.
+
+#include "rcm_apply.h"
+
+#include <hip/hip_runtime.h>
+
+#include <rocprim/device/device_segmented_radix_sort.hpp>
+
+#include "rcm_common.hpp"
+
+namespace rcm {
+namespace {
+
+constexpr int kThreads = 256;
+
+inline size_t align_up(size_t x) { return (x + 255) / 256 * 256; }
+
+inline int grid_for(int64_t work, int threads, int max_blocks = 8192) {
+  int64_t b = (work + threads - 1) / threads;
+  if (b < 1) b = 1;
+  if (b > max_blocks) b = max_blocks;
+  return static_cast<int>(b);
+}
+
+inline unsigned key_bits(int32_t n) {
+  unsigned b = 1;
+  while (b < 31 && (1ll << b) < n) ++b;
+  return b;
+}
+
+// Workspace regions of rcm_permute.
+struct ApplyLayout {
+  size_t deg, blk, keys, vals, sort, total;
+  size_t sort_bytes;
+};
+
+ApplyLayout apply_layout(int32_t n, int64_t nnz, bool with_values) {
+  ApplyLayout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off += align_up(bytes);
+    return at;
+  };
+  const size_t N = static_cast<size_t>(n), M = static_cast<size_t>(nnz);
+  L.deg = take(4 * N);
+  L.blk = take(4 * (N / 4096 + 2));
+  L.keys = take(4 * M);
+  L.vals = with_values ? take(8 * M) : 0;
+  size_t sort_bytes = 0;
+  const int32_t* off_dummy = nullptr;
+  if (with_values) {
+    (void)rocprim::segmented_radix_sort_pairs(
+        nullptr, sort_bytes, static_cast<const int32_t*>(nullptr), static_cast<int32_t*>(nullptr),
+        static_cast<const double*>(nullptr), static_cast<double*>(nullptr),
+        static_cast<unsigned>(M), static_cast<unsigned>(N), off_dummy, off_dummy, 0,
+        key_bits(n));
+  } else {
+    (void)rocprim::segmented_radix_sort_keys(
+        nullptr, sort_bytes, static_cast<const int32_t*>(nullptr), static_cast<int32_t*>(nullptr),
+        static_cast<unsigned>(M), static_cast<unsigned>(N), off_dummy, off_dummy, 0,
+        key_bits(n));
+  }
+  L.sort_bytes = sort_bytes;
+  L.sort = take(sort_bytes);
+  L.total = off;
+  return L;
+}
+
+__global__ void k_new_degrees(int32_t n, const int32_t* __restrict__ rowptr,
+                              const int32_t* __restrict__ perm, int32_t* __restrict__ deg) {
+  for (int32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+    const int32_t v = perm[k];
+    deg[k] = rowptr[v + 1] - rowptr[v];
+  }
+}
+
+// Row k of B before sorting: row perm[k] of A, columns renamed.
+__global__ void k_move_rows(int32_t n, const int32_t* __restrict__ rowptr,
+                            const int32_t* __restrict__ colidx, const double* __restrict__ vals,
+                            const int32_t* __restrict__ perm, const int32_t* __restrict__ iperm,
+                            const int32_t* __restrict__ rowptr_out, int32_t* __restrict__ keys,
+                            double* __restrict__ vals_tmp) {
+  for (int32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+    const int32_t v = perm[k];
+    const int32_t a = rowptr[v], b = rowptr[v + 1];
+    const int32_t o = rowptr_out[k];
+    for (int32_t e = a; e < b; ++e) {
+      keys[o + (e - a)] = iperm[colidx[e]];
+      if (vals) vals_tmp[o + (e - a)] = vals[e];
+    }
+  }
+}
+
+constexpr int kGroup = 8;  // lanes per row in the product
+
+__global__ void __launch_bounds__(256) k_spmv(int32_t n, const int32_t* __restrict__ rowptr,
+                                              const int32_t* __restrict__ colidx,
+                                              const double* __restrict__ vals,
+                                              const double* __restrict__ x,
+                                              double* __restrict__ y) {
+  const int lane = threadIdx.x % kGroup;
+  const int64_t groups = static_cast<int64_t>(gridDim.x) * (blockDim.x / kGroup);
+  for (int64_t row = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) / kGroup;
+       row < n; row += groups) {
+    const int32_t a = rowptr[row], b = rowptr[row + 1];
+    double s = 0.0;
+    for (int32_t e = a + lane; e < b; e += kGroup) {
+      const double w = vals ? vals[e] : 1.0;
+      s = fma(w, x[colidx[e]], s);
+    }
+#pragma unroll
+    for (int off = kGroup / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, kGroup);
+    if (lane == 0) y[row] = s;
+  }
+}
+
+}  // namespace
+}  // namespace rcm
+
+using namespace rcm;
+
+extern "C" {
+
+size_t rcm_permute_workspace_bytes(int32_t n, int64_t nnz, int32_t with_values) {
+  if (n <= 0 || nnz < 0 || nnz >= (1ll << 31) - 1) return 0;
+  return apply_layout(n, nnz, with_values != 0).total;
+}
+
+rcm_status rcm_permute(int32_t n, int64_t nnz, const int32_t* rowptr, const int32_t* colidx,
+                       const double* vals, const int32_t* perm, const int32_t* iperm,
+                       int32_t* rowptr_out, int32_t* colidx_out, double* vals_out,
+                       void* workspace, size_t workspace_bytes, void* stream) {
+  if (n < 0 || nnz < 0 || nnz >= (1ll << 31) - 1) return RCM_ERR_INVALID_ARGUMENT;
+  if (n == 0) return RCM_OK;
+  if (!rowptr || !perm || !iperm || !rowptr_out || (nnz > 0 && (!colidx || !colidx_out)))
+    return RCM_ERR_INVALID_ARGUMENT;
+  if (vals && !vals_out) return RCM_ERR_INVALID_ARGUMENT;
+  const ApplyLayout L = apply_layout(n, nnz, vals != nullptr);
+  if (!workspace || workspace_bytes < L.total) return RCM_ERR_WORKSPACE_TOO_SMALL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* ws = static_cast<char*>(workspace);
+  int32_t* deg = reinterpret_cast<int32_t*>(ws + L.deg);
+  int32_t* blk = reinterpret_cast<int32_t*>(ws + L.blk);
+  int32_t* keys = reinterpret_cast<int32_t*>(ws + L.keys);
+  double* vtmp = vals ? reinterpret_cast<double*>(ws + L.vals) : nullptr;
+  void* sort_tmp = ws + L.sort;
+  k_new_degrees<<<grid_for(n, kThreads), kThreads, 0, s>>>(n, rowptr, perm, deg);
+  if (hipGetLastError() != hipSuccess) return RCM_ERR_HIP;
+  if (launch_exclusive_scan(deg, rowptr_out, n, blk, rowptr_out + n, s) != hipSuccess)
+    return RCM_ERR_HIP;
+  if (nnz == 0) return RCM_OK;
+  k_move_rows<<<grid_for(n, kThreads), kThreads, 0, s>>>(n, rowptr, colidx, vals, perm, iperm,
+                                                        rowptr_out, keys, vtmp);
+  if (hipGetLastError() != hipSuccess) return RCM_ERR_HIP;
+  size_t sort_bytes = L.sort_bytes;
+  hipError_t e;
+  if (vals) {
+    e = rocprim::segmented_radix_sort_pairs(sort_tmp, sort_bytes, keys, colidx_out, vtmp, vals_out,
+                                            static_cast<unsigned>(nnz), static_cast<unsigned>(n),
+                                            rowptr_out, rowptr_out + 1, 0, key_bits(n), s);
+  } else {
+    e = rocprim::segmented_radix_sort_keys(sort_tmp, sort_bytes, keys, colidx_out,
+                                           static_cast<unsigned>(nnz), static_cast<unsigned>(n),
+                                           rowptr_out, rowptr_out + 1, 0, key_bits(n), s);
+  }
+  return e == hipSuccess ? RCM_OK : RCM_ERR_HIP;
+}
+
+rcm_status rcm_spmv(int32_t n, const int32_t* rowptr, const int32_t* colidx, const double* vals,
+                    const double* x, double* y, void* stream) {
+  if (n < 0) return RCM_ERR_INVALID_ARGUMENT;
+  if (n == 0) return RCM_OK;
+  if (!rowptr || !x || !y) return RCM_ERR_INVALID_ARGUMENT;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int blocks = grid_for(static_cast<int64_t>(n) * kGroup, kThreads, 1 << 16);
+  k_spmv<<<blocks, kThreads, 0, s>>>(n, rowptr, colidx, vals, x, y);
+  return hipGetLastError() == hipSuccess ? RCM_OK : RCM_ERR_HIP;
+}
+
+}  // extern "C"

@@ -13,6 +13,7 @@ from paper_1610_08128_amd import rcm
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "rcm.h")
 SERVER_HEADER = os.path.join(ROOT, "include", "rcm_server.h")
+APPLY_HEADER = os.path.join(ROOT, "include", "rcm_apply.h")
 
 
 def _declared_functions(path=HEADER):
@@ -34,13 +35,23 @@ def test_server_header_declares_the_documented_entry_points():
 
 def test_library_exports_every_declared_symbol():
     L = rcm.lib()
-    declared = _declared_functions() + _declared_functions(SERVER_HEADER)
+    declared = (_declared_functions() + _declared_functions(SERVER_HEADER)
+                + _declared_functions(APPLY_HEADER))
     for name in declared:
         assert hasattr(L, name), name
     out = subprocess.run(["nm", "-D", "--defined-only", rcm.LIB_PATH], capture_output=True,
                          text=True, check=True).stdout
     exported = set(re.findall(r" T (rcm_[a-z_]+)", out))
     assert set(declared) <= exported
+
+
+def test_apply_header_declares_the_documented_entry_points():
+    from paper_1610_08128_amd import apply
+
+    assert _declared_functions(APPLY_HEADER) == sorted(apply.APPLY_EXPORTED)
+    assert apply.permute_workspace_bytes(0, 0) == 0
+    assert 0 < apply.permute_workspace_bytes(1000, 7000) < apply.permute_workspace_bytes(
+        1000, 7000, with_values=True)
 
 
 def test_server_config_checks_need_no_gpu():
