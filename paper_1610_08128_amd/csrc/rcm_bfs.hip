@@ -102,6 +102,8 @@ struct Shared {
   unsigned long long carr[2];
   unsigned long long crest[2];
   int32_t wsum[kMaxTeam];
+  int32_t wpre;                    // team_counts: this work-group's prefix
+  int32_t wtot;                    // team_counts: the team's total
   int32_t state[8];
 };
 
@@ -201,6 +203,20 @@ __device__ __forceinline__ void narrow_wait(Team& t, Shared& S) {
   }
   __syncthreads();
   t.aborted = S.flag != 0;
+}
+
+// The W per-work-group counts published in ctl->wg_sum (read after a team
+// barrier): S.wsum holds them, S.wpre the sum over work-groups before wid,
+// S.wtot the sum over all.  One wave scans them.
+__device__ __forceinline__ void team_counts(Team& t, Shared& S, int W, int wid) {
+  if (threadIdx.x < 64) {
+    const int32_t c = static_cast<int>(threadIdx.x) < W ? ld_relaxed(&t.ctl->wg_sum[threadIdx.x]) : 0;
+    const int32_t incl = wave_incl_scan(c);
+    if (static_cast<int>(threadIdx.x) < W) S.wsum[threadIdx.x] = c;
+    if (static_cast<int>(threadIdx.x) == wid) S.wpre = incl - c;
+    if (threadIdx.x == 63) S.wtot = incl;
+  }
+  __syncthreads();
 }
 
 // Split [b, e) into W contiguous chunks; chunk of work-group wid.
@@ -734,10 +750,8 @@ __device__ __forceinline__ void own_bfs_levels(const BfsParams& P, Team& t, Shar
       if (threadIdx.x == 0) st_relaxed(&t.ctl->wg_sum[t.wid], own_n);
       team_barrier(t, S, false);
       if (t.aborted) return;
-      if (threadIdx.x < t.W) S.wsum[threadIdx.x] = ld_relaxed(&t.ctl->wg_sum[threadIdx.x]);
-      __syncthreads();
-      int32_t prefix = 0;
-      for (int w = 0; w < t.wid; ++w) prefix += S.wsum[w];
+      team_counts(t, S, t.W, t.wid);
+      const int32_t prefix = S.wpre;
       for (int32_t i = threadIdx.x; i < own_n; i += B) {
         const int32_t at = g_e + prefix + i;
         if (at < end)
@@ -1185,13 +1199,9 @@ __device__ __forceinline__ void global_label_level(const BfsParams& P, Team& t, 
   team_barrier(t, S, solo);
   if (t.aborted) return;
   const long long t2 = wall_clock64();
-  if (threadIdx.x < W) S.wsum[threadIdx.x] = ld_relaxed(&t.ctl->wg_sum[threadIdx.x]);
-  __syncthreads();
-  int32_t prefix = 0, total = 0;
-  for (int w = 0; w < W; ++w) {
-    prefix += w < wid ? S.wsum[w] : 0;
-    total += S.wsum[w];
-  }
+  team_counts(t, S, W, wid);
+  const int32_t prefix = S.wpre;
+  const int32_t total = S.wtot;
   if (total == 0) {
     done = true;
     return;
