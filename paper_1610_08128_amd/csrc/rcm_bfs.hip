@@ -104,6 +104,10 @@ struct Shared {
   int32_t wsum[kMaxTeam];
   int32_t wpre;                    // team_counts: this work-group's prefix
   int32_t wtot;                    // team_counts: the team's total
+  int32_t wmax;                    // team_counts: the largest count
+  int32_t lown_base;               // wide labelled level: the label range of the
+  int32_t lown_len;                // children this work-group placed (its list
+  int32_t lown_ok;                 // in srec), valid when it holds them all
   int32_t state[8];
 };
 
@@ -212,9 +216,16 @@ __device__ __forceinline__ void team_counts(Team& t, Shared& S, int W, int wid) 
   if (threadIdx.x < 64) {
     const int32_t c = static_cast<int>(threadIdx.x) < W ? ld_relaxed(&t.ctl->wg_sum[threadIdx.x]) : 0;
     const int32_t incl = wave_incl_scan(c);
+    int32_t mx = c;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const int32_t y = __shfl_xor(mx, o, 64);
+      mx = y > mx ? y : mx;
+    }
     if (static_cast<int>(threadIdx.x) < W) S.wsum[threadIdx.x] = c;
     if (static_cast<int>(threadIdx.x) == wid) S.wpre = incl - c;
     if (threadIdx.x == 63) S.wtot = incl;
+    if (threadIdx.x == 0) S.wmax = mx;
   }
   __syncthreads();
 }
@@ -1152,12 +1163,21 @@ __device__ __forceinline__ bool lds_label_levels(const BfsParams& P, Team& t, Sh
 // neighbours for the next level; barrier.
 __device__ __forceinline__ void global_label_level(const BfsParams& P, Team& t, Shared& S, int32_t end, bool solo,
                                    int32_t& cur_b, int32_t& cur_e, int32_t& levels, bool& done,
-                                   long long& my_m) {
+                                   long long& my_m, bool own = false) {
   const int B = blockDim.x;
   const int W = solo ? 1 : t.W;
   const int wid = solo ? 0 : t.wid;
+  // own: this work-group's parents are the children it placed at the
+  // previous level, a contiguous label range whose records are still in its
+  // LDS list; else an even chunk of the level, read from qi
+  const bool use_own = own && !solo && S.lown_ok != 0;
   int32_t lo, hi;
-  my_chunk(cur_b, cur_e, W, wid, lo, hi);
+  if (use_own) {
+    lo = S.lown_base;
+    hi = lo + S.lown_len;
+  } else {
+    my_chunk(cur_b, cur_e, W, wid, lo, hi);
+  }
   const long long ta = wall_clock64();
   const bool one_round = hi - lo <= B;
   bool captured = false;
@@ -1167,7 +1187,13 @@ __device__ __forceinline__ void global_label_level(const BfsParams& P, Team& t, 
   unsigned cmask = 0;
   int wg_total = 0;
   for (int32_t p = lo + threadIdx.x; p < hi; p += B) {
-    const int4 e = ld_rec(P, p);
+    int4 e;
+    if (use_own) {
+      const int4 c = reinterpret_cast<const int4*>(S.u.srec)[p - lo];
+      e = make_int4(c.x, c.y, c.z, 0);
+    } else {
+      e = ld_rec(P, p);
+    }
     const int32_t u = e.x;
     const uint32_t pl = static_cast<uint32_t>(p);
     int c;
@@ -1255,6 +1281,14 @@ __device__ __forceinline__ void global_label_level(const BfsParams& P, Team& t, 
     const int4 c = reinterpret_cast<const int4*>(S.u.srec)[i];
     claim_row(P, c.x, make_int4(c.y, c.z, 0, 0), static_cast<uint32_t>(c.w));
   }
+  if (threadIdx.x == 0) {
+    // the lists serve as the next level's parents when every work-group's
+    // list holds all its children (the same decision in every work-group:
+    // each has all the counts)
+    S.lown_base = list_base;
+    S.lown_len = S.wsum[wid];
+    S.lown_ok = (!solo && S.wmax <= kStageCap) ? 1 : 0;
+  }
   team_barrier(t, S, solo);
   if (t.aborted) return;
   if (t.wid == 0 && threadIdx.x == 0 && !solo) {
@@ -1332,8 +1366,11 @@ __device__ __forceinline__ int32_t label_pass(const BfsParams& P, Team& t, Share
       }
       continue;
     }
-    while (!done && (cur_e - cur_b) >= P.narrow_cutoff) {
-      global_label_level(P, t, S, end, false, cur_b, cur_e, levels, done, my_m);
+    // wide levels; every `rebalance` levels the parents are chunked evenly
+    // again instead of taken from each work-group's own list
+    for (int since = 0; !done && (cur_e - cur_b) >= P.narrow_cutoff; ++since) {
+      global_label_level(P, t, S, end, false, cur_b, cur_e, levels, done, my_m,
+                         since % P.rebalance != 0);
       if (t.aborted) return 0;
     }
   }
@@ -1454,8 +1491,10 @@ __global__ void __launch_bounds__(512) k_order(BfsParams P) {
   t.g = P.gctl;
   t.nbar = 0;
   t.woke = 0;
-  if (threadIdx.x == 0)
+  if (threadIdx.x == 0) {
     for (int i = 0; i < 2; ++i) S.carr[i] = S.crest[i] = 0;
+    S.lown_ok = 0;
+  }
   t.aborted = false;
   if (static_cast<int32_t>(blockIdx.x) < P.big_blocks) {
     t.W = P.team_size;
