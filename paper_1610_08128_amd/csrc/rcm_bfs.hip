@@ -411,7 +411,9 @@ __device__ __forceinline__ bool lds_bfs_levels(const BfsParams& P, Team& t, Shar
   }
   __syncthreads();
   int32_t nlev = 0;
+  long long e_clear = 0, e_expand = 0, e_reduce = 0, e_book = 0;
   while (true) {
+    const long long q0 = wall_clock64();
     const int nx = (level + 1) % 3;
     int32_t* key_ins = N.key[(level + 1) & 1];
     int32_t* key_clr = N.key[level & 1];
@@ -421,6 +423,7 @@ __device__ __forceinline__ bool lds_bfs_levels(const BfsParams& P, Team& t, Shar
       N.rows[(level + 2) % 3] = 0;
       N.kmin[(level + 2) % 3] = kMaxKey;
     }
+    const long long q1 = wall_clock64();
     uint64_t mykey = kMaxKey;
     for (int32_t i = threadIdx.x; i < len; i += B) {
       const int4 e = lds_rec(N, level & 1, i);
@@ -451,12 +454,18 @@ __device__ __forceinline__ bool lds_bfs_levels(const BfsParams& P, Team& t, Shar
         }
       }
     }
+    const long long q2 = wall_clock64();
     mykey = wave_min_u64(mykey);
     if ((threadIdx.x & 63) == 0 && mykey != kMaxKey) atomicMin(&N.kmin[nx], mykey);
     __syncthreads();
+    const long long q3 = wall_clock64();
     const int32_t cnt = N.cnt[nx];
     const int32_t rows = N.rows[nx];
     ++nlev;
+    e_clear += q1 - q0;
+    e_expand += q2 - q1;
+    e_reduce += q3 - q2;
+    e_book += wall_clock64() - q3;
     if (cnt == 0) {
       done = true;
       break;
@@ -484,6 +493,10 @@ __device__ __forceinline__ bool lds_bfs_levels(const BfsParams& P, Team& t, Shar
     st_relaxed(tail + (level + 1) % 3, 0);
     t.ctl->clk[8] += wall_clock64() - c0;
     t.ctl->clk[9] += nlev;
+    t.ctl->clk[20] += e_clear;
+    t.ctl->clk[21] += e_expand;
+    t.ctl->clk[22] += e_reduce;
+    t.ctl->clk[23] += e_book;
   }
   __syncthreads();
   return true;
