@@ -45,7 +45,7 @@ WORKLOADS = {
 # sources at the time of the measurement, so a changed kernel reports null.
 # Summaries with the commands: profiles/k_order_<workload>_hbm_counters.md.
 MEASURED_TRAFFIC = {
-    "grid3d_128x128x128": ("d9011a415e3d4571", 6500539965),
+    "grid3d_128x128x128": ("64f117eaf9c2c532", 5539835236),
 }
 KERNEL_SOURCES = ("paper_1610_08128_amd/csrc/rcm_bfs.hip",
                   "paper_1610_08128_amd/csrc/rcm_common.hpp")
