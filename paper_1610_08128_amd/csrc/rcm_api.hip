@@ -84,7 +84,7 @@ bool parse_options(const rcm_options* o, Opts* out, bool batched = false) {
 struct Layout {
   size_t vinfo, beta, parent, flags, pos, csize, seeds, visit, claim, qi, tmp, iperm;
   size_t sizes, offs, results, t_single, t_small, t_big, scan_blk;
-  size_t seg_off, comp_seg_off, segstats, gctl, teams, small_ctl, misc, sched;
+  size_t seg_off, comp_seg_off, segstats, gctl, teams, slots, small_ctl, misc, sched;
   size_t rowptr_g, colidx_g;
   size_t total;
 };
@@ -122,6 +122,7 @@ Layout make_layout(int64_t n, int64_t nnz, int64_t nseg, bool batched, int teams
   L.segstats = take(sizeof(SegStats) * static_cast<size_t>(nseg));
   L.gctl = take(sizeof(GlobalCtl));
   L.teams = take(sizeof(TeamCtl) * kMaxConcurrentTeams);
+  L.slots = take(sizeof(TeamSlots) * kMaxConcurrentTeams);
   L.small_ctl = take(sizeof(TeamCtl) * static_cast<size_t>(teams_small));
   L.misc = take(256);
   L.sched = take(128 * sizeof(int32_t));
@@ -257,6 +258,7 @@ rcm_status run(const Graph& gin, const int32_t* seg_off_host, const Opts& opt, c
   SegStats* segstats = reinterpret_cast<SegStats*>(ws + L.segstats);
   GlobalCtl* gctl = reinterpret_cast<GlobalCtl*>(ws + L.gctl);
   TeamCtl* teams = reinterpret_cast<TeamCtl*>(ws + L.teams);
+  TeamSlots* slots = reinterpret_cast<TeamSlots*>(ws + L.slots);
   TeamCtl* small_ctl = reinterpret_cast<TeamCtl*>(ws + L.small_ctl);
   int32_t* misc = reinterpret_cast<int32_t*>(ws + L.misc);  // [0..2] errors, [4] ncomp, [8..10] counts
   int32_t* sched = reinterpret_cast<int32_t*>(ws + L.sched);
@@ -306,6 +308,7 @@ rcm_status run(const Graph& gin, const int32_t* seg_off_host, const Opts& opt, c
   P.narrow_cutoff = opt.narrow_cutoff;
   P.rebalance = opt.rebalance;
   P.teams = teams;
+  P.slots = slots;
   P.small_teams = small_ctl;
   P.queues = misc + 16;
   P.team_size = opt.team_size;
@@ -338,7 +341,10 @@ rcm_status run(const Graph& gin, const int32_t* seg_off_host, const Opts& opt, c
     }
     if (blocks <= 0) return RCM_OK;
     HIP_TRY(hipMemsetAsync(P.queues, 0, 2 * sizeof(int32_t), s));
-    if (nteams > 0) HIP_TRY(hipMemsetAsync(teams, 0, sizeof(TeamCtl) * nteams, s));
+    if (nteams > 0) {
+      HIP_TRY(hipMemsetAsync(teams, 0, sizeof(TeamCtl) * nteams, s));
+      HIP_TRY(hipMemsetAsync(slots, 0, sizeof(TeamSlots) * nteams, s));
+    }
     if (n_small > 0) HIP_TRY(hipMemsetAsync(small_ctl, 0, sizeof(TeamCtl) * blocks, s));
     timer.kmark(kslot, true);
     HIP_TRY(launch_order(P, blocks, threads, s));

@@ -51,11 +51,12 @@ constexpr int kRB = 8;  // row batch: entries of a row loaded together
 
 struct Team {
   TeamCtl* ctl;
+  TeamSlots* slots;
   GlobalCtl* g;
   int W;
   int wid;
   int comp;                 // index of the component being ordered (diagnostics)
-  unsigned long long nbar;  // barrier arrivals expected so far (thread 0 only)
+  uint32_t seq;             // team barriers passed (every thread, in step)
   unsigned long long woke;  // narrow episodes seen (thread 0 only)
   bool aborted;
 };
@@ -96,15 +97,12 @@ struct Shared {
   int32_t spill;                   // own-frontier level: records went to qi
   int32_t total;                   // own-frontier level: next level size
   int32_t nspill;                  // own-frontier level: records in qi
-  // counting barriers (used by thread 0): arrivals expected so far, and the
-  // word's value above them (spills + 2^12 x found, in units of 2^20) when
-  // it last completed
-  unsigned long long carr[2];
-  unsigned long long crest[2];
+
   int32_t wsum[kMaxTeam];
   int32_t wpre;                    // team_counts: this work-group's prefix
   int32_t wtot;                    // team_counts: the team's total
   int32_t wmax;                    // team_counts: the largest count
+  int32_t wspill;                  // team_counts: work-groups that flagged a spill
   int32_t lown_base;               // wide labelled level: the label range of the
   int32_t lown_len;                // children this work-group placed (its list
   int32_t lown_ok;                 // in srec), valid when it holds them all
@@ -153,28 +151,91 @@ __device__ __forceinline__ void drain_memory_ops() {
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
+// Team barrier that also exchanges one 32-bit payload per work-group (bit 31
+// a flag, bits 0..30 a count): every work-group stores (barrier number,
+// payload) into its own slot, and lanes 0..W-1 of wave 0 each wait for one
+// work-group's slot.  Afterwards S.wsum[w] holds work-group w's count,
+// S.wpre the sum over work-groups before this one, S.wtot the total, S.wmax
+// the largest, S.wspill the number of flags.  drain: every wave first
+// completes its own memory operations (whatever another work-group reads
+// after the barrier was written with atomics or device-scope stores, so no
+// L2 write-back is needed); acquire: invalidate this CU's caches afterwards
+// so that plain loads see other work-groups' data.
+__device__ __forceinline__ void slot_exchange(Team& t, Shared& S, uint32_t payload, bool drain,
+                                              bool acquire) {
+  if (drain) drain_memory_ops();
+  __syncthreads();
+  t.seq += 1;
+  const uint32_t seq = t.seq;
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    unsigned long long* base = &t.slots->s[seq & 1][0][0];
+    if (lane == 0)
+      __hip_atomic_store(base + t.wid * 16, (static_cast<unsigned long long>(seq) << 32) | payload,
+                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    unsigned long long v = 0;
+    bool ok = true;
+    if (lane < t.W) {
+      long spins = 0;
+      const long long t0 = wall_clock64();
+      while (true) {
+        v = __hip_atomic_load(base + lane * 16, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (static_cast<uint32_t>(v >> 32) == seq) break;
+        if ((++spins & 255) == 0) {
+          if (ld_relaxed(&t.g->error) != 0) { ok = false; break; }
+          if (wall_clock64() - t0 > kWaitLimitTicks) {
+            flag_error(t.g, RCM_ERR_ABORTED);
+            ok = false;
+            break;
+          }
+        }
+      }
+    }
+    const bool all_ok = __all(ok);
+    const uint32_t p = lane < t.W ? static_cast<uint32_t>(v) : 0u;
+    const int32_t c = static_cast<int32_t>(p & 0x7FFFFFFFu);
+    const int32_t incl = wave_incl_scan(c);
+    int32_t mx = c;
+    int32_t fl = static_cast<int32_t>(p >> 31);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const int32_t y = __shfl_xor(mx, o, 64);
+      mx = y > mx ? y : mx;
+      fl += __shfl_xor(fl, o, 64);
+    }
+    if (lane < t.W) S.wsum[lane] = c;
+    if (lane == t.wid) S.wpre = incl - c;
+    if (lane == 63) S.wtot = incl;
+    if (lane == 0) {
+      S.wmax = mx;
+      S.wspill = fl;
+      S.flag = all_ok ? 0 : 1;
+      if (acquire && all_ok) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+  }
+  __syncthreads();
+  t.aborted = S.flag != 0;
+}
+
+// The same counts for a work-group alone.
+__device__ __forceinline__ void local_counts(Shared& S, int32_t c) {
+  if (threadIdx.x == 0) {
+    S.wsum[0] = c;
+    S.wpre = 0;
+    S.wtot = c;
+    S.wmax = c;
+    S.wspill = 0;
+  }
+  __syncthreads();
+}
+
 // Team barrier; `solo` = only this work-group is active (narrow mode or W=1).
-// What one work-group hands to another across it is written with atomics or
-// device-scope stores, so arriving needs only every wave's own operations
-// to have completed (no L2 write-back); leaving invalidates this CU's caches
-// (an agent-scope acquire) so that plain loads see the other work-groups'
-// data.
 __device__ __forceinline__ void team_barrier(Team& t, Shared& S, bool solo) {
   if (solo || t.W == 1) {
     __syncthreads();
     return;
   }
-  drain_memory_ops();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    t.nbar += static_cast<unsigned long long>(t.W);
-    __hip_atomic_fetch_add(&t.ctl->bar, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const bool ok = wait_at_least(t, &t.ctl->bar, t.nbar, false);
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    S.flag = ok ? 0 : 1;
-  }
-  __syncthreads();
-  t.aborted = S.flag != 0;
+  slot_exchange(t, S, 0u, true, true);
 }
 
 // Narrow mode hand-over.  Work-group 0 publishes the pass state and wakes
@@ -207,27 +268,6 @@ __device__ __forceinline__ void narrow_wait(Team& t, Shared& S) {
   }
   __syncthreads();
   t.aborted = S.flag != 0;
-}
-
-// The W per-work-group counts published in ctl->wg_sum (read after a team
-// barrier): S.wsum holds them, S.wpre the sum over work-groups before wid,
-// S.wtot the sum over all.  One wave scans them.
-__device__ __forceinline__ void team_counts(Team& t, Shared& S, int W, int wid) {
-  if (threadIdx.x < 64) {
-    const int32_t c = static_cast<int>(threadIdx.x) < W ? ld_relaxed(&t.ctl->wg_sum[threadIdx.x]) : 0;
-    const int32_t incl = wave_incl_scan(c);
-    int32_t mx = c;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      const int32_t y = __shfl_xor(mx, o, 64);
-      mx = y > mx ? y : mx;
-    }
-    if (static_cast<int>(threadIdx.x) < W) S.wsum[threadIdx.x] = c;
-    if (static_cast<int>(threadIdx.x) == wid) S.wpre = incl - c;
-    if (threadIdx.x == 63) S.wtot = incl;
-    if (threadIdx.x == 0) S.wmax = mx;
-  }
-  __syncthreads();
 }
 
 // Split [b, e) into W contiguous chunks; chunk of work-group wid.
@@ -692,7 +732,6 @@ __device__ __forceinline__ void own_bfs_levels(const BfsParams& P, Team& t, Shar
       __syncthreads();
     }
     if (threadIdx.x == 0) {
-      const int w = level & 1;
       if (t.wid == 0) {
         // slots two levels ahead: free now, needed again after the next barrier
         st_relaxed(tail + (level + 1) % 3, 0);
@@ -700,46 +739,24 @@ __device__ __forceinline__ void own_bfs_levels(const BfsParams& P, Team& t, Shar
                            __HIP_MEMORY_SCOPE_AGENT);
         drain_memory_ops();
       }
-      // the word is the exact sum of every arrival's add = 1 + 2^20 spilled
-      // + 2^32 found; with the arrivals known, the rest gives this level's
-      // spills and vertices
-      S.carr[w] += static_cast<unsigned long long>(t.W);
-      const unsigned long long add = 1ull + (spilled ? (1ull << 20) : 0ull) +
-                                     (static_cast<unsigned long long>(my_new) << 32);
-      __hip_atomic_fetch_add(&t.ctl->cbar[w], add, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      // the next level's minimum key is only read once the pass has ended,
+      // behind a full barrier
       if (S.key != kMaxKey) atomicMin(minkey + (level + 1) % 3, S.key);
-      long spins = 0;
-      const long long t0 = wall_clock64();
-      bool ok = true;
-      unsigned long long v;
-      while (true) {
-        v = __hip_atomic_load(&t.ctl->cbar[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (((v ^ S.carr[w]) & 0xFFFFFull) == 0) break;
-        if ((++spins & 255) == 0) {
-          if (ld_relaxed(&t.g->error) != 0) { ok = false; break; }
-          if (wall_clock64() - t0 > kWaitLimitTicks) {
-            flag_error(t.g, RCM_ERR_ABORTED);
-            ok = false;
-            break;
-          }
-        }
-      }
-      const unsigned long long rest = (v - S.carr[w]) >> 20;
-      const unsigned long long d = rest - S.crest[w];
-      S.crest[w] = rest;
-      const uint32_t nsp = static_cast<uint32_t>(d & 0xFFFull);   // < W spills per level
-      S.total = static_cast<int32_t>(static_cast<uint32_t>(d >> 12));
+    }
+    // the level's size travels with the arrival; a flag marks a spill to qi
+    slot_exchange(t, S, (spilled ? 0x80000000u : 0u) | static_cast<uint32_t>(my_new), false,
+                  false);
+    if (t.aborted) return;
+    if (threadIdx.x == 0) {
+      S.total = S.wtot;
       S.nspill = 0;
-      if (ok && nsp != 0) {
+      if (S.wspill != 0) {
         // some work-group spilled: its records are in qi
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         S.nspill = ld_relaxed(tail + l3);
       }
-      S.flag = ok ? 0 : 1;
     }
     __syncthreads();
-    t.aborted = S.flag != 0;
-    if (t.aborted) return;
     const int32_t total = S.total;
     const int32_t nspill = S.nspill;
     if (t.wid == 0 && threadIdx.x == 0) {
@@ -771,10 +788,8 @@ __device__ __forceinline__ void own_bfs_levels(const BfsParams& P, Team& t, Shar
     if (total < P.narrow_cutoff) {
       // hand the frontier to the narrow levels: own records after the
       // spilled ones, in work-group order
-      if (threadIdx.x == 0) st_relaxed(&t.ctl->wg_sum[t.wid], own_n);
-      team_barrier(t, S, false);
+      slot_exchange(t, S, static_cast<uint32_t>(own_n), true, true);
       if (t.aborted) return;
-      team_counts(t, S, t.W, t.wid);
       const int32_t prefix = S.wpre;
       for (int32_t i = threadIdx.x; i < own_n; i += B) {
         const int32_t at = g_e + prefix + i;
@@ -1230,15 +1245,17 @@ __device__ __forceinline__ void global_label_level(const BfsParams& P, Team& t, 
     c_mine = c;
     wg_total += c;
   }
-  {
-    const long long tot = block_sum_i64(wg_total, S.red);
-    if (threadIdx.x == 0) st_relaxed(&t.ctl->wg_sum[wid], static_cast<int32_t>(tot));
-  }
+  const long long tot = block_sum_i64(wg_total, S.red);
   const long long t1 = wall_clock64();
-  team_barrier(t, S, solo);
+  // the counts are all this barrier hands over: the count phase only read,
+  // and placement touches other labels and claims than it read
+  if (solo) {
+    local_counts(S, static_cast<int32_t>(tot));
+  } else {
+    slot_exchange(t, S, static_cast<uint32_t>(tot), false, false);
+  }
   if (t.aborted) return;
   const long long t2 = wall_clock64();
-  team_counts(t, S, W, wid);
   const int32_t prefix = S.wpre;
   const int32_t total = S.wtot;
   if (total == 0) {
@@ -1502,17 +1519,16 @@ __global__ void __launch_bounds__(512) k_order(BfsParams P) {
   __shared__ Shared S;
   Team t;
   t.g = P.gctl;
-  t.nbar = 0;
+  t.slots = nullptr;
+  t.seq = 0;
   t.woke = 0;
-  if (threadIdx.x == 0) {
-    for (int i = 0; i < 2; ++i) S.carr[i] = S.crest[i] = 0;
-    S.lown_ok = 0;
-  }
+  if (threadIdx.x == 0) S.lown_ok = 0;
   t.aborted = false;
   if (static_cast<int32_t>(blockIdx.x) < P.big_blocks) {
     t.W = P.team_size;
     t.wid = blockIdx.x % P.team_size;
     t.ctl = P.teams + blockIdx.x / P.team_size;
+    t.slots = P.slots + blockIdx.x / P.team_size;
     while (true) {
       if (t.wid == 0 && threadIdx.x == 0)
         st_relaxed(&t.ctl->task, atomicAdd(&P.queues[0], 1));
@@ -1530,7 +1546,6 @@ __global__ void __launch_bounds__(512) k_order(BfsParams P) {
   t.W = 1;
   t.wid = 0;
   t.ctl = P.small_teams + blockIdx.x;
-  t.nbar = 0;
   t.woke = 0;
   // the small list first, then whatever the teams have not taken yet of
   // the large one

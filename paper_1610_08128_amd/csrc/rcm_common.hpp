@@ -43,13 +43,6 @@ struct CompResult {
 // Control block of one team (zeroed before each launch).  Fields written by
 // different agents sit on separate 128-byte lines.
 struct alignas(128) TeamCtl {
-  unsigned long long bar;        // barrier arrivals (monotone)
-  unsigned long long pad0[15];
-  unsigned long long cbar[2];    // counting barriers of the own-frontier levels,
-                                 // alternating by level: bits 0..19 arrivals,
-                                 // 20..31 work-groups that spilled to qi, 32..63
-                                 // vertices found (all running sums, modular)
-  unsigned long long pad5[14];
   int32_t tail[6];               // append counters, [pass parity][level mod 3]
   int32_t pad1[26];
   unsigned long long minkey[6];  // min (deg << 32 | id) per level, same indexing
@@ -58,7 +51,6 @@ struct alignas(128) TeamCtl {
   unsigned long long pad3[15];
   int32_t narrow_state[8];       // frontier bounds handed back after narrow levels
   int32_t pad4[24];
-  int32_t wg_sum[kMaxTeam];      // per-WG counts of the current level
   long long msum;                // sum of degrees of the current component
   unsigned long long lastkey;    // min (deg << 32 | id) over the last level of a
                                  // labelled pass that also serves the search
@@ -67,6 +59,15 @@ struct alignas(128) TeamCtl {
                                  // [1] labelled ticks, [2] pp levels, [3] labelled
                                  // levels, [4..23] per-phase ticks
 
+};
+
+// Barrier slots of one team (zeroed before each launch): work-group w
+// arrives at barrier number q by storing (q << 32 | payload) into
+// s[q & 1][w][0]; each slot has a 128-byte line of its own.  Two sets, so a
+// work-group that has passed barrier q can arrive at q + 1 while others
+// still read q's payloads.
+struct alignas(128) TeamSlots {
+  unsigned long long s[2][kMaxTeam][16];
 };
 
 // Global control shared by all teams of one launch.
@@ -263,6 +264,7 @@ struct BfsParams {
   int32_t ntasks;
   CompResult* results;
   TeamCtl* teams;             // one per multi-work-group team
+  TeamSlots* slots;           // one per multi-work-group team
   TeamCtl* small_teams;       // one per block in single-work-group mode
   int32_t* queues;            // [0] next large task, [1] next small task (zeroed per launch)
   GlobalCtl* gctl;
