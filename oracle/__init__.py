@@ -180,7 +180,9 @@ def cm_from_root(n, rowptr, colidx, root, mode=0) -> np.ndarray:
 def rcm(n, rowptr, colidx, *, pp_variant=0, reverse_mode=0, full_check=False,
         cm_mode=0) -> OracleResult:
     """Whole ordering.  cm_mode 0 = Algorithm 1 queue, 1 = Algorithm 3
-    level-synchronous labelling."""
+    level-synchronous labelling, 2 = level order by id (no sort), 3 = level
+    order by (degree, id) (one global sort at the end); 2 and 3 are the
+    alternatives to per-level sorting named as future work in Section VI."""
     lib = _load()
     n = int(n)
     rp = _i32(rowptr) if rowptr is not None else None

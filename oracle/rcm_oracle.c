@@ -360,11 +360,50 @@ int32_t orc_cm_levelsync(const int32_t* rowptr, const int32_t* colidx, const int
 }
 
 /* ------------------------------------------------------------------------ */
+/* Level orders: the alternatives to per-level sorting that Section VI      */
+/* names as future work.  The component is labelled level by level of the   */
+/* level structure rooted at root; within a level the vertices follow       */
+/*   by_degree 0: increasing id (no sort: the order of the frontier vector) */
+/*   by_degree 1: increasing (degree, id) (one global sort at the end by    */
+/*                (level, degree, id); the parent label is not a key).      */
+/* level[] must be -1 on the component on entry and is -1 again on exit.    */
+/* Same output contract as orc_cm_queue.                                     */
+/* ------------------------------------------------------------------------ */
+
+int32_t orc_cm_level_order(const int32_t* rowptr, const int32_t* colidx, const int32_t* deg,
+                           int32_t root, int32_t base, int by_degree, int32_t* label,
+                           int32_t* cm, int32_t* level, int32_t* order, int32_t* nlevels)
+{
+    int32_t count = 0;
+    int32_t ecc = orc_level_structure(rowptr, colidx, root, level, order, &count);
+    orc_tuple* T = (orc_tuple*)malloc(sizeof(orc_tuple) * (size_t)(count > 0 ? count : 1));
+    if (!T) return -1;
+    for (int32_t i = 0; i < count; ++i) {
+        int32_t v = order[i];
+        T[i].key0 = level[v];
+        T[i].key1 = by_degree ? deg[v] : 0;
+        T[i].v = v;
+    }
+    /* lexicographic (level, degree or 0, id): the SortPerm comparison with
+     * the level in the parent label's place */
+    qsort(T, (size_t)count, sizeof(orc_tuple), cmp_tuple);
+    for (int32_t i = 0; i < count; ++i) {
+        label[T[i].v] = base + i;
+        cm[base + i] = T[i].v;
+    }
+    for (int32_t i = 0; i < count; ++i) level[order[i]] = -1;
+    free(T);
+    if (nlevels) *nlevels = ecc + 1;
+    return count;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Whole ordering.                                                          */
 /*   pp_variant   0 = Algorithm 2 root (default), 1 = Algorithm 4 pick      */
 /*   reverse_mode 0 = reverse each component's block (default), 1 = global  */
 /*   full_check   also reject duplicate entries and asymmetric patterns     */
-/*   cm_mode      0 = Algorithm 1 queue, 1 = Algorithm 3 level-synchronous  */
+/*   cm_mode      0 = Algorithm 1 queue, 1 = Algorithm 3 level-synchronous, */
+/*                2 = level order by id, 3 = level order by (degree, id)    */
 /* perm_out[k] = original vertex placed at position k (new -> old).         */
 /* Optional per-component outputs (each of capacity n, may be NULL):        */
 /*   comp_offset[c], comp_root[c], comp_nbfs[c], comp_levels[c].            */
@@ -410,6 +449,9 @@ int orc_rcm_ex(int32_t n, const int32_t* rowptr, const int32_t* colidx, int pp_v
         int32_t nlev = 0, got;
         if (cm_mode == 1)
             got = orc_cm_levelsync(rowptr, colidx, deg, r, nv, label, cm, parent, &nlev);
+        else if (cm_mode == 2 || cm_mode == 3)
+            got = orc_cm_level_order(rowptr, colidx, deg, r, nv, cm_mode == 3, label, cm, level,
+                                     order, &nlev);
         else
             got = orc_cm_queue(rowptr, colidx, deg, r, nv, label, cm, &nlev);
         if (got < 0) {
@@ -425,7 +467,11 @@ int orc_rcm_ex(int32_t n, const int32_t* rowptr, const int32_t* colidx, int pp_v
         local.num_bfs += nbfs;
         local.num_levels += nlev;
         if (nlev - 1 > local.pseudo_diameter) local.pseudo_diameter = nlev - 1;
-        local.edges_traversed += (int64_t)(nbfs + 1) * m_c;
+        /* the labelled BFS scans the component once more; a level order
+         * reuses the search's last level structure, unless the root is
+         * Algorithm 4's pick, whose level structure is one more BFS */
+        int extra = (cm_mode == 2 || cm_mode == 3) ? (pp_variant == 1 ? 1 : 0) : 1;
+        local.edges_traversed += (int64_t)(nbfs + extra) * m_c;
         /* reverse this component's block (return of Algorithm 3) */
         if (reverse_mode == 0)
             for (int32_t t = 0; t < got; ++t) perm_out[nv + t] = cm[nv + got - 1 - t];
