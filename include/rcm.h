@@ -75,13 +75,17 @@ typedef struct {
   int64_t edges_traversed;  /* sum over components of (num_bfs + 1) * (directed
                                off-diagonal entries of the component): the
                                entries scanned by every level structure of the
-                               pseudo-peripheral search plus the labelled BFS */
+                               pseudo-peripheral search plus the labelled BFS
+                               (label_mode 1 and 2 with pp_variant 0: num_bfs
+                               times, as no labelled BFS runs)                 */
   int32_t num_components;   /* connected components (isolated vertices count) */
   int32_t pseudo_diameter;  /* max over components of the root's eccentricity */
   int32_t num_bfs;          /* level structures computed by the pseudo-peripheral
                                search (Algorithm 2), summed over components;
                                an isolated vertex counts 2                     */
-  int32_t num_levels;       /* levels of the labelled BFS, summed over comps  */
+  int32_t num_levels;       /* levels of the labelled BFS (of the root's level
+                               structure with label_mode 1 and 2), summed over
+                               components                                    */
 } rcm_stats;
 
 /* Options.  Zero-initialised options select every default. */
@@ -115,7 +119,21 @@ typedef struct {
                             share of the frontier in LDS and redistribute it
                             evenly every this many levels; 0 = auto (8),
                             1 = every level                                    */
-  int32_t reserved[6];
+  int32_t label_mode;    /* how each level's vertices are ordered (the
+                            alternatives to per-level sorting that Section VI
+                            names as future work):
+                            0: per-level SortPerm by (parent label, degree,
+                               id), Algorithm 3 (default)
+                            1: no sort: each level in increasing vertex id,
+                               the order the frontier vector holds it in
+                            2: one global sort at the end by (level, degree,
+                               id), the parent key dropped
+                            1 and 2 take the levels from the last level
+                            structure of the root search (one more from the
+                            returned vertex with pp_variant 1) and skip the
+                            labelled BFS; the result is still reversed per
+                            reverse_mode.                                      */
+  int32_t reserved[5];
 } rcm_options;
 
 /* Human-readable name of a status code (static string). */

@@ -18,7 +18,8 @@ INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(PKG, "librcm.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["rcm_prep.hip", "rcm_bfs.hip", "rcm_api.hip", "rcm_server.hip", "rcm_apply.hip"]
+SOURCES = ["rcm_prep.hip", "rcm_bfs.hip", "rcm_api.hip", "rcm_server.hip", "rcm_apply.hip",
+           "rcm_levelorder.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

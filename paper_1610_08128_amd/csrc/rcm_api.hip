@@ -40,6 +40,7 @@ struct Opts {
   int narrow_cutoff = 256;
   int max_teams = 16;
   int rebalance = 8;
+  int label_mode = 0;
 };
 
 // Auto values differ for batched calls: many components of many graphs share
@@ -65,6 +66,7 @@ bool parse_options(const rcm_options* o, Opts* out, bool batched = false) {
       return false;
     if (o->max_teams < 0 || o->max_teams > kMaxConcurrentTeams) return false;
     if (o->rebalance_levels < 0) return false;
+    if (o->label_mode < 0 || o->label_mode > 2) return false;
     r.pp_variant = o->pp_variant;
     r.reverse_mode = o->reverse_mode;
     r.check_full = o->check_full;
@@ -75,6 +77,7 @@ bool parse_options(const rcm_options* o, Opts* out, bool batched = false) {
     if (o->small_threads) r.small_threads = o->small_threads;
     if (o->max_teams) r.max_teams = o->max_teams;
     if (o->rebalance_levels) r.rebalance = o->rebalance_levels;
+    r.label_mode = o->label_mode;
   }
   *out = r;
   return true;
@@ -307,6 +310,7 @@ rcm_status run(const Graph& gin, const int32_t* seg_off_host, const Opts& opt, c
   P.reverse_mode = opt.reverse_mode;
   P.narrow_cutoff = opt.narrow_cutoff;
   P.rebalance = opt.rebalance;
+  P.label_mode = opt.label_mode;
   P.teams = teams;
   P.slots = slots;
   P.small_teams = small_ctl;
@@ -410,7 +414,9 @@ rcm_status run(const Graph& gin, const int32_t* seg_off_host, const Opts& opt, c
     }
     timer.mark(3);
     const int32_t n_single = h[0], n_small = h[1], n_big = h[2];
-    HIP_TRY(launch_singletons(t_single, n_single, perm_out, iperm, results, s));
+    HIP_TRY(launch_singletons(t_single, n_single, perm_out, iperm,
+                              opt.label_mode ? reinterpret_cast<int32_t*>(claim) : nullptr,
+                              opt.label_mode ? tmp : nullptr, results, s));
     st = launch(t_big, n_big, t_small, n_small, 0, false);
     if (st != RCM_OK) return st;
   }
@@ -420,9 +426,23 @@ rcm_status run(const Graph& gin, const int32_t* seg_off_host, const Opts& opt, c
   if (h[0]) report_device_error(gctl, s);
   if (h[0] == RCM_ERR_NOT_SYMMETRIC) return RCM_ERR_NOT_SYMMETRIC;
   if (h[0]) return RCM_ERR_ABORTED;
+  if (opt.label_mode != 0) {
+    // level orders: sort by the levels and block offsets the ordering
+    // kernel left in claim and tmp (the task lists and qi are free by now
+    // and serve as scratch)
+    const size_t temp_need = level_order_temp_bytes(g.n);
+    const size_t temp_have = L.scan_blk - L.t_single;
+    if (temp_need == 0 || temp_need > temp_have) return RCM_ERR_WORKSPACE_TOO_SMALL;
+    int32_t deg_bits = 1;
+    while (deg_bits < 31 && (1ll << deg_bits) <= g.nnz) ++deg_bits;
+    HIP_TRY(launch_level_order(g.n, deg_bits, opt.label_mode == 2, vinfo,
+                               reinterpret_cast<const int32_t*>(claim), tmp, perm_out, iperm,
+                               ws + L.qi, ws + L.t_single, temp_have, s));
+  }
   // 6. result statistics
   HIP_TRY(launch_bw_after(g, perm_out, iperm, beta, segstats, s));
-  HIP_TRY(launch_comp_stats(g, ncomp, seeds, results, comp_seg_off, segstats, s));
+  HIP_TRY(launch_comp_stats(g, ncomp, seeds, results, comp_seg_off, segstats,
+                            opt.label_mode == 0 || opt.pp_variant == 1 ? 1 : 0, s));
   if (stats_host) {
     std::vector<SegStats> hs(g.nseg);
     HIP_TRY(hipMemcpyAsync(hs.data(), segstats, sizeof(SegStats) * g.nseg,

@@ -57,6 +57,10 @@ struct Team {
   int wid;
   int comp;                 // index of the component being ordered (diagnostics)
   uint32_t seq;             // team barriers passed (every thread, in step)
+  int32_t o;                // level orders: first position of the component's
+                            // block in the final (reversed) order
+  long long pm;             // level orders: degrees of the vertices this thread
+                            // reached in the current pass
   unsigned long long woke;  // narrow episodes seen (thread 0 only)
   bool aborted;
 };
@@ -327,15 +331,31 @@ __device__ __forceinline__ int4 ld_rec(const BfsParams& P, int32_t pos) {
 // Unlabelled BFS (one level structure).
 // ---------------------------------------------------------------------------
 
+// Level orders keep, for every vertex the current pass reaches, its level in
+// claim[] (claims belong to the labelled BFS, which those orders never run)
+// and the first position of its component's block in the final order in
+// tmp[], and sum the degrees reached; the last pass of the search leaves the
+// root's level structure there.
+__device__ __forceinline__ void note_level(const BfsParams& P, Team& t, int32_t v, int32_t level,
+                                           int32_t deg) {
+  if (P.label_mode != 0) {
+    __hip_atomic_store(&P.claim[v], static_cast<uint32_t>(level), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&P.tmp[v], t.o, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    t.pm += deg;
+  }
+}
+
 // Expand qi[lo, hi) (this work-group's share of the level).  A neighbour is
 // new when atomicMax(visit, epoch) returns an older stamp; past-the-row lanes
 // hit the parent's own stamp, which already equals epoch.  New vertices go
 // to the LDS stage or, when it is full, straight to qi[cur_e + ...] (at a
 // slot reserved on the team's tail counter, or, for a work-group alone, at
 // its own index in the level).
-__device__ __forceinline__ void bfs_expand(const BfsParams& P, Shared& S, int32_t lo, int32_t hi,
-                                           int32_t cur_e, int32_t end, int32_t epoch,
-                                           int32_t* tail_slot, bool solo, uint64_t& mykey) {
+__device__ __forceinline__ void bfs_expand(const BfsParams& P, Team& t, Shared& S, int32_t lo,
+                                           int32_t hi, int32_t cur_e, int32_t end, int32_t epoch,
+                                           int32_t new_level, int32_t* tail_slot, bool solo,
+                                           uint64_t& mykey) {
   const int B = blockDim.x;
   for (int32_t p = lo + threadIdx.x; p < hi; p += B) {
     const int4 e = ld_rec(P, p);
@@ -365,6 +385,7 @@ __device__ __forceinline__ void bfs_expand(const BfsParams& P, Shared& S, int32_
 #pragma unroll
       for (int j = 0; j < kRB; ++j) {
         if (!(mask >> j & 1u)) continue;
+        note_level(P, t, nb[j], new_level, inf[j].z);
         const int4 r = record(nb[j], inf[j]);
         if (idx < kStageCap) {
           reinterpret_cast<int4*>(S.u.srec)[idx] = r;
@@ -489,6 +510,7 @@ __device__ __forceinline__ bool lds_bfs_levels(const BfsParams& P, Team& t, Shar
           if (cur_e + idx < end) P.qi[cur_e + idx] = r;
           if (idx < kNarrowCap) lds_put(N, (level + 1) & 1, idx, r);
           P.visit[nb[j]] = epoch;
+          note_level(P, t, nb[j], level + 1, inf[j].z);
           const uint64_t kv = pack_key(inf[j].z, nb[j]);
           mykey = kv < mykey ? kv : mykey;
         }
@@ -562,7 +584,7 @@ __device__ __forceinline__ void global_bfs_level(const BfsParams& P, Team& t, Sh
   my_chunk(cur_b, cur_e, W, wid, lo, hi);
   uint64_t mykey = kMaxKey;
   const long long ta = wall_clock64();
-  bfs_expand(P, S, lo, hi, cur_e, end, epoch, tail + l3, solo, mykey);
+  bfs_expand(P, t, S, lo, hi, cur_e, end, epoch, level + 1, tail + l3, solo, mykey);
   mykey = wave_min_u64(mykey);
   if ((threadIdx.x & 63) == 0 && mykey != kMaxKey) atomicMin(&S.key, mykey);
   __syncthreads();
@@ -690,6 +712,7 @@ __device__ __forceinline__ void own_bfs_levels(const BfsParams& P, Team& t, Shar
 #pragma unroll
         for (int j = 0; j < kRB; ++j) {
           if (!(mask >> j & 1u)) continue;
+          note_level(P, t, nb[j], level + 1, inf[j].z);
           const uint64_t kv = pack_key(inf[j].z, nb[j]);
           mykey = kv < mykey ? kv : mykey;
           if (idx < kOwnCap) {
@@ -814,10 +837,13 @@ __device__ __forceinline__ void bfs_pass(const BfsParams& P, Team& t, Shared& S,
   const long long clk0 = wall_clock64();
   int32_t* tail = t.ctl->tail + parity * 3;
   unsigned long long* minkey = t.ctl->minkey + parity * 3;
+  t.pm = 0;
   if (t.wid == 0 && threadIdx.x == 0) {
     const int4 ri = P.vinfo[root];
     st_rec(&P.qi[o], record(root, ri));
     __hip_atomic_store(&P.visit[root], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    note_level(P, t, root, 0, ri.z);
+    __hip_atomic_store(&t.ctl->pass_m[parity], 0ll, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     for (int i = 0; i < 3; ++i) st_relaxed(tail + i, 0);
     __hip_atomic_store(minkey + 0, pack_key(ri.z, root), __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_AGENT);
@@ -882,12 +908,20 @@ __device__ __forceinline__ void bfs_pass(const BfsParams& P, Team& t, Shared& S,
     t.aborted = true;
     return;
   }
+  if (P.label_mode != 0) {
+    const long long tot = block_sum_i64(t.pm, S.red);
+    if (threadIdx.x == 0 && tot != 0)
+      __hip_atomic_fetch_add(&t.ctl->pass_m[parity], tot, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+  }
   __syncthreads();
   // the last level's slot is stable until the next pass of the same parity
   ecc = level;
   lastkey = ld_relaxed(minkey + level % 3);
   // every work-group has read the counters before the next pass reuses them
   team_barrier(t, S, false);
+  if (P.label_mode != 0)
+    t.pm = __hip_atomic_load(&t.ctl->pass_m[parity], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (t.wid == 0 && threadIdx.x == 0) {
     t.ctl->clk[0] += wall_clock64() - clk0;
     t.ctl->clk[2] += level + 1;
@@ -1449,12 +1483,17 @@ __device__ __forceinline__ void order_component(const BfsParams& P, Team& t, Sha
   uint64_t lastkey = 0;
   int32_t nbfs = 1;
   int32_t found = end;
+  // the block's first position once reversed (level orders; the first pass
+  // of a component of unknown size writes o, which later passes correct)
+  auto block_start = [&]() { return (task.anchor >= 0 ? task.anchor : o + size - 1) - size + 1; };
+  t.o = size >= 0 ? block_start() : o;
   bfs_pass(P, t, S, o, end, task.seed, 1, 0, ecc, lastkey, size >= 0 ? nullptr : &found);
   if (t.aborted) return;
   if (size < 0) {
     size = found - o;
     end = found;
   }
+  t.o = block_start();
   int32_t r = task.seed;
   int32_t nlvl = ecc - 1;
   long long m = 0;
@@ -1465,7 +1504,7 @@ __device__ __forceinline__ void order_component(const BfsParams& P, Team& t, Sha
     const int32_t v = static_cast<int32_t>(lastkey & 0xffffffffu);  // min degree, last level
     ++nbfs;
     r = v;
-    if (P.pp_variant == 0 && nbfs >= 3) {
+    if (P.pp_variant == 0 && nbfs >= 3 && P.label_mode == 0) {
       // Algorithm 2 returns the root of its last search and Algorithm 3
       // starts there, so from the third search on the search is run as the
       // labelled BFS itself: if the eccentricity does not grow, the search
@@ -1488,7 +1527,20 @@ __device__ __forceinline__ void order_component(const BfsParams& P, Team& t, Sha
     }
   }
   const int32_t root = P.pp_variant == 1 ? static_cast<int32_t>(lastkey & 0xffffffffu) : r;
-  if (!labelled) {
+  // reversal: Cuthill-McKee label t of this component goes to anchor - t
+  const int32_t anchor = task.anchor >= 0 ? task.anchor : o + size - 1;
+  if (P.label_mode != 0) {
+    // level order: the levels come from a level structure rooted at `root`,
+    // the search's last one or, for Algorithm 4's pick, one more
+    if (P.pp_variant == 1) {
+      uint64_t k2 = 0;
+      bfs_pass(P, t, S, o, end, root, nbfs + 1, nbfs & 1, ecc, k2, nullptr);
+      if (t.aborted) return;
+    }
+    // every vertex now holds its level and block start; the host sorts
+    levels = ecc + 1;
+    m = t.pm;
+  } else if (!labelled) {
     levels = label_pass(P, t, S, o, end, root, &m, nullptr);
     if (t.aborted) return;
   }
@@ -1500,8 +1552,7 @@ __device__ __forceinline__ void order_component(const BfsParams& P, Team& t, Sha
     res->size = size;
     res->m = m;
   }
-  // reversal: Cuthill-McKee label t of this component goes to anchor - t
-  const int32_t anchor = task.anchor >= 0 ? task.anchor : o + size - 1;
+  if (P.label_mode != 0) return;  // perm is written by the sort
   const int32_t nthreads = t.W * blockDim.x;
   for (int32_t i = t.wid * blockDim.x + threadIdx.x; i < size; i += nthreads) {
     const int32_t v = ld_rec(P, o + i).x;

@@ -410,11 +410,16 @@ __global__ void k_class_scan(int32_t* sched, int32_t* counts) {
 
 __global__ void k_singletons(const CompTask* __restrict__ tasks, int32_t count,
                              int32_t* __restrict__ perm, int32_t* __restrict__ iperm,
+                             int32_t* __restrict__ level, int32_t* __restrict__ block,
                              CompResult* __restrict__ results) {
   for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
     const CompTask t = tasks[i];
     perm[t.anchor] = t.seed;
     iperm[t.seed] = t.anchor;
+    if (level) {
+      level[t.seed] = 0;
+      block[t.seed] = t.anchor;
+    }
     // an isolated vertex: Algorithm 2 computes two one-level structures
     results[t.index].root = t.seed;
     results[t.index].nbfs = 2;
@@ -473,9 +478,11 @@ __global__ void k_comp_seg_bounds(int nseg, const int32_t* __restrict__ seg_off,
   }
 }
 
+// labelled_bfs: 1 when a labelled BFS ran after the search (its entries
+// are counted too), 0 when the search's last level structure was used.
 __global__ void k_comp_stats(int32_t ncomp, int32_t chunk, const CompResult* __restrict__ res,
                              const int32_t* __restrict__ comp_seg_off, int nseg,
-                             SegStats* __restrict__ out) {
+                             int32_t labelled_bfs, SegStats* __restrict__ out) {
   __shared__ long long red[16];
   const int32_t c0 = blockIdx.x * chunk;
   if (c0 >= ncomp) return;
@@ -490,7 +497,7 @@ __global__ void k_comp_stats(int32_t ncomp, int32_t chunk, const CompResult* __r
       diam = (r.levels - 1) > diam ? (r.levels - 1) : diam;
       nb += r.nbfs;
       nl += r.levels;
-      edges += static_cast<long long>(r.nbfs + 1) * r.m;
+      edges += static_cast<long long>(r.nbfs + labelled_bfs) * r.m;
     }
     diam = block_max_i64(diam, red);
     nb = block_sum_i64(nb, red);
@@ -587,9 +594,10 @@ hipError_t launch_tasks(const Graph& g, int32_t ncomp, const int32_t* seeds, con
 }
 
 hipError_t launch_singletons(const CompTask* tasks, int32_t count, int32_t* perm, int32_t* iperm,
-                             CompResult* results, hipStream_t s) {
+                             int32_t* level, int32_t* block, CompResult* results, hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  k_singletons<<<grid_for(count, kThreads), kThreads, 0, s>>>(tasks, count, perm, iperm, results);
+  k_singletons<<<grid_for(count, kThreads), kThreads, 0, s>>>(tasks, count, perm, iperm, level,
+                                                              block, results);
   return hipGetLastError();
 }
 
@@ -605,13 +613,14 @@ hipError_t launch_bw_after(const Graph& g, const int32_t* perm, const int32_t* i
 
 hipError_t launch_comp_stats(const Graph& g, int32_t ncomp, const int32_t* seeds,
                              const CompResult* results, int32_t* comp_seg_off, SegStats* seg,
-                             hipStream_t s) {
+                             int32_t labelled_bfs, hipStream_t s) {
   if (ncomp <= 0) return hipSuccess;
   k_comp_seg_bounds<<<grid_for(g.nseg + 1, kThreads), kThreads, 0, s>>>(g.nseg, g.seg_off, seeds,
                                                                        ncomp, comp_seg_off);
   constexpr int32_t chunk = 4096;
   const int nb = (ncomp + chunk - 1) / chunk;
-  k_comp_stats<<<nb, kThreads, 0, s>>>(ncomp, chunk, results, comp_seg_off, g.nseg, seg);
+  k_comp_stats<<<nb, kThreads, 0, s>>>(ncomp, chunk, results, comp_seg_off, g.nseg, labelled_bfs,
+                                       seg);
   return hipGetLastError();
 }
 

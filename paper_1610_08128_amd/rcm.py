@@ -75,7 +75,8 @@ class Options(ctypes.Structure):
         ("small_threads", ctypes.c_int32),
         ("max_teams", ctypes.c_int32),
         ("rebalance_levels", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 6),
+        ("label_mode", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 5),
     ]
 
 
@@ -137,7 +138,7 @@ def status_string(status: int) -> str:
 
 def make_options(*, pp_variant=0, reverse_mode=0, check_full=False, team_size=0,
                  block_threads=0, small_cutoff=0, narrow_cutoff=0, small_threads=0,
-                 max_teams=0, rebalance_levels=0) -> Options:
+                 max_teams=0, rebalance_levels=0, label_mode=0) -> Options:
     o = Options()
     o.pp_variant = int(pp_variant)
     o.reverse_mode = int(reverse_mode)
@@ -149,6 +150,7 @@ def make_options(*, pp_variant=0, reverse_mode=0, check_full=False, team_size=0,
     o.small_threads = int(small_threads)
     o.max_teams = int(max_teams)
     o.rebalance_levels = int(rebalance_levels)
+    o.label_mode = int(label_mode)
     return o
 
 

@@ -29,11 +29,18 @@ def gpu_order(g, **opts):
     return perm.cpu().numpy(), iperm.cpu().numpy(), st
 
 
-def check(g, *, pp_variant=0, reverse_mode=0, **gpu_opts):
-    _say(f"case {g.name} n={g.n} nnz={g.nnz} pp={pp_variant} rev={reverse_mode} {gpu_opts}")
-    want = oracle.rcm(g.n, g.rowptr, g.colidx, pp_variant=pp_variant, reverse_mode=reverse_mode)
+# the library's label_mode and the oracle's cm_mode for the same order
+CM_MODE = {0: 0, 1: 2, 2: 3}
+
+
+def check(g, *, pp_variant=0, reverse_mode=0, label_mode=0, **gpu_opts):
+    _say(f"case {g.name} n={g.n} nnz={g.nnz} pp={pp_variant} rev={reverse_mode} "
+         f"label={label_mode} {gpu_opts}")
+    want = oracle.rcm(g.n, g.rowptr, g.colidx, pp_variant=pp_variant, reverse_mode=reverse_mode,
+                      cm_mode=CM_MODE[label_mode])
     assert want.status == oracle.OK
-    perm, iperm, st = gpu_order(g, pp_variant=pp_variant, reverse_mode=reverse_mode, **gpu_opts)
+    perm, iperm, st = gpu_order(g, pp_variant=pp_variant, reverse_mode=reverse_mode,
+                                label_mode=label_mode, **gpu_opts)
     if not np.array_equal(perm, want.perm):
         bad = np.nonzero(perm != want.perm)[0]
         raise AssertionError(f"perm differs at {bad.size} positions, first {bad[:10]}: "
@@ -224,7 +231,8 @@ def _check_batch(graphs, **opts):
     perm = perm.cpu().numpy()
     for i, g in enumerate(graphs):
         want = oracle.rcm(g.n, g.rowptr, g.colidx, pp_variant=opts.get("pp_variant", 0),
-                          reverse_mode=opts.get("reverse_mode", 0))
+                          reverse_mode=opts.get("reverse_mode", 0),
+                          cm_mode=CM_MODE[opts.get("label_mode", 0)])
         assert np.array_equal(perm[vo[i]:vo[i + 1]], want.perm), f"graph {i}"
         assert stats[i] == want.stats, (i, stats[i], want.stats)
 
@@ -250,3 +258,42 @@ def test_batched_concurrent_teams():
 def test_batched_512():
     graphs = I.batch_graphs(512, seed=4)
     _check_batch(graphs)
+
+
+# ---------------------------------------------------------------------------
+# Level orders (label_mode 1: no sort, 2: one global sort at the end)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("idx", range(17))
+@pytest.mark.parametrize("label_mode", [1, 2])
+def test_level_orders_tiny(idx, label_mode):
+    g = _tiny_graphs()[idx]
+    for pp in (0, 1):
+        for rev in (0, 1):
+            check(g, pp_variant=pp, reverse_mode=rev, label_mode=label_mode)
+
+
+@pytest.mark.parametrize("seed", range(12))
+@pytest.mark.parametrize("label_mode", [1, 2])
+def test_level_orders_random(seed, label_mode):
+    g = _random_graph(400 + seed)
+    check(g, pp_variant=seed % 2, reverse_mode=(seed // 2) % 2, label_mode=label_mode)
+    check(g, label_mode=label_mode, small_cutoff=1, team_size=1 + seed % 8, narrow_cutoff=16)
+
+
+@pytest.mark.parametrize("label_mode", [1, 2])
+def test_level_orders_grids(label_mode):
+    check(I.config(0, seed=3), label_mode=label_mode)
+    check(I.config(0, seed=3), label_mode=label_mode, small_cutoff=1)
+    # the 128^3 grid at full size, in the benchmark's launch configuration
+    check(I.config(1), label_mode=label_mode)
+    check(I.config(1), label_mode=label_mode, pp_variant=1, reverse_mode=1)
+
+
+def test_level_orders_batched():
+    graphs = [_random_graph(500 + i) for i in range(8)] + [I.path(1), I.complete(5)]
+    graphs += [I.grid2d(20 + 3 * i, 30, seed=600 + i) for i in range(4)]
+    for label_mode in (1, 2):
+        _check_batch(graphs, label_mode=label_mode)
+        _check_batch(graphs, label_mode=label_mode, small_cutoff=500, team_size=4,
+                     pp_variant=1, reverse_mode=1)
