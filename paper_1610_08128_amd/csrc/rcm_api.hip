@@ -416,7 +416,7 @@ rcm_status run(const Graph& gin, const int32_t* seg_off_host, const Opts& opt, c
     const int32_t n_single = h[0], n_small = h[1], n_big = h[2];
     HIP_TRY(launch_singletons(t_single, n_single, perm_out, iperm,
                               opt.label_mode ? reinterpret_cast<int32_t*>(claim) : nullptr,
-                              opt.label_mode ? tmp : nullptr, results, s));
+                              results, s));
     st = launch(t_big, n_big, t_small, n_small, 0, false);
     if (st != RCM_OK) return st;
   }
@@ -427,16 +427,15 @@ rcm_status run(const Graph& gin, const int32_t* seg_off_host, const Opts& opt, c
   if (h[0] == RCM_ERR_NOT_SYMMETRIC) return RCM_ERR_NOT_SYMMETRIC;
   if (h[0]) return RCM_ERR_ABORTED;
   if (opt.label_mode != 0) {
-    // level orders: sort by the levels and block offsets the ordering
-    // kernel left in claim and tmp (the task lists and qi are free by now
-    // and serve as scratch)
+    // level orders: sort by the keys the ordering kernel left in claim
+    // (the task lists and qi are free by now and serve as scratch)
     const size_t temp_need = level_order_temp_bytes(g.n);
     const size_t temp_have = L.scan_blk - L.t_single;
     if (temp_need == 0 || temp_need > temp_have) return RCM_ERR_WORKSPACE_TOO_SMALL;
     int32_t deg_bits = 1;
     while (deg_bits < 31 && (1ll << deg_bits) <= g.nnz) ++deg_bits;
     HIP_TRY(launch_level_order(g.n, deg_bits, opt.label_mode == 2, vinfo,
-                               reinterpret_cast<const int32_t*>(claim), tmp, perm_out, iperm,
+                               reinterpret_cast<const int32_t*>(claim), perm_out, iperm,
                                ws + L.qi, ws + L.t_single, temp_have, s));
   }
   // 6. result statistics

@@ -57,8 +57,8 @@ struct Team {
   int wid;
   int comp;                 // index of the component being ordered (diagnostics)
   uint32_t seq;             // team barriers passed (every thread, in step)
-  int32_t o;                // level orders: first position of the component's
-                            // block in the final (reversed) order
+  int32_t anchor;           // level orders: final position of the component's
+                            // Cuthill-McKee label 0
   long long pm;             // level orders: degrees of the vertices this thread
                             // reached in the current pass
   unsigned long long woke;  // narrow episodes seen (thread 0 only)
@@ -331,17 +331,19 @@ __device__ __forceinline__ int4 ld_rec(const BfsParams& P, int32_t pos) {
 // Unlabelled BFS (one level structure).
 // ---------------------------------------------------------------------------
 
-// Level orders keep, for every vertex the current pass reaches, its level in
-// claim[] (claims belong to the labelled BFS, which those orders never run)
-// and the first position of its component's block in the final order in
-// tmp[], and sum the degrees reached; the last pass of the search leaves the
-// root's level structure there.
+// Level orders keep, for every vertex the current pass expands (each once),
+// the key anchor - level in claim[] (claims belong to the labelled BFS,
+// which those orders never run; anchor = the final position of the
+// component's Cuthill-McKee label 0, so the keys of a component stay inside
+// its block and a deeper level gets a smaller key), and sum the degrees
+// expanded.  The last pass of the search leaves the keys of the root's level
+// structure.  The store is issued after the vertex's row load, so that its
+// completion overlaps that load instead of delaying the next one.
 __device__ __forceinline__ void note_level(const BfsParams& P, Team& t, int32_t v, int32_t level,
                                            int32_t deg) {
   if (P.label_mode != 0) {
-    __hip_atomic_store(&P.claim[v], static_cast<uint32_t>(level), __ATOMIC_RELAXED,
+    __hip_atomic_store(&P.claim[v], static_cast<uint32_t>(t.anchor - level), __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(&P.tmp[v], t.o, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     t.pm += deg;
   }
 }
@@ -360,9 +362,11 @@ __device__ __forceinline__ void bfs_expand(const BfsParams& P, Team& t, Shared& 
   for (int32_t p = lo + threadIdx.x; p < hi; p += B) {
     const int4 e = ld_rec(P, p);
     const int32_t u = e.x;
+    if (e.y >= e.z) note_level(P, t, u, new_level - 1, e.w);
     for (int32_t k0 = e.y; k0 < e.z; k0 += kRB) {
       int32_t nb[kRB];
       load_batch(P.colidx, k0, e.z, u, nb);
+      if (k0 == e.y) note_level(P, t, u, new_level - 1, e.w);
       int32_t old[kRB];
       int4 inf[kRB];
       // the records are loaded alongside the atomics (both need only nb)
@@ -385,7 +389,6 @@ __device__ __forceinline__ void bfs_expand(const BfsParams& P, Team& t, Shared& 
 #pragma unroll
       for (int j = 0; j < kRB; ++j) {
         if (!(mask >> j & 1u)) continue;
-        note_level(P, t, nb[j], new_level, inf[j].z);
         const int4 r = record(nb[j], inf[j]);
         if (idx < kStageCap) {
           reinterpret_cast<int4*>(S.u.srec)[idx] = r;
@@ -489,9 +492,11 @@ __device__ __forceinline__ bool lds_bfs_levels(const BfsParams& P, Team& t, Shar
     for (int32_t i = threadIdx.x; i < len; i += B) {
       const int4 e = lds_rec(N, level & 1, i);
       const int32_t u = e.x;
+      if (e.y >= e.z) note_level(P, t, u, level, e.w);
       for (int32_t k0 = e.y; k0 < e.z; k0 += kRB) {
         int32_t nb[kRB];
         load_batch(P.colidx, k0, e.z, u, nb);
+        if (k0 == e.y) note_level(P, t, u, level, e.w);
         int32_t vs[kRB];
         int4 inf[kRB];
 #pragma unroll
@@ -510,7 +515,6 @@ __device__ __forceinline__ bool lds_bfs_levels(const BfsParams& P, Team& t, Shar
           if (cur_e + idx < end) P.qi[cur_e + idx] = r;
           if (idx < kNarrowCap) lds_put(N, (level + 1) & 1, idx, r);
           P.visit[nb[j]] = epoch;
-          note_level(P, t, nb[j], level + 1, inf[j].z);
           const uint64_t kv = pack_key(inf[j].z, nb[j]);
           mykey = kv < mykey ? kv : mykey;
         }
@@ -652,10 +656,10 @@ __device__ __forceinline__ void global_bfs_level(const BfsParams& P, Team& t, Sh
 // Wide unlabelled levels with each work-group's share of the frontier in LDS:
 // a work-group expands the vertices it found itself at the previous level
 // (plus, at the first level and after a spill, its chunk of records in qi),
-// so records neither go to nor come back from qi.  The level's size travels
-// in the arrival atomic of a counting barrier (two words alternating by
-// level), and the next level's minimum key is issued after arriving (it is
-// only read once the pass ends, behind a full barrier).  Enters with the
+// so records neither go to nor come back from qi.  The level's size and a
+// spill flag travel in the team barrier's slot payload, and the next
+// level's minimum key is issued just before arriving (it is only read once
+// the pass ends, behind a full barrier).  Enters with the
 // frontier in qi[cur_b, cur_e); returns when the pass has ended (done) or
 // the frontier is narrower than the narrow cutoff, which is then written to
 // qi[cur_b, cur_e) for the narrow levels.
@@ -692,12 +696,15 @@ __device__ __forceinline__ void own_bfs_levels(const BfsParams& P, Team& t, Shar
         e = ld_rec(P, lo + i);
       } else {
         const int32_t j = i - n_glob;
-        e = make_int4(S.u.own[cb][j][0], S.u.own[cb][j][1], S.u.own[cb][j][2], 0);
+        e = make_int4(S.u.own[cb][j][0], S.u.own[cb][j][1], S.u.own[cb][j][2],
+                      S.u.own[cb][j][3]);
       }
       const int32_t u = e.x;
+      if (e.y >= e.z) note_level(P, t, u, level, e.w);
       for (int32_t k0 = e.y; k0 < e.z; k0 += kRB) {
         int32_t nb[kRB];
         load_batch(P.colidx, k0, e.z, u, nb);
+        if (k0 == e.y) note_level(P, t, u, level, e.w);
         int4 inf[kRB];
         int32_t old[kRB];
 #pragma unroll
@@ -712,7 +719,6 @@ __device__ __forceinline__ void own_bfs_levels(const BfsParams& P, Team& t, Shar
 #pragma unroll
         for (int j = 0; j < kRB; ++j) {
           if (!(mask >> j & 1u)) continue;
-          note_level(P, t, nb[j], level + 1, inf[j].z);
           const uint64_t kv = pack_key(inf[j].z, nb[j]);
           mykey = kv < mykey ? kv : mykey;
           if (idx < kOwnCap) {
@@ -842,7 +848,6 @@ __device__ __forceinline__ void bfs_pass(const BfsParams& P, Team& t, Shared& S,
     const int4 ri = P.vinfo[root];
     st_rec(&P.qi[o], record(root, ri));
     __hip_atomic_store(&P.visit[root], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    note_level(P, t, root, 0, ri.z);
     __hip_atomic_store(&t.ctl->pass_m[parity], 0ll, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     for (int i = 0; i < 3; ++i) st_relaxed(tail + i, 0);
     __hip_atomic_store(minkey + 0, pack_key(ri.z, root), __ATOMIC_RELAXED,
@@ -1483,17 +1488,16 @@ __device__ __forceinline__ void order_component(const BfsParams& P, Team& t, Sha
   uint64_t lastkey = 0;
   int32_t nbfs = 1;
   int32_t found = end;
-  // the block's first position once reversed (level orders; the first pass
-  // of a component of unknown size writes o, which later passes correct)
-  auto block_start = [&]() { return (task.anchor >= 0 ? task.anchor : o + size - 1) - size + 1; };
-  t.o = size >= 0 ? block_start() : o;
+  // level orders' key anchor (the first pass of a component of unknown size
+  // writes provisional keys, which later passes replace)
+  t.anchor = task.anchor >= 0 ? task.anchor : (size >= 0 ? o + size - 1 : end - 1);
   bfs_pass(P, t, S, o, end, task.seed, 1, 0, ecc, lastkey, size >= 0 ? nullptr : &found);
   if (t.aborted) return;
   if (size < 0) {
     size = found - o;
     end = found;
   }
-  t.o = block_start();
+  t.anchor = task.anchor >= 0 ? task.anchor : o + size - 1;
   int32_t r = task.seed;
   int32_t nlvl = ecc - 1;
   long long m = 0;

@@ -239,28 +239,28 @@ hipError_t launch_tasks(const Graph& g, int32_t ncomp, const int32_t* seeds, con
                         CompTask* tasks_big, int32_t* counts, int32_t* sizes, int32_t* offs,
                         int32_t* scan_blk, CompResult* results, int32_t* sched,
                         hipStream_t s);
-// level / block (nullable): level 0 and the vertex's position, for the
-// level orders' keys
+// key (nullable): the level orders' key of an isolated vertex, its position
 hipError_t launch_singletons(const CompTask* tasks, int32_t count, int32_t* perm, int32_t* iperm,
-                             int32_t* level, int32_t* block, CompResult* results, hipStream_t s);
+                             int32_t* key, CompResult* results, hipStream_t s);
 hipError_t launch_bw_after(const Graph& g, const int32_t* perm, const int32_t* iperm,
                            int32_t* beta, SegStats* seg, hipStream_t s);
 hipError_t launch_comp_stats(const Graph& g, int32_t ncomp, const int32_t* seeds,
                              const CompResult* results, int32_t* comp_seg_off, SegStats* seg,
                              int32_t labelled_bfs, hipStream_t s);
 
-// Level orders (label_mode 1 and 2): the ordering kernel leaves every
-// vertex's level in the root's level structure in level[v] and the first
-// position of its component's block in the final order in block[v].
-// perm[k] = the vertices sorted by block, then by level, degree (when
-// by_degree) and id, each descending -- the reversed order -- and iperm its
-// inverse.  scratch: 16 n bytes (four int32 arrays of n);
-// temp: level_order_temp_bytes(n).
+// Level orders (label_mode 1 and 2): the ordering kernel leaves in key[v]
+// anchor - level, anchor being the final position of the component's
+// Cuthill-McKee label 0 and level the vertex's level in the root's level
+// structure (an isolated vertex: its position).  perm[k] = the vertices
+// sorted by key ascending, then by degree (when by_degree) and id
+// descending -- the reversed order -- and iperm its inverse.
+// scratch: 16 n bytes (four int32 arrays of n); temp:
+// level_order_temp_bytes(n).
 size_t level_order_temp_bytes(int32_t n);
 hipError_t launch_level_order(int32_t n, int32_t max_degree_bits, bool by_degree,
-                              const int4* vinfo, const int32_t* level,
-                              const int32_t* block, int32_t* perm, int32_t* iperm, void* scratch,
-                              void* temp, size_t temp_bytes, hipStream_t s);
+                              const int4* vinfo, const int32_t* key, int32_t* perm,
+                              int32_t* iperm, void* scratch, void* temp, size_t temp_bytes,
+                              hipStream_t s);
 hipError_t launch_exclusive_scan(const int32_t* in, int32_t* out, int32_t count, int32_t* tmp,
                                  int32_t* total_out, hipStream_t s);
 

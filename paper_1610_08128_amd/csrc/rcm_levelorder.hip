@@ -5,13 +5,15 @@
 // vector holds its entries) and the global sort orders by (degree, id), the
 // keys SortPerm uses after the parent label.
 //
-// The ordering kernel leaves, for every vertex, its level in the root's
-// level structure and the first position its component's block takes in
-// the final order (which already accounts for the reversal mode).  The
-// final order lists the blocks by that position and, inside a block, the
-// vertices by (level, degree, id) descending.  Three stable LSD radix sorts produce it,
-// least significant key first: by degree over the vertices in descending id
-// order (global sort only), then by level, then by block.
+// The ordering kernel leaves, for every vertex, the key anchor - level:
+// anchor is the final position of its component's Cuthill-McKee label 0
+// (which already accounts for the reversal mode), level its level in the
+// root's level structure, so the keys of a component stay inside its block
+// and a deeper level gets a smaller key.  The final order is the keys
+// ascending and, for equal keys, degree and then id descending: the reverse
+// of (level, degree, id) inside each block.  Two stable LSD radix sorts
+// produce it, least significant key first: by degree over the vertices in
+// descending id order (global sort only), then by key.
 
 #include <hip/hip_runtime.h>
 
@@ -37,36 +39,23 @@ inline unsigned bits_for(int64_t n) {
   return b;
 }
 
-// Sort keys, each ascending in the order wanted.
-struct LevelKeys {
-  const int4* vinfo;
-  const int32_t* level;
-  const int32_t* block;
-  uint32_t deg_max, level_max;
-  __device__ uint32_t degree(int32_t v) const {
-    return deg_max - static_cast<uint32_t>(vinfo[v].z);
-  }
-  __device__ uint32_t lev(int32_t v) const { return level_max - static_cast<uint32_t>(level[v]); }
-  __device__ uint32_t blk(int32_t v) const { return static_cast<uint32_t>(block[v]); }
-};
-
-// vals[i] = n - 1 - i (descending id) and its first key.
-__global__ void k_lo_init(int32_t n, int32_t by_degree, LevelKeys K, uint32_t* __restrict__ key_out,
-                          int32_t* __restrict__ val_out) {
+// vals[i] = n - 1 - i (descending id) and its first sort key: the degree
+// complement (ordering by degree) or the position key.
+__global__ void k_lo_init(int32_t n, int32_t by_degree, uint32_t deg_max,
+                          const int4* __restrict__ vinfo, const int32_t* __restrict__ key,
+                          uint32_t* __restrict__ key_out, int32_t* __restrict__ val_out) {
   for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     const int32_t v = n - 1 - i;
     val_out[i] = v;
-    key_out[i] = by_degree ? K.degree(v) : K.lev(v);
+    key_out[i] = by_degree ? deg_max - static_cast<uint32_t>(vinfo[v].z)
+                           : static_cast<uint32_t>(key[v]);
   }
 }
 
-// which: 0 = level key, 1 = block key of vals[i].
-__global__ void k_lo_gather(int32_t n, int32_t which, LevelKeys K,
-                            const int32_t* __restrict__ vals, uint32_t* __restrict__ key_out) {
-  for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    const int32_t v = vals[i];
-    key_out[i] = which == 0 ? K.lev(v) : K.blk(v);
-  }
+__global__ void k_lo_gather(int32_t n, const int32_t* __restrict__ vals,
+                            const int32_t* __restrict__ key, uint32_t* __restrict__ key_out) {
+  for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    key_out[i] = static_cast<uint32_t>(key[vals[i]]);
 }
 
 __global__ void k_lo_inverse(int32_t n, const int32_t* __restrict__ perm,
@@ -98,45 +87,33 @@ size_t level_order_temp_bytes(int32_t n) {
 }
 
 hipError_t launch_level_order(int32_t n, int32_t max_degree_bits, bool by_degree,
-                              const int4* vinfo, const int32_t* level,
-                              const int32_t* block, int32_t* perm, int32_t* iperm, void* scratch,
-                              void* temp, size_t temp_bytes, hipStream_t s) {
+                              const int4* vinfo, const int32_t* key, int32_t* perm,
+                              int32_t* iperm, void* scratch, void* temp, size_t temp_bytes,
+                              hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const size_t N = static_cast<size_t>(n);
   uint32_t* ka = static_cast<uint32_t*>(scratch);
   int32_t* va = reinterpret_cast<int32_t*>(ka + N);
   uint32_t* kb = reinterpret_cast<uint32_t*>(va + N);
   int32_t* vb = reinterpret_cast<int32_t*>(kb + N);
-  // levels and block starts lie in [0, n); degrees in [0, 2^max_degree_bits)
-  const unsigned pos_bits = bits_for(n);
+  // keys lie in [0, n); degrees in [0, 2^max_degree_bits)
+  const unsigned key_bits = bits_for(n);
   const unsigned deg_bits = static_cast<unsigned>(max_degree_bits);
-  LevelKeys K;
-  K.vinfo = vinfo;
-  K.level = level;
-  K.block = block;
-  K.deg_max = deg_bits >= 32 ? 0xFFFFFFFFu : ((1u << deg_bits) - 1u);
-  K.level_max = pos_bits >= 32 ? 0xFFFFFFFFu : ((1u << pos_bits) - 1u);
+  const uint32_t deg_max = deg_bits >= 32 ? 0xFFFFFFFFu : ((1u << deg_bits) - 1u);
   const int g = grid_for(n);
-  k_lo_init<<<g, kThreads, 0, s>>>(n, by_degree ? 1 : 0, K, ka, va);
+  k_lo_init<<<g, kThreads, 0, s>>>(n, by_degree ? 1 : 0, deg_max, vinfo, key, ka, va);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  int32_t* cur = vb;  // vertices in (level, degree, id) order after the next sorts
   if (by_degree) {
     e = sort_pairs(temp, temp_bytes, ka, kb, va, vb, n, deg_bits, s);
     if (e != hipSuccess) return e;
-    k_lo_gather<<<g, kThreads, 0, s>>>(n, 0, K, vb, ka);
+    k_lo_gather<<<g, kThreads, 0, s>>>(n, vb, key, ka);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    e = sort_pairs(temp, temp_bytes, ka, kb, vb, va, n, pos_bits, s);
-    cur = va;
+    e = sort_pairs(temp, temp_bytes, ka, kb, vb, perm, n, key_bits, s);
   } else {
-    e = sort_pairs(temp, temp_bytes, ka, kb, va, vb, n, pos_bits, s);
+    e = sort_pairs(temp, temp_bytes, ka, kb, va, perm, n, key_bits, s);
   }
-  if (e != hipSuccess) return e;
-  k_lo_gather<<<g, kThreads, 0, s>>>(n, 1, K, cur, ka);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  e = sort_pairs(temp, temp_bytes, ka, kb, cur, perm, n, pos_bits, s);
   if (e != hipSuccess) return e;
   k_lo_inverse<<<g, kThreads, 0, s>>>(n, perm, iperm);
   return hipGetLastError();

@@ -410,16 +410,12 @@ __global__ void k_class_scan(int32_t* sched, int32_t* counts) {
 
 __global__ void k_singletons(const CompTask* __restrict__ tasks, int32_t count,
                              int32_t* __restrict__ perm, int32_t* __restrict__ iperm,
-                             int32_t* __restrict__ level, int32_t* __restrict__ block,
-                             CompResult* __restrict__ results) {
+                             int32_t* __restrict__ key, CompResult* __restrict__ results) {
   for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
     const CompTask t = tasks[i];
     perm[t.anchor] = t.seed;
     iperm[t.seed] = t.anchor;
-    if (level) {
-      level[t.seed] = 0;
-      block[t.seed] = t.anchor;
-    }
+    if (key) key[t.seed] = t.anchor;
     // an isolated vertex: Algorithm 2 computes two one-level structures
     results[t.index].root = t.seed;
     results[t.index].nbfs = 2;
@@ -594,10 +590,10 @@ hipError_t launch_tasks(const Graph& g, int32_t ncomp, const int32_t* seeds, con
 }
 
 hipError_t launch_singletons(const CompTask* tasks, int32_t count, int32_t* perm, int32_t* iperm,
-                             int32_t* level, int32_t* block, CompResult* results, hipStream_t s) {
+                             int32_t* key, CompResult* results, hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  k_singletons<<<grid_for(count, kThreads), kThreads, 0, s>>>(tasks, count, perm, iperm, level,
-                                                              block, results);
+  k_singletons<<<grid_for(count, kThreads), kThreads, 0, s>>>(tasks, count, perm, iperm, key,
+                                                              results);
   return hipGetLastError();
 }
 
