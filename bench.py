@@ -45,7 +45,7 @@ WORKLOADS = {
 # sources at the time of the measurement, so a changed kernel reports null.
 # Summaries with the commands: profiles/k_order_<workload>_hbm_counters.md.
 MEASURED_TRAFFIC = {
-    "grid3d_128x128x128": ("64f117eaf9c2c532", 5539835236),
+    "grid3d_128x128x128": ("77bda7e1838dcbf9", 5618950066),
 }
 KERNEL_SOURCES = ("paper_1610_08128_amd/csrc/rcm_bfs.hip",
                   "paper_1610_08128_amd/csrc/rcm_common.hpp")
