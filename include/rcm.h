@@ -133,7 +133,19 @@ typedef struct {
                             returned vertex with pp_variant 1) and skip the
                             labelled BFS; the result is still reversed per
                             reverse_mode.                                      */
-  int32_t reserved[5];
+  int32_t async_search;  /* level structures of the pseudo-peripheral search
+                            of a large component (a team's, at least n/8
+                            vertices): 0 = auto (asynchronous), 1 =
+                            asynchronous, -1 = level-synchronous.
+                            Asynchronous is a label-correcting BFS whose
+                            work-groups expand their own frontiers for
+                            rebalance_levels steps between team barriers
+                            instead of meeting once per level (the
+                            non-level-synchronous BFS that Section VI leaves
+                            as future work).  Same result; a pass whose
+                            frontier outgrows its ring falls back to the
+                            level-synchronous pass                         */
+  int32_t reserved[4];
 } rcm_options;
 
 /* Human-readable name of a status code (static string). */

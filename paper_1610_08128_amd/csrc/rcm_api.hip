@@ -41,6 +41,7 @@ struct Opts {
   int max_teams = 16;
   int rebalance = 8;
   int label_mode = 0;
+  int async_search = 1;
 };
 
 // Auto values differ for batched calls: many components of many graphs share
@@ -67,6 +68,7 @@ bool parse_options(const rcm_options* o, Opts* out, bool batched = false) {
     if (o->max_teams < 0 || o->max_teams > kMaxConcurrentTeams) return false;
     if (o->rebalance_levels < 0) return false;
     if (o->label_mode < 0 || o->label_mode > 2) return false;
+    if (o->async_search < -1 || o->async_search > 1) return false;
     r.pp_variant = o->pp_variant;
     r.reverse_mode = o->reverse_mode;
     r.check_full = o->check_full;
@@ -78,6 +80,7 @@ bool parse_options(const rcm_options* o, Opts* out, bool batched = false) {
     if (o->max_teams) r.max_teams = o->max_teams;
     if (o->rebalance_levels) r.rebalance = o->rebalance_levels;
     r.label_mode = o->label_mode;
+    if (o->async_search) r.async_search = o->async_search > 0 ? 1 : 0;
   }
   *out = r;
   return true;
@@ -85,7 +88,7 @@ bool parse_options(const rcm_options* o, Opts* out, bool batched = false) {
 
 // Workspace layout (every region 256-byte aligned).
 struct Layout {
-  size_t vinfo, beta, parent, flags, pos, csize, seeds, visit, claim, qi, tmp, iperm;
+  size_t vinfo, beta, parent, flags, pos, csize, seeds, visit, claim, qi, tmp, iperm, dkey;
   size_t sizes, offs, results, t_single, t_small, t_big, scan_blk;
   size_t seg_off, comp_seg_off, segstats, gctl, teams, slots, small_ctl, misc, sched;
   size_t rowptr_g, colidx_g;
@@ -113,6 +116,7 @@ Layout make_layout(int64_t n, int64_t nnz, int64_t nseg, bool batched, int teams
   L.qi = take(16 * N);
   L.tmp = take(4 * N);
   L.iperm = take(4 * N);
+  L.dkey = take(8 * N);
   L.sizes = take(4 * N);
   L.offs = take(4 * N);
   L.results = take(sizeof(CompResult) * N);
@@ -311,6 +315,10 @@ rcm_status run(const Graph& gin, const int32_t* seg_off_host, const Opts& opt, c
   P.narrow_cutoff = opt.narrow_cutoff;
   P.rebalance = opt.rebalance;
   P.label_mode = opt.label_mode;
+  P.async_search = opt.async_search;
+  P.dkey = reinterpret_cast<unsigned long long*>(ws + L.dkey);
+  // distance words of the asynchronous passes start below every pass tag
+  if (opt.async_search) HIP_TRY(hipMemsetAsync(P.dkey, 0, 8 * static_cast<size_t>(g.n), s));
   P.teams = teams;
   P.slots = slots;
   P.small_teams = small_ctl;

@@ -107,6 +107,7 @@ struct Shared {
   int32_t wtot;                    // team_counts: the team's total
   int32_t wmax;                    // team_counts: the largest count
   int32_t wspill;                  // team_counts: work-groups that flagged a spill
+  int32_t ovf;                     // asynchronous passes: a record found no ring slot
   int32_t lown_base;               // wide labelled level: the label range of the
   int32_t lown_len;                // children this work-group placed (its list
   int32_t lown_ok;                 // in srec), valid when it holds them all
@@ -934,6 +935,271 @@ __device__ __forceinline__ void bfs_pass(const BfsParams& P, Team& t, Shared& S,
 }
 
 // ---------------------------------------------------------------------------
+// Asynchronous level structure: a label-correcting BFS without a barrier per
+// level (the non-level-synchronous BFS that Section VI leaves as future
+// work).  It yields the same eccentricity and the same minimum-(degree, id)
+// vertex of the last level as bfs_pass, because the distances it settles on
+// are the exact BFS distances whatever order the updates take.
+// ---------------------------------------------------------------------------
+
+// dkey[v] = tag << 32 | (2^32 - 1 - distance): in one pass a larger word is a
+// shorter distance, and every word of the current pass (its tag) beats those
+// of earlier passes, so atomicMax both visits and corrects.
+__device__ __forceinline__ unsigned long long dist_key(uint32_t tag, int32_t d) {
+  return (static_cast<unsigned long long>(tag) << 32) |
+         (0xFFFFFFFFu - static_cast<uint32_t>(d));
+}
+
+// Position of virtual ring index v in qi[o, o + ring).
+__device__ __forceinline__ int32_t ring_pos(int32_t o, int32_t ring, int32_t v) {
+  return o + static_cast<int32_t>(static_cast<uint32_t>(v) % static_cast<uint32_t>(ring));
+}
+
+// One level structure of the component whose label block is [o, end), from
+// `root`, for a team of several work-groups.  Rounds: every work-group
+// expands its share of the frontier and then, for up to `rebalance` steps,
+// the vertices it reached itself (records carry their tentative distance;
+// an improved vertex is expanded again by whoever improved it, a superseded
+// record is skipped), with no team barrier between the steps.  One barrier
+// per round then spreads all records evenly (qi[o, end) serves as a ring of
+// frontier records) and detects the end.  Finally a sweep over the vertices
+// carrying this pass's tag yields the eccentricity, the last level's minimum
+// key, the number of vertices reached (the component's size when found_end
+// is given) and, for level orders, the keys.  Returns false if the ring
+// would overflow (a frontier and its successor above the block size), having
+// computed nothing: the caller then runs bfs_pass.
+__device__ __forceinline__ bool async_bfs_pass(const BfsParams& P, Team& t, Shared& S, int32_t o,
+                                               int32_t end, int32_t root, uint32_t tag, int parity,
+                                               int32_t& ecc, uint64_t& lastkey,
+                                               int32_t* found_end) {
+  const long long clk0 = wall_clock64();
+  const int B = blockDim.x;
+  int32_t* tail = t.ctl->tail + parity * 3;
+  const int32_t ring = end - o;
+  if (t.wid == 0 && threadIdx.x == 0) {
+    const int4 ri = P.vinfo[root];
+    __hip_atomic_store(&P.dkey[root], dist_key(tag, 0), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+    st_rec(&P.qi[o], make_int4(root, ri.x, ri.y, 0));
+    for (int i = 0; i < 3; ++i) st_relaxed(tail + i, 0);
+    st_relaxed(&t.ctl->a_ecc[parity], 0);
+    st_relaxed(&t.ctl->a_cnt[parity], 0);
+    __hip_atomic_store(&t.ctl->a_key[parity], kMaxKey, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&t.ctl->pass_m[parity], 0ll, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  team_barrier(t, S, false);
+  if (t.aborted) return true;
+  int32_t g_b = 0, g_e = 1;  // the frontier: virtual ring indices [g_b, g_e)
+  int32_t rounds = 0;
+  bool overflow = false;
+  while (true) {
+    const int l3 = rounds % 3;
+    int32_t lo, hi;
+    my_chunk(g_b, g_e, t.W, t.wid, lo, hi);
+    int32_t n_glob = hi - lo;
+    const int32_t room = ring - (g_e - g_b);  // ring slots the next frontier may use
+    int cb = 0;
+    int32_t own_n = 0;
+    if (threadIdx.x == 0) {
+      S.spill = 0;
+      S.ovf = 0;
+    }
+    for (int step = 0; step < P.rebalance; ++step) {
+      if (threadIdx.x == 0) S.cnt = 0;
+      __syncthreads();
+      for (int32_t i = threadIdx.x; i < n_glob + own_n; i += B) {
+        int4 e;
+        if (i < n_glob) {
+          e = ld_rec(P, ring_pos(o, ring, lo + i));
+        } else {
+          const int32_t j = i - n_glob;
+          e = make_int4(S.u.own[cb][j][0], S.u.own[cb][j][1], S.u.own[cb][j][2],
+                        S.u.own[cb][j][3]);
+        }
+        const int32_t u = e.x;
+        const int32_t du = e.w;
+        // a record whose vertex has since been reached by a shorter path is
+        // superseded (the vertex is expanded again from that path)
+        const unsigned long long cur =
+            __hip_atomic_load(&P.dkey[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned long long want = dist_key(tag, du + 1);
+        for (int32_t k0 = e.y; k0 < e.z; k0 += kRB) {
+          int32_t nb[kRB];
+          load_batch(P.colidx, k0, e.z, u, nb);
+          if (cur != dist_key(tag, du)) break;
+          int4 inf[kRB];
+          unsigned long long old[kRB];
+#pragma unroll
+          for (int j = 0; j < kRB; ++j) inf[j] = P.vinfo[nb[j]];
+          // past-the-row lanes and self loops hit u, whose word beats want
+#pragma unroll
+          for (int j = 0; j < kRB; ++j) old[j] = atomicMax(&P.dkey[nb[j]], want);
+          unsigned mask = 0;
+#pragma unroll
+          for (int j = 0; j < kRB; ++j) mask |= (old[j] < want ? 1u : 0u) << j;
+          if (mask == 0) continue;
+          int32_t idx = atomicAdd(&S.cnt, __popc(mask));
+#pragma unroll
+          for (int j = 0; j < kRB; ++j) {
+            if (!(mask >> j & 1u)) continue;
+            if (idx < kOwnCap) {
+              S.u.own[cb ^ 1][idx][0] = nb[j];
+              S.u.own[cb ^ 1][idx][1] = inf[j].x;
+              S.u.own[cb ^ 1][idx][2] = inf[j].y;
+              S.u.own[cb ^ 1][idx][3] = du + 1;
+            } else {
+              // straight into the next round's frontier
+              const int32_t at = atomicAdd(tail + l3, 1);
+              if (at < room) {
+                st_rec(&P.qi[ring_pos(o, ring, g_e + at)], make_int4(nb[j], inf[j].x, inf[j].y,
+                                                                     du + 1));
+              } else {
+                S.ovf = 1;
+              }
+              S.spill = 1;
+            }
+            ++idx;
+          }
+        }
+      }
+      __syncthreads();
+      const int32_t cnt = S.cnt;
+      own_n = cnt < kOwnCap ? cnt : kOwnCap;
+      cb ^= 1;
+      n_glob = 0;
+      if (own_n == 0) break;
+    }
+    // the rest of this work-group's records go to the next round's frontier
+    if (threadIdx.x == 0) {
+      S.base = own_n > 0 ? atomicAdd(tail + l3, own_n) : 0;
+      if (own_n > 0) S.spill = 1;
+    }
+    __syncthreads();
+    for (int32_t i = threadIdx.x; i < own_n; i += B) {
+      const int32_t at = S.base + i;
+      if (at < room) {
+        st_rec(&P.qi[ring_pos(o, ring, g_e + at)],
+               make_int4(S.u.own[cb][i][0], S.u.own[cb][i][1], S.u.own[cb][i][2],
+                         S.u.own[cb][i][3]));
+      } else {
+        S.ovf = 1;
+      }
+    }
+    __syncthreads();
+    const bool wrote = S.spill != 0;
+    if (wrote) {
+      // records in qi must be complete before this work-group arrives
+      drain_memory_ops();
+      __syncthreads();
+    }
+    if (t.wid == 0 && threadIdx.x == 0) {
+      // the counter two rounds ahead: free now, needed after the next barrier
+      st_relaxed(tail + (rounds + 1) % 3, 0);
+      drain_memory_ops();
+    }
+    // payload: a flag for records written, a count of 1 for an overflow
+    slot_exchange(t, S, (wrote ? 0x80000000u : 0u) | (S.ovf ? 1u : 0u), false, false);
+    if (t.aborted) return true;
+    if (threadIdx.x == 0) {
+      S.nspill = 0;
+      if (S.wspill != 0) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        S.nspill = ld_relaxed(tail + l3);
+      }
+      S.total = S.wtot;
+    }
+    __syncthreads();
+    if (S.total != 0) {
+      overflow = true;
+      break;
+    }
+    const int32_t total = S.nspill;
+    ++rounds;
+    if (total == 0) break;
+    g_b = g_e;
+    g_e += total;
+    // bounds that a correct pass never reaches (index range, round count,
+    // the device wait limit for the whole pass)
+    if (g_e < 0 || rounds > 4 * ring + 16 || wall_clock64() - clk0 > kWaitLimitTicks) {
+      if (threadIdx.x == 0) flag_error(t.g, RCM_ERR_ABORTED, 11, t.comp);
+      t.aborted = true;
+      return true;
+    }
+  }
+  // every update of the pass is complete and visible before the sweep
+  team_barrier(t, S, false);
+  if (t.aborted || overflow) return !overflow;
+  // sweep: this pass's distances are final
+  int32_t my_max = -1, my_cnt = 0;
+  uint64_t my_key = kMaxKey;
+  long long my_m = 0;
+  for (int32_t v = t.wid * B + threadIdx.x; v < P.n; v += t.W * B) {
+    const unsigned long long kv = P.dkey[v];
+    if (static_cast<uint32_t>(kv >> 32) != tag) continue;
+    const int32_t d = static_cast<int32_t>(0xFFFFFFFFu - static_cast<uint32_t>(kv));
+    ++my_cnt;
+    // the visited stamp, as a level-synchronous pass leaves it (the search
+    // for the other components skips the stamped vertices of vertex 0's)
+    __hip_atomic_store(&P.visit[v], static_cast<int32_t>(tag & 63u), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+    if (P.label_mode != 0) {
+      my_m += P.vinfo[v].z;
+      __hip_atomic_store(&P.claim[v], static_cast<uint32_t>(t.anchor - d), __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (d >= my_max) {
+      const uint64_t kk = pack_key(P.vinfo[v].z, v);
+      if (d > my_max) {
+        my_max = d;
+        my_key = kk;
+      } else if (kk < my_key) {
+        my_key = kk;
+      }
+    }
+  }
+  // the largest distance first (with the counts), then the minimum key there
+  if (threadIdx.x == 0) S.cnt = -1;
+  __syncthreads();
+  atomicMax(&S.cnt, my_max);
+  const long long cnt_sum = block_sum_i64(my_cnt, S.red);
+  const long long m_sum = block_sum_i64(my_m, S.red);
+  const int32_t wg_max = S.cnt;
+  if (threadIdx.x == 0) {
+    if (wg_max >= 0) atomicMax(&t.ctl->a_ecc[parity], wg_max);
+    if (cnt_sum != 0) atomicAdd(&t.ctl->a_cnt[parity], static_cast<int32_t>(cnt_sum));
+    if (m_sum != 0)
+      __hip_atomic_fetch_add(&t.ctl->pass_m[parity], m_sum, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+  }
+  team_barrier(t, S, false);
+  if (t.aborted) return true;
+  const int32_t e_all = ld_relaxed(&t.ctl->a_ecc[parity]);
+  if (my_max == e_all && my_key != kMaxKey) atomicMin(&t.ctl->a_key[parity], my_key);
+  team_barrier(t, S, false);
+  if (t.aborted) return true;
+  ecc = e_all;
+  lastkey = __hip_atomic_load(&t.ctl->a_key[parity], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const int32_t count = ld_relaxed(&t.ctl->a_cnt[parity]);
+  if (P.label_mode != 0)
+    t.pm = __hip_atomic_load(&t.ctl->pass_m[parity], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (found_end != nullptr) {
+    *found_end = o + count;
+  } else if (count != end - o) {
+    // the pass reached more or fewer vertices than the component holds
+    if (threadIdx.x == 0 && t.wid == 0)
+      flag_error(t.g, RCM_ERR_NOT_SYMMETRIC, 12, t.comp, 0, ecc, count, end - o, end);
+    t.aborted = true;
+    return true;
+  }
+  if (t.wid == 0 && threadIdx.x == 0) {
+    t.ctl->clk[0] += wall_clock64() - clk0;
+    t.ctl->clk[2] += ecc + 1;
+  }
+  return true;
+}
+
+// ---------------------------------------------------------------------------
 // Labelled BFS (Algorithm 3).
 // ---------------------------------------------------------------------------
 
@@ -1491,7 +1757,23 @@ __device__ __forceinline__ void order_component(const BfsParams& P, Team& t, Sha
   // level orders' key anchor (the first pass of a component of unknown size
   // writes provisional keys, which later passes replace)
   t.anchor = task.anchor >= 0 ? task.anchor : (size >= 0 ? o + size - 1 : end - 1);
-  bfs_pass(P, t, S, o, end, task.seed, 1, 0, ecc, lastkey, size >= 0 ? nullptr : &found);
+  // A level structure of the search: asynchronous for a team on a large
+  // component (it sweeps all n vertices once at its end), else (or when its
+  // ring of records would overflow) level-synchronous.  The tag makes every
+  // (component, pass) distinct and grows with the pass.
+  const bool try_async = P.async_search != 0 && t.W > 1 && task.index < (1 << 25) &&
+                         (size < 0 || static_cast<long long>(size) * 8 >= P.n);
+  auto search_pass = [&](int32_t from, int32_t epoch, int parity, int32_t& e, uint64_t& lk,
+                         int32_t* found_at) {
+    if (try_async && epoch < 64) {
+      const uint32_t tag =
+          (static_cast<uint32_t>(task.index + 1) << 6) | static_cast<uint32_t>(epoch);
+      if (async_bfs_pass(P, t, S, o, end, from, tag, parity, e, lk, found_at)) return;
+      if (t.aborted) return;
+    }
+    bfs_pass(P, t, S, o, end, from, epoch, parity, e, lk, found_at);
+  };
+  search_pass(task.seed, 1, 0, ecc, lastkey, size >= 0 ? nullptr : &found);
   if (t.aborted) return;
   if (size < 0) {
     size = found - o;
@@ -1526,7 +1808,7 @@ __device__ __forceinline__ void order_component(const BfsParams& P, Team& t, Sha
       ecc = levels - 1;
       labelled = true;
     } else {
-      bfs_pass(P, t, S, o, end, v, nbfs, (nbfs - 1) & 1, ecc, lastkey, nullptr);
+      search_pass(v, nbfs, (nbfs - 1) & 1, ecc, lastkey, nullptr);
       if (t.aborted) return;
     }
   }
@@ -1538,7 +1820,7 @@ __device__ __forceinline__ void order_component(const BfsParams& P, Team& t, Sha
     // the search's last one or, for Algorithm 4's pick, one more
     if (P.pp_variant == 1) {
       uint64_t k2 = 0;
-      bfs_pass(P, t, S, o, end, root, nbfs + 1, nbfs & 1, ecc, k2, nullptr);
+      search_pass(root, nbfs + 1, nbfs & 1, ecc, k2, nullptr);
       if (t.aborted) return;
     }
     // every vertex now holds its level and block start; the host sorts

@@ -54,6 +54,9 @@ struct alignas(128) TeamCtl {
   long long msum;                // sum of degrees of the current component
   long long pass_m[2];           // level orders: sum of degrees reached by the
                                  // current unlabelled pass, [pass parity]
+  int32_t a_ecc[2];              // asynchronous passes, [pass parity]: largest
+  int32_t a_cnt[2];              // distance, vertices reached, and the minimum
+  unsigned long long a_key[2];   // (deg << 32 | id) at the largest distance
   unsigned long long lastkey;    // min (deg << 32 | id) over the last level of a
                                  // labelled pass that also serves the search
   int32_t task;                  // large-component task handed to the team
@@ -292,7 +295,9 @@ struct BfsParams {
   int32_t reverse_mode;
   int32_t narrow_cutoff;
   int32_t rebalance;          // wide unlabelled levels between redistributions
-  int32_t label_mode;         // 0: labelled BFS; 1, 2: level order (keys left in iperm)
+  int32_t label_mode;         // 0: labelled BFS; 1, 2: level order (keys left in claim)
+  int32_t async_search;       // 1: large components' searches run asynchronous passes
+  unsigned long long* dkey;   // per vertex: pass tag << 32 | ~distance (asynchronous passes)
 };
 
 // One launch of the ordering kernel over the task lists in p; cooperative

@@ -76,7 +76,8 @@ class Options(ctypes.Structure):
         ("max_teams", ctypes.c_int32),
         ("rebalance_levels", ctypes.c_int32),
         ("label_mode", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 5),
+        ("async_search", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 4),
     ]
 
 
@@ -138,7 +139,7 @@ def status_string(status: int) -> str:
 
 def make_options(*, pp_variant=0, reverse_mode=0, check_full=False, team_size=0,
                  block_threads=0, small_cutoff=0, narrow_cutoff=0, small_threads=0,
-                 max_teams=0, rebalance_levels=0, label_mode=0) -> Options:
+                 max_teams=0, rebalance_levels=0, label_mode=0, async_search=0) -> Options:
     o = Options()
     o.pp_variant = int(pp_variant)
     o.reverse_mode = int(reverse_mode)
@@ -151,6 +152,7 @@ def make_options(*, pp_variant=0, reverse_mode=0, check_full=False, team_size=0,
     o.max_teams = int(max_teams)
     o.rebalance_levels = int(rebalance_levels)
     o.label_mode = int(label_mode)
+    o.async_search = int(async_search)
     return o
 
 

@@ -106,6 +106,12 @@ def test_invalid_arguments_need_no_gpu():
     bad = rcm.make_options(max_teams=65)
     status, _ = rcm.order_raw(0, 0, 0, 0, options=bad)
     assert status == rcm.ERR_INVALID_ARGUMENT
+    bad = rcm.make_options(async_search=-2)
+    status, _ = rcm.order_raw(0, 0, 0, 0, options=bad)
+    assert status == rcm.ERR_INVALID_ARGUMENT
+    bad = rcm.make_options(async_search=2)
+    status, _ = rcm.order_raw(0, 0, 0, 0, options=bad)
+    assert status == rcm.ERR_INVALID_ARGUMENT
     bad = rcm.make_options(label_mode=3)
     status, _ = rcm.order_raw(0, 0, 0, 0, options=bad)
     assert status == rcm.ERR_INVALID_ARGUMENT

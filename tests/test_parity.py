@@ -297,3 +297,47 @@ def test_level_orders_batched():
         _check_batch(graphs, label_mode=label_mode)
         _check_batch(graphs, label_mode=label_mode, small_cutoff=500, team_size=4,
                      pp_variant=1, reverse_mode=1)
+
+
+# ---------------------------------------------------------------------------
+# Asynchronous (label-correcting) search passes: same results
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed", range(10))
+def test_async_search_random(seed):
+    g = _random_graph(700 + seed)
+    check(g, async_search=1, small_cutoff=1, team_size=2 + seed % 7, pp_variant=seed % 2,
+          reverse_mode=(seed // 2) % 2)
+    check(g, async_search=1, small_cutoff=1, team_size=8, rebalance_levels=1 + seed % 4,
+          narrow_cutoff=16, label_mode=seed % 3)
+
+
+def test_async_search_grids():
+    check(I.config(0, seed=4), async_search=1, small_cutoff=1)
+    check(I.config(0, seed=4), async_search=1, small_cutoff=1, team_size=3, rebalance_levels=2)
+    # the 128^3 grid at full size, in the benchmark's launch configuration
+    check(I.config(1), async_search=1)
+    check(I.config(1), async_search=1, label_mode=2)
+    check(I.config(1), async_search=1, pp_variant=1, reverse_mode=1, rebalance_levels=3)
+
+
+def test_async_search_batched():
+    graphs = [_random_graph(800 + i) for i in range(6)] + [I.path(1), I.complete(5)]
+    graphs += [I.grid2d(40 + 5 * i, 30, seed=900 + i) for i in range(3)]
+    _check_batch(graphs, async_search=1, small_cutoff=500, team_size=4)
+    _check_batch(graphs, async_search=1, small_cutoff=500, team_size=4, label_mode=1,
+                 pp_variant=1, reverse_mode=1)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_level_synchronous_search(seed):
+    """The level-synchronous search passes (async_search=-1) on the team path."""
+    g = _random_graph(1000 + seed)
+    check(g, async_search=-1, small_cutoff=1, team_size=2 + seed, narrow_cutoff=16 * seed,
+          pp_variant=seed % 2, label_mode=seed % 3)
+
+
+@pytest.mark.parametrize("team,threads,narrow", [(64, 256, 0), (16, 512, 1024)])
+def test_level_synchronous_grid_128_cubed(team, threads, narrow):
+    check(I.config(1), async_search=-1, team_size=team, block_threads=threads,
+          narrow_cutoff=narrow)
