@@ -45,7 +45,7 @@ WORKLOADS = {
 # sources at the time of the measurement, so a changed kernel reports null.
 # Summaries with the commands: profiles/k_order_<workload>_hbm_counters.md.
 MEASURED_TRAFFIC = {
-    "grid3d_128x128x128": ("77bda7e1838dcbf9", 5618950066),
+    "grid3d_128x128x128": ("0b14df622f34c8aa", 6190229834),
 }
 KERNEL_SOURCES = ("paper_1610_08128_amd/csrc/rcm_bfs.hip",
                   "paper_1610_08128_amd/csrc/rcm_common.hpp")
@@ -76,20 +76,27 @@ def unlabelled_passes(k_pp: int) -> int:
     return k_pp - 1 if k_pp >= 3 else k_pp
 
 
-def order_kernel_bytes(n: int, m: int, k_pp: int) -> int:
+def order_kernel_bytes(n: int, m: int, k_pp: int, asynchronous: bool = True) -> int:
     """Algorithmic HBM bytes of one launch of the ordering kernel for a
     component of n vertices and m directed off-diagonal entries:
-      every unlabelled BFS pass: 8m + 20n (rowptr 8n, colidx 4m, visited
-        gather 4m, visited write 4n, frontier write + read 8n);
+      every unlabelled BFS pass, level-synchronous: 8m + 20n (rowptr 8n,
+        colidx 4m, visited gather 4m, visited write 4n, frontier write +
+        read 8n);
+      every unlabelled pass, asynchronous (the default for a large
+        component): 12m + 36n (colidx 4m, distance-word atomics 8m; per
+        vertex the record gather 16n and the superseded-record check 8n; the
+        final sweep reads the distance words 8n and writes the stamps 4n);
       the labelled BFS: 8m + 48n (adds claims, degrees, labels);
       the reversal: 12n (read the order, write perm and iperm)."""
-    return unlabelled_passes(k_pp) * (8 * m + 20 * n) + (8 * m + 48 * n) + 12 * n
+    per_pass = (12 * m + 36 * n) if asynchronous else (8 * m + 20 * n)
+    return unlabelled_passes(k_pp) * per_pass + (8 * m + 48 * n) + 12 * n
 
 
-def whole_call_bytes(n: int, nnz: int, m: int, k_pp: int) -> int:
+def whole_call_bytes(n: int, nnz: int, m: int, k_pp: int, asynchronous: bool = True) -> int:
     """Algorithmic bytes of a whole ordering: the kernel above plus the
     input scan (4n + 4nnz) and the result scan (8n + 8nnz)."""
-    return order_kernel_bytes(n, m, k_pp) + (4 * n + 4 * nnz) + (8 * n + 8 * nnz)
+    return (order_kernel_bytes(n, m, k_pp, asynchronous) + (4 * n + 4 * nnz)
+            + (8 * n + 8 * nnz))
 
 
 def cpu_baseline(g, budget_s: float):
@@ -535,6 +542,9 @@ def main():
     ap.add_argument("--serve-pool", type=int, default=32,
                     help="distinct request graphs generated for --mode serve (reused cyclically)")
     ap.add_argument("--team-size", type=int, default=0)
+    ap.add_argument("--async-search", type=int, default=0, choices=[-1, 0, 1],
+                    help="search passes of the large component: 0 = auto (asynchronous), "
+                         "1 = asynchronous, -1 = level-synchronous")
     ap.add_argument("--block-threads", type=int, default=0)
     ap.add_argument("--cpu-budget", type=float, default=12.0,
                     help="seconds of oracle work for the CPU baseline (0 = skip)")
@@ -568,7 +578,8 @@ def main():
     dev = torch.device("cuda", 0)
     rp = torch.from_numpy(g.rowptr).to(dev)
     ci = torch.from_numpy(g.colidx).to(dev)
-    opts = dict(team_size=args.team_size, block_threads=args.block_threads)
+    opts = dict(team_size=args.team_size, block_threads=args.block_threads,
+                async_search=args.async_search)
     ws = torch.empty(rcm.workspace_bytes(g.n, g.nnz, **opts), dtype=torch.uint8, device=dev)
     stream = torch.cuda.Stream(device=dev)
     if args.calibrate_copy_mb > 0:
@@ -604,8 +615,9 @@ def main():
     teps = st["edges_traversed"] * args.steps / dt
 
     roofline = None
+    asynchronous = args.async_search >= 0
     if k_pp is not None:
-        kbytes = order_kernel_bytes(g.n, m, k_pp)
+        kbytes = order_kernel_bytes(g.n, m, k_pp, asynchronous)
         kavg_s = float(np.mean(kern_ms)) / 1000.0
         achieved = kbytes / kavg_s / 1e9
         roofline = {
@@ -620,7 +632,7 @@ def main():
             "algorithmic_bytes_per_launch": kbytes,
             "avg_launch_ms": round(kavg_s * 1000.0, 4),
             "whole_call_hbm_frac": round(
-                whole_call_bytes(g.n, g.nnz, m, k_pp) / (ms_per_step / 1000.0) / 1e9
+                whole_call_bytes(g.n, g.nnz, m, k_pp, asynchronous) / (ms_per_step / 1000.0) / 1e9
                 / HBM_PEAK_GBS, 5),
         }
 
@@ -651,6 +663,7 @@ def main():
             "bfs_passes": st["num_bfs"] + 1,
             "team_size": args.team_size or 64,
             "block_threads": args.block_threads or 256,
+            "search_passes": "asynchronous" if asynchronous else "level-synchronous",
         },
         "teps": round(teps, 1),
         "nnz_per_s": round(g.nnz * args.steps / dt, 1),
