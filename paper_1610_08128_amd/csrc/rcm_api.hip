@@ -316,6 +316,8 @@ rcm_status run(const Graph& gin, const int32_t* seg_off_host, const Opts& opt, c
   P.rebalance = opt.rebalance;
   P.label_mode = opt.label_mode;
   P.async_search = opt.async_search;
+  P.seg_off = g.seg_off;
+  P.nseg = g.nseg;
   P.dkey = reinterpret_cast<unsigned long long*>(ws + L.dkey);
   // distance words of the asynchronous passes start below every pass tag
   if (opt.async_search) HIP_TRY(hipMemsetAsync(P.dkey, 0, 8 * static_cast<size_t>(g.n), s));

@@ -963,15 +963,16 @@ __device__ __forceinline__ int32_t ring_pos(int32_t o, int32_t ring, int32_t v) 
 // record is skipped), with no team barrier between the steps.  One barrier
 // per round then spreads all records evenly (qi[o, end) serves as a ring of
 // frontier records) and detects the end.  Finally a sweep over the vertices
-// carrying this pass's tag yields the eccentricity, the last level's minimum
+// of the component's graph [seg_b, seg_e) (a component never leaves its
+// graph) carrying this pass's tag yields the eccentricity, the last level's minimum
 // key, the number of vertices reached (the component's size when found_end
 // is given) and, for level orders, the keys.  Returns false if the ring
 // would overflow (a frontier and its successor above the block size), having
 // computed nothing: the caller then runs bfs_pass.
 __device__ __forceinline__ bool async_bfs_pass(const BfsParams& P, Team& t, Shared& S, int32_t o,
                                                int32_t end, int32_t root, uint32_t tag, int parity,
-                                               int32_t& ecc, uint64_t& lastkey,
-                                               int32_t* found_end) {
+                                               int32_t seg_b, int32_t seg_e, int32_t& ecc,
+                                               uint64_t& lastkey, int32_t* found_end) {
   const long long clk0 = wall_clock64();
   const int B = blockDim.x;
   int32_t* tail = t.ctl->tail + parity * 3;
@@ -1134,7 +1135,7 @@ __device__ __forceinline__ bool async_bfs_pass(const BfsParams& P, Team& t, Shar
   int32_t my_max = -1, my_cnt = 0;
   uint64_t my_key = kMaxKey;
   long long my_m = 0;
-  for (int32_t v = t.wid * B + threadIdx.x; v < P.n; v += t.W * B) {
+  for (int32_t v = seg_b + t.wid * B + threadIdx.x; v < seg_e; v += t.W * B) {
     const unsigned long long kv = P.dkey[v];
     if (static_cast<uint32_t>(kv >> 32) != tag) continue;
     const int32_t d = static_cast<int32_t>(0xFFFFFFFFu - static_cast<uint32_t>(kv));
@@ -1758,17 +1759,23 @@ __device__ __forceinline__ void order_component(const BfsParams& P, Team& t, Sha
   // writes provisional keys, which later passes replace)
   t.anchor = task.anchor >= 0 ? task.anchor : (size >= 0 ? o + size - 1 : end - 1);
   // A level structure of the search: asynchronous for a team on a large
-  // component (it sweeps all n vertices once at its end), else (or when its
-  // ring of records would overflow) level-synchronous.  The tag makes every
-  // (component, pass) distinct and grows with the pass.
-  const bool try_async = P.async_search != 0 && t.W > 1 && task.index < (1 << 25) &&
-                         (size < 0 || static_cast<long long>(size) * 8 >= P.n);
+  // component (it sweeps the vertices of the component's graph once at its
+  // end, so the component must be at least an eighth of them), else (or
+  // when its ring of records would overflow) level-synchronous.  The tag
+  // makes every (component, pass) distinct and grows with the pass.
+  const int seg = P.nseg > 1 ? find_segment(P.seg_off, P.nseg, task.seed) : 0;
+  const int32_t seg_b = P.nseg > 1 ? P.seg_off[seg] : 0;
+  const int32_t seg_e = P.nseg > 1 ? P.seg_off[seg + 1] : P.n;
+  const bool try_async =
+      P.async_search != 0 && t.W > 1 && task.index < (1 << 25) &&
+      (size < 0 || static_cast<long long>(size) * 8 >= static_cast<long long>(seg_e - seg_b));
   auto search_pass = [&](int32_t from, int32_t epoch, int parity, int32_t& e, uint64_t& lk,
                          int32_t* found_at) {
     if (try_async && epoch < 64) {
       const uint32_t tag =
           (static_cast<uint32_t>(task.index + 1) << 6) | static_cast<uint32_t>(epoch);
-      if (async_bfs_pass(P, t, S, o, end, from, tag, parity, e, lk, found_at)) return;
+      if (async_bfs_pass(P, t, S, o, end, from, tag, parity, seg_b, seg_e, e, lk, found_at))
+        return;
       if (t.aborted) return;
     }
     bfs_pass(P, t, S, o, end, from, epoch, parity, e, lk, found_at);

@@ -297,6 +297,8 @@ struct BfsParams {
   int32_t rebalance;          // wide unlabelled levels between redistributions
   int32_t label_mode;         // 0: labelled BFS; 1, 2: level order (keys left in claim)
   int32_t async_search;       // 1: large components' searches run asynchronous passes
+  const int32_t* seg_off;     // vertex offsets of the graphs (segments), nseg + 1
+  int32_t nseg;
   unsigned long long* dkey;   // per vertex: pass tag << 32 | ~distance (asynchronous passes)
 };
 
