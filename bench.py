@@ -45,7 +45,7 @@ WORKLOADS = {
 # sources at the time of the measurement, so a changed kernel reports null.
 # Summaries with the commands: profiles/k_order_<workload>_hbm_counters.md.
 MEASURED_TRAFFIC = {
-    "grid3d_128x128x128": ("0b14df622f34c8aa", 6190229834),
+    "grid3d_128x128x128": ("6d73284a58db0608", 6365776625),
 }
 KERNEL_SOURCES = ("paper_1610_08128_amd/csrc/rcm_bfs.hip",
                   "paper_1610_08128_amd/csrc/rcm_common.hpp")
@@ -661,7 +661,7 @@ def main():
             "nnz": g.nnz,
             "pseudo_diameter": st["pseudo_diameter"],
             "bfs_passes": st["num_bfs"] + 1,
-            "team_size": args.team_size or 64,
+            "team_size": args.team_size or (256 if g.n >= (1 << 18) else 64),
             "block_threads": args.block_threads or 256,
             "search_passes": "asynchronous" if asynchronous else "level-synchronous",
         },

@@ -99,8 +99,10 @@ typedef struct {
                             asymmetric patterns (NOT_SYMMETRIC); costs
                             O(sum of squared row lengths)                      */
   int32_t team_size;     /* work-groups cooperating on one large component;
-                            0 = auto (64, eight per XCD; 8 in batched calls);
-                            1..64                                              */
+                            0 = auto (256, one per compute unit, for graphs
+                            of at least 2^18 vertices, else 64; 8 in batched
+                            calls); 1..256, capped at the number of
+                            work-groups resident at once                      */
   int32_t block_threads; /* threads per work-group of the large-component
                             team; 0 = auto (256); 256 or 512                   */
   int32_t small_cutoff;  /* components with at most this many vertices are
@@ -145,7 +147,10 @@ typedef struct {
                             as future work).  Same result; a pass whose
                             frontier outgrows its ring falls back to the
                             level-synchronous pass                         */
-  int32_t reserved[4];
+  int32_t label_team;    /* work-groups of a team that run the labelled BFS
+                            (the others sleep meanwhile); 0 = auto (64), at
+                            most team_size is used                         */
+  int32_t reserved[3];
 } rcm_options;
 
 /* Human-readable name of a status code (static string). */

@@ -33,7 +33,7 @@ struct Opts {
   int pp_variant = 0;
   int reverse_mode = 0;
   int check_full = 0;
-  int team_size = 64;
+  int team_size = 0;  // 0: by size, see team_for
   int threads = 256;
   int small_threads = 512;
   int small_cutoff = 1 << 18;
@@ -42,7 +42,16 @@ struct Opts {
   int rebalance = 8;
   int label_mode = 0;
   int async_search = 1;
+  int label_team = 64;
 };
+
+// Auto team size of a single graph: all compute units for a large graph
+// (its asynchronous search passes speed up up to one work-group per CU),
+// 64 for a smaller one, whose narrow levels only pay for more barrier slots.
+inline int team_for(const Opts& o, int64_t n) {
+  if (o.team_size > 0) return o.team_size;
+  return n >= (1 << 18) ? 256 : 64;
+}
 
 // Auto values differ for batched calls: many components of many graphs share
 // one launch, so more, smaller teams take the larger ones (measured on the
@@ -69,6 +78,7 @@ bool parse_options(const rcm_options* o, Opts* out, bool batched = false) {
     if (o->rebalance_levels < 0) return false;
     if (o->label_mode < 0 || o->label_mode > 2) return false;
     if (o->async_search < -1 || o->async_search > 1) return false;
+    if (o->label_team < 0 || o->label_team > kMaxTeam) return false;
     r.pp_variant = o->pp_variant;
     r.reverse_mode = o->reverse_mode;
     r.check_full = o->check_full;
@@ -81,6 +91,7 @@ bool parse_options(const rcm_options* o, Opts* out, bool batched = false) {
     if (o->rebalance_levels) r.rebalance = o->rebalance_levels;
     r.label_mode = o->label_mode;
     if (o->async_search) r.async_search = o->async_search > 0 ? 1 : 0;
+    if (o->label_team) r.label_team = o->label_team;
   }
   *out = r;
   return true;
@@ -90,7 +101,7 @@ bool parse_options(const rcm_options* o, Opts* out, bool batched = false) {
 struct Layout {
   size_t vinfo, beta, parent, flags, pos, csize, seeds, visit, claim, qi, tmp, iperm, dkey;
   size_t sizes, offs, results, t_single, t_small, t_big, scan_blk;
-  size_t seg_off, comp_seg_off, segstats, gctl, teams, slots, small_ctl, misc, sched;
+  size_t seg_off, comp_seg_off, segstats, gctl, teams, slots, sub_slots, small_ctl, misc, sched;
   size_t rowptr_g, colidx_g;
   size_t total;
 };
@@ -130,6 +141,7 @@ Layout make_layout(int64_t n, int64_t nnz, int64_t nseg, bool batched, int teams
   L.gctl = take(sizeof(GlobalCtl));
   L.teams = take(sizeof(TeamCtl) * kMaxConcurrentTeams);
   L.slots = take(sizeof(TeamSlots) * kMaxConcurrentTeams);
+  L.sub_slots = take(sizeof(TeamSlots) * kMaxConcurrentTeams);
   L.small_ctl = take(sizeof(TeamCtl) * static_cast<size_t>(teams_small));
   L.misc = take(256);
   L.sched = take(128 * sizeof(int32_t));
@@ -323,9 +335,12 @@ rcm_status run(const Graph& gin, const int32_t* seg_off_host, const Opts& opt, c
   if (opt.async_search) HIP_TRY(hipMemsetAsync(P.dkey, 0, 8 * static_cast<size_t>(g.n), s));
   P.teams = teams;
   P.slots = slots;
+  P.sub_slots = reinterpret_cast<TeamSlots*>(ws + L.sub_slots);
+  P.label_team = opt.label_team;
   P.small_teams = small_ctl;
   P.queues = misc + 16;
-  P.team_size = opt.team_size;
+  const int team_auto = team_for(opt, g.n);
+  P.team_size = team_auto;
   // One launch of the ordering kernel: teams of team_size work-groups take
   // the large components, largest first, and single-work-group blocks the
   // small ones; team work-groups join the small list once the large one is
@@ -342,10 +357,14 @@ rcm_status run(const Graph& gin, const int32_t* seg_off_host, const Opts& opt, c
     if (n_big > 0) {
       threads = opt.threads;
       const int resident = max_team_blocks(threads);
-      if (resident < opt.team_size) return RCM_ERR_HIP;
-      const int room = n_small > 0 ? std::max(resident / 2, opt.team_size) : resident;
-      nteams = std::max(1, std::min({n_big, opt.max_teams, room / opt.team_size}));
-      P.big_blocks = nteams * opt.team_size;
+      if (resident < 1) return RCM_ERR_HIP;
+      // a team never exceeds what is resident at once (the launch is
+      // cooperative)
+      const int team = std::min(team_auto, resident);
+      P.team_size = team;
+      const int room = n_small > 0 ? std::max(resident / 2, team) : resident;
+      nteams = std::max(1, std::min({n_big, opt.max_teams, room / team}));
+      P.big_blocks = nteams * team;
       const int extra = n_small > 0 ? std::min(n_small, resident - P.big_blocks) : 0;
       blocks = std::min(P.big_blocks + std::max(extra, 0), kSmallTeams);
     } else {
@@ -358,6 +377,7 @@ rcm_status run(const Graph& gin, const int32_t* seg_off_host, const Opts& opt, c
     if (nteams > 0) {
       HIP_TRY(hipMemsetAsync(teams, 0, sizeof(TeamCtl) * nteams, s));
       HIP_TRY(hipMemsetAsync(slots, 0, sizeof(TeamSlots) * nteams, s));
+      HIP_TRY(hipMemsetAsync(P.sub_slots, 0, sizeof(TeamSlots) * nteams, s));
     }
     if (n_small > 0) HIP_TRY(hipMemsetAsync(small_ctl, 0, sizeof(TeamCtl) * blocks, s));
     timer.kmark(kslot, true);

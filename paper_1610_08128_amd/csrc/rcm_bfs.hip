@@ -57,6 +57,9 @@ struct Team {
   int wid;
   int comp;                 // index of the component being ordered (diagnostics)
   uint32_t seq;             // team barriers passed (every thread, in step)
+  TeamSlots* sub_slots;     // the labelling sub-team's barrier slots
+  uint32_t sub_seq;         // barriers the labelling sub-team has passed
+  unsigned long long ldone; // labelled passes seen finished
   int32_t anchor;           // level orders: final position of the component's
                             // Cuthill-McKee label 0
   long long pm;             // level orders: degrees of the vertices this thread
@@ -158,8 +161,8 @@ __device__ __forceinline__ void drain_memory_ops() {
 
 // Team barrier that also exchanges one 32-bit payload per work-group (bit 31
 // a flag, bits 0..30 a count): every work-group stores (barrier number,
-// payload) into its own slot, and lanes 0..W-1 of wave 0 each wait for one
-// work-group's slot.  Afterwards S.wsum[w] holds work-group w's count,
+// payload) into its own slot, and the lanes of wave 0 wait for the W slots
+// (lane l for work-groups l, l + 64, ...).  Afterwards S.wsum[w] holds work-group w's count,
 // S.wpre the sum over work-groups before this one, S.wtot the total, S.wmax
 // the largest, S.wspill the number of flags.  drain: every wave first
 // completes its own memory operations (whatever another work-group reads
@@ -178,14 +181,29 @@ __device__ __forceinline__ void slot_exchange(Team& t, Shared& S, uint32_t paylo
     if (lane == 0)
       __hip_atomic_store(base + t.wid * 16, (static_cast<unsigned long long>(seq) << 32) | payload,
                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    unsigned long long v = 0;
+    // lane l waits for work-groups l, l + 64, ... (kMaxTeam / 64 at most),
+    // polling all of them in each round trip
+    constexpr int kPer = kMaxTeam / 64;
+    unsigned long long v[kPer];
     bool ok = true;
-    if (lane < t.W) {
+    {
+      unsigned pending = 0;
+#pragma unroll
+      for (int j = 0; j < kPer; ++j)
+        if (lane + 64 * j < t.W) pending |= 1u << j;
       long spins = 0;
       const long long t0 = wall_clock64();
-      while (true) {
-        v = __hip_atomic_load(base + lane * 16, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (static_cast<uint32_t>(v >> 32) == seq) break;
+      while (pending != 0) {
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+          if (!(pending >> j & 1u)) continue;
+          v[j] = __hip_atomic_load(base + (lane + 64 * j) * 16, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+          if (static_cast<uint32_t>(v[j] >> 32) == seq) pending &= ~(1u << j);
+        }
+        if (pending == 0) break;
+        // long waits back off, so that waiting lanes leave memory to the work
+        if (spins > 64) __builtin_amdgcn_s_sleep(1);
         if ((++spins & 255) == 0) {
           if (ld_relaxed(&t.g->error) != 0) { ok = false; break; }
           if (wall_clock64() - t0 > kWaitLimitTicks) {
@@ -196,22 +214,31 @@ __device__ __forceinline__ void slot_exchange(Team& t, Shared& S, uint32_t paylo
         }
       }
     }
+    int32_t below = 0, all = 0, mx = 0, fl = 0;
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+      const int w = lane + 64 * j;
+      if (w >= t.W) continue;
+      const uint32_t p = static_cast<uint32_t>(v[j]);
+      const int32_t c = ok ? static_cast<int32_t>(p & 0x7FFFFFFFu) : 0;
+      S.wsum[w] = c;
+      below += w < t.wid ? c : 0;
+      all += c;
+      mx = c > mx ? c : mx;
+      fl += ok ? static_cast<int32_t>(p >> 31) : 0;
+    }
     const bool all_ok = __all(ok);
-    const uint32_t p = lane < t.W ? static_cast<uint32_t>(v) : 0u;
-    const int32_t c = static_cast<int32_t>(p & 0x7FFFFFFFu);
-    const int32_t incl = wave_incl_scan(c);
-    int32_t mx = c;
-    int32_t fl = static_cast<int32_t>(p >> 31);
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
+      below += __shfl_xor(below, o, 64);
+      all += __shfl_xor(all, o, 64);
       const int32_t y = __shfl_xor(mx, o, 64);
       mx = y > mx ? y : mx;
       fl += __shfl_xor(fl, o, 64);
     }
-    if (lane < t.W) S.wsum[lane] = c;
-    if (lane == t.wid) S.wpre = incl - c;
-    if (lane == 63) S.wtot = incl;
     if (lane == 0) {
+      S.wpre = below;
+      S.wtot = all;
       S.wmax = mx;
       S.wspill = fl;
       S.flag = all_ok ? 0 : 1;
@@ -1744,6 +1771,56 @@ __device__ __forceinline__ int32_t label_pass(const BfsParams& P, Team& t, Share
   return levels;
 }
 
+// The labelled BFS of a team, run by its first label_team work-groups (the
+// labelled levels gain nothing from more, unlike the search's passes) with
+// barrier slots of their own; the others sleep until it is done and then
+// take its results from the team's control block.
+__device__ __forceinline__ int32_t labelled_pass(const BfsParams& P, Team& t, Shared& S, int32_t o,
+                                                 int32_t end, int32_t root, long long* msum,
+                                                 uint64_t* lastkey) {
+  const int Wl = P.label_team < t.W ? P.label_team : t.W;
+  if (Wl >= t.W) return label_pass(P, t, S, o, end, root, msum, lastkey);
+  t.ldone += 1;
+  if (t.wid < Wl) {
+    const int W0 = t.W;
+    TeamSlots* const slots0 = t.slots;
+    const uint32_t seq0 = t.seq;
+    t.W = Wl;
+    t.slots = t.sub_slots;
+    t.seq = t.sub_seq;
+    const int32_t levels = label_pass(P, t, S, o, end, root, msum, lastkey);
+    t.sub_seq = t.seq;
+    t.W = W0;
+    t.slots = slots0;
+    t.seq = seq0;
+    if (t.aborted) return 0;
+    if (t.wid == 0 && threadIdx.x == 0) {
+      // the sub-team's last barrier completed every record and claim;
+      // msum and lastkey are already in the control block
+      st_relaxed(&t.ctl->llevels, levels);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __hip_atomic_fetch_add(&t.ctl->ldone, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    return levels;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const bool ok = wait_at_least(t, &t.ctl->ldone, t.ldone, true);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    S.state[0] = ld_relaxed(&t.ctl->llevels);
+    // narrow episodes of the sub-team happened without this work-group
+    t.woke = ld_relaxed(&t.ctl->wake);
+    S.flag = ok ? 0 : 1;
+  }
+  __syncthreads();
+  t.aborted = S.flag != 0;
+  if (t.aborted) return 0;
+  *msum = __hip_atomic_load(&t.ctl->msum, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (lastkey != nullptr)
+    *lastkey = __hip_atomic_load(&t.ctl->lastkey, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return S.state[0];
+}
+
 __device__ __forceinline__ void order_component(const BfsParams& P, Team& t, Shared& S, const CompTask& task) {
   const int32_t o = task.offset;
   // a task of unknown size (the component of vertex 0) learns it from the
@@ -1810,7 +1887,7 @@ __device__ __forceinline__ void order_component(const BfsParams& P, Team& t, Sha
         team_barrier(t, S, false);
         if (t.aborted) return;
       }
-      levels = label_pass(P, t, S, o, end, v, &m, &lastkey);
+      levels = labelled_pass(P, t, S, o, end, v, &m, &lastkey);
       if (t.aborted) return;
       ecc = levels - 1;
       labelled = true;
@@ -1834,7 +1911,7 @@ __device__ __forceinline__ void order_component(const BfsParams& P, Team& t, Sha
     levels = ecc + 1;
     m = t.pm;
   } else if (!labelled) {
-    levels = label_pass(P, t, S, o, end, root, &m, nullptr);
+    levels = labelled_pass(P, t, S, o, end, root, &m, nullptr);
     if (t.aborted) return;
   }
   if (t.wid == 0 && threadIdx.x == 0) {
@@ -1865,6 +1942,9 @@ __global__ void __launch_bounds__(512) k_order(BfsParams P) {
   t.g = P.gctl;
   t.slots = nullptr;
   t.seq = 0;
+  t.sub_slots = nullptr;
+  t.sub_seq = 0;
+  t.ldone = 0;
   t.woke = 0;
   if (threadIdx.x == 0) S.lown_ok = 0;
   t.aborted = false;
@@ -1873,6 +1953,7 @@ __global__ void __launch_bounds__(512) k_order(BfsParams P) {
     t.wid = blockIdx.x % P.team_size;
     t.ctl = P.teams + blockIdx.x / P.team_size;
     t.slots = P.slots + blockIdx.x / P.team_size;
+    t.sub_slots = P.sub_slots + blockIdx.x / P.team_size;
     while (true) {
       if (t.wid == 0 && threadIdx.x == 0)
         st_relaxed(&t.ctl->task, atomicAdd(&P.queues[0], 1));

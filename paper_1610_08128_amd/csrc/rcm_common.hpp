@@ -11,7 +11,8 @@ namespace rcm {
 
 constexpr uint32_t kUnclaimed = 0xFFFFFFFFu;
 constexpr uint64_t kMaxKey = ~0ull;
-constexpr int kMaxTeam = 64;             // work-groups per team
+constexpr int kMaxTeam = 256;            // work-groups per team
+static_assert(kMaxTeam % 64 == 0, "barrier slots are polled by the 64 lanes of one wave");
 constexpr int kMaxConcurrentTeams = 64;  // large-component teams per launch
 // A device-side wait gives up (and flags RCM_ERR_ABORTED) after 30 s of the
 // 100 MHz constant-rate clock read by wall_clock64(): far beyond any
@@ -54,6 +55,8 @@ struct alignas(128) TeamCtl {
   long long msum;                // sum of degrees of the current component
   long long pass_m[2];           // level orders: sum of degrees reached by the
                                  // current unlabelled pass, [pass parity]
+  unsigned long long ldone;      // labelled passes finished by the labelling sub-team
+  int32_t llevels;               // levels of the last labelled pass
   int32_t a_ecc[2];              // asynchronous passes, [pass parity]: largest
   int32_t a_cnt[2];              // distance, vertices reached, and the minimum
   unsigned long long a_key[2];   // (deg << 32 | id) at the largest distance
@@ -297,6 +300,8 @@ struct BfsParams {
   int32_t rebalance;          // wide unlabelled levels between redistributions
   int32_t label_mode;         // 0: labelled BFS; 1, 2: level order (keys left in claim)
   int32_t async_search;       // 1: large components' searches run asynchronous passes
+  TeamSlots* sub_slots;       // barrier slots of the labelling sub-teams
+  int32_t label_team;         // work-groups of a team that run the labelled BFS
   const int32_t* seg_off;     // vertex offsets of the graphs (segments), nseg + 1
   int32_t nseg;
   unsigned long long* dkey;   // per vertex: pass tag << 32 | ~distance (asynchronous passes)

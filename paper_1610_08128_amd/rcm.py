@@ -77,7 +77,8 @@ class Options(ctypes.Structure):
         ("rebalance_levels", ctypes.c_int32),
         ("label_mode", ctypes.c_int32),
         ("async_search", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 4),
+        ("label_team", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 3),
     ]
 
 
@@ -139,7 +140,8 @@ def status_string(status: int) -> str:
 
 def make_options(*, pp_variant=0, reverse_mode=0, check_full=False, team_size=0,
                  block_threads=0, small_cutoff=0, narrow_cutoff=0, small_threads=0,
-                 max_teams=0, rebalance_levels=0, label_mode=0, async_search=0) -> Options:
+                 max_teams=0, rebalance_levels=0, label_mode=0, async_search=0,
+                 label_team=0) -> Options:
     o = Options()
     o.pp_variant = int(pp_variant)
     o.reverse_mode = int(reverse_mode)
@@ -153,6 +155,7 @@ def make_options(*, pp_variant=0, reverse_mode=0, check_full=False, team_size=0,
     o.rebalance_levels = int(rebalance_levels)
     o.label_mode = int(label_mode)
     o.async_search = int(async_search)
+    o.label_team = int(label_team)
     return o
 
 

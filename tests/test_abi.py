@@ -115,7 +115,10 @@ def test_invalid_arguments_need_no_gpu():
     bad = rcm.make_options(label_mode=3)
     status, _ = rcm.order_raw(0, 0, 0, 0, options=bad)
     assert status == rcm.ERR_INVALID_ARGUMENT
-    bad = rcm.make_options(team_size=65)
+    bad = rcm.make_options(label_team=257)
+    status, _ = rcm.order_raw(0, 0, 0, 0, options=bad)
+    assert status == rcm.ERR_INVALID_ARGUMENT
+    bad = rcm.make_options(team_size=257)
     status, _ = rcm.order_raw(0, 0, 0, 0, options=bad)
     assert status == rcm.ERR_INVALID_ARGUMENT
     # n == 0 is a no-op
