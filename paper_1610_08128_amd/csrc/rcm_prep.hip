@@ -142,16 +142,18 @@ __global__ void k_full_check(int32_t n, const int32_t* __restrict__ rowptr,
 // parent[] is read and written with device-scope atomics (it changes under
 // other work-groups' feet).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int32_t uf_find(int32_t* parent, int32_t x) {
+
+// Root of x without writing anything on the way.  The compression below must
+// not halve paths: a halving store into parent[i] from another thread could
+// land after i's own root store and leave i pointing at a non-root.  The
+// hooking uses it too: the smallest-neighbour start leaves shallow trees, and
+// halving stores there cost more (device-scope writes on every hop) than the
+// hops they save.
+__device__ __forceinline__ int32_t uf_root(const int32_t* parent, int32_t x) {
   while (true) {
     const int32_t p = ld_relaxed(parent + x);
     if (p == x) return x;
-    const int32_t gp = ld_relaxed(parent + p);
-    if (gp != p) {
-      // path halving: gp is an ancestor of x, so pointing x at it is safe
-      __hip_atomic_store(parent + x, gp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    x = gp;
+    x = p;
   }
 }
 
@@ -180,7 +182,7 @@ __global__ void k_cc_hook(int32_t n, const int32_t* __restrict__ rowptr,
   for (int32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += gridDim.x * blockDim.x) {
     if (skip && skip[u] != 0) continue;
     // root of u, found once and kept while it stays u's root
-    int32_t a = uf_find(parent, u);
+    int32_t a = uf_root(parent, u);
     for (int32_t k = rowptr[u]; k < rowptr[u + 1]; ++k) {
       const int32_t v = colidx[k];
       // a skipped (already ordered) component is closed under adjacency in a
@@ -190,9 +192,9 @@ __global__ void k_cc_hook(int32_t n, const int32_t* __restrict__ rowptr,
         continue;
       }
       if (v >= u) continue;  // each undirected edge once
-      int32_t b = uf_find(parent, v);
+      int32_t b = uf_root(parent, v);
       if (a == b) continue;
-      a = uf_find(parent, a);  // a may have been hooked meanwhile
+      a = uf_root(parent, a);  // a may have been hooked meanwhile
       while (a != b) {
         if (a < b) { const int32_t t = a; a = b; b = t; }
         // hook the larger root a under the smaller root b
@@ -200,21 +202,10 @@ __global__ void k_cc_hook(int32_t n, const int32_t* __restrict__ rowptr,
         if (__hip_atomic_compare_exchange_strong(parent + a, &expected, b, __ATOMIC_RELAXED,
                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
           break;
-        a = uf_find(parent, expected);
-        b = uf_find(parent, b);
+        a = uf_root(parent, expected);
+        b = uf_root(parent, b);
       }
     }
-  }
-}
-
-// Root of x without writing anything on the way.  The compression below must
-// not halve paths: a halving store into parent[i] from another thread could
-// land after i's own root store and leave i pointing at a non-root.
-__device__ __forceinline__ int32_t uf_root(const int32_t* parent, int32_t x) {
-  while (true) {
-    const int32_t p = ld_relaxed(parent + x);
-    if (p == x) return x;
-    x = p;
   }
 }
 
