@@ -92,6 +92,17 @@ union SharedBuf {
   NarrowLds nw;
 };
 
+// Labelled levels keep, behind a work-group's child list in srec, the rows
+// (one register batch) its first kRowCap children loaded for their claims;
+// at the next level those children are the work-group's parents and count
+// their own children from there instead of reloading the rows.
+constexpr int kRowCap = 1024;
+static_assert(sizeof(SharedBuf) >= sizeof(int32_t) * (4 * kStageCap + kRB * kRowCap),
+              "no room for the kept rows");
+__device__ __forceinline__ int32_t* kept_row(SharedBuf& u, int32_t i) {
+  return reinterpret_cast<int32_t*>(&u) + 4 * kStageCap + kRB * i;
+}
+
 struct Shared {
   SharedBuf u;
   int scan[17];
@@ -1560,7 +1571,14 @@ __device__ __forceinline__ void global_label_level(const BfsParams& P, Team& t, 
     int c;
     if (one_round && e.z - e.y <= kRB) {
       if (e.z > e.y) {
-        load_batch(P.colidx, e.y, e.z, u, cnb);
+        if (use_own && p - lo < kRowCap) {
+          // the row this parent loaded for its claims at the previous level
+          const int32_t* kr = kept_row(S.u, p - lo);
+#pragma unroll
+          for (int j = 0; j < kRB; ++j) cnb[j] = kr[j];
+        } else {
+          load_batch(P.colidx, e.y, e.z, u, cnb);
+        }
         uint32_t cl[kRB];
 #pragma unroll
         for (int j = 0; j < kRB; ++j) cl[j] = P.claim[cnb[j]];
@@ -1642,7 +1660,23 @@ __device__ __forceinline__ void global_label_level(const BfsParams& P, Team& t, 
   const long long t3 = wall_clock64();
   for (int32_t i = threadIdx.x; i < list_len; i += B) {
     const int4 c = reinterpret_cast<const int4*>(S.u.srec)[i];
-    claim_row(P, c.x, make_int4(c.y, c.z, 0, 0), static_cast<uint32_t>(c.w));
+    if (i < kRowCap && c.z - c.y <= kRB) {
+      // one batch: claim, and keep the row for the child's own count
+      int32_t nb[kRB];
+      if (c.z > c.y) {
+        load_batch(P.colidx, c.y, c.z, c.x, nb);
+#pragma unroll
+        for (int j = 0; j < kRB; ++j) atomicMin(&P.claim[nb[j]], static_cast<uint32_t>(c.w));
+      } else {
+#pragma unroll
+        for (int j = 0; j < kRB; ++j) nb[j] = c.x;
+      }
+      int32_t* kr = kept_row(S.u, i);
+#pragma unroll
+      for (int j = 0; j < kRB; ++j) kr[j] = nb[j];
+    } else {
+      claim_row(P, c.x, make_int4(c.y, c.z, 0, 0), static_cast<uint32_t>(c.w));
+    }
   }
   if (threadIdx.x == 0) {
     // the lists serve as the next level's parents when every work-group's
