@@ -117,10 +117,10 @@ typedef struct {
                             teams; 0 = auto (512); 256 or 512                  */
   int32_t max_teams;     /* most large-component teams run at once; 0 = auto
                             (16; 32 in batched calls), at most 64              */
-  int32_t rebalance_levels; /* wide unlabelled levels keep each work-group's
-                            share of the frontier in LDS and redistribute it
-                            evenly every this many levels; 0 = auto (8),
-                            1 = every level                                    */
+  int32_t rebalance_levels; /* wide levels of the level-synchronous passes keep
+                            each work-group's share of the frontier in LDS
+                            and redistribute it evenly every this many
+                            levels; 0 = auto (8), 1 = every level             */
   int32_t label_mode;    /* how each level's vertices are ordered (the
                             alternatives to per-level sorting that Section VI
                             names as future work):
@@ -141,7 +141,7 @@ typedef struct {
                             asynchronous, -1 = level-synchronous.
                             Asynchronous is a label-correcting BFS whose
                             work-groups expand their own frontiers for
-                            rebalance_levels steps between team barriers
+                            search_round steps between team barriers
                             instead of meeting once per level (the
                             non-level-synchronous BFS that Section VI leaves
                             as future work).  Same result; a pass whose
@@ -150,7 +150,10 @@ typedef struct {
   int32_t label_team;    /* work-groups of a team that run the labelled BFS
                             (the others sleep meanwhile); 0 = auto (64), at
                             most team_size is used                         */
-  int32_t reserved[3];
+  int32_t search_round;  /* steps each work-group takes on its own between the
+                            team barriers of an asynchronous search pass;
+                            0 = auto (16)                                  */
+  int32_t reserved[2];
 } rcm_options;
 
 /* Human-readable name of a status code (static string). */

@@ -43,6 +43,7 @@ struct Opts {
   int label_mode = 0;
   int async_search = 1;
   int label_team = 64;
+  int search_round = 16;
 };
 
 // Auto team size of a single graph: all compute units for a large graph
@@ -79,6 +80,7 @@ bool parse_options(const rcm_options* o, Opts* out, bool batched = false) {
     if (o->label_mode < 0 || o->label_mode > 2) return false;
     if (o->async_search < -1 || o->async_search > 1) return false;
     if (o->label_team < 0 || o->label_team > kMaxTeam) return false;
+    if (o->search_round < 0) return false;
     r.pp_variant = o->pp_variant;
     r.reverse_mode = o->reverse_mode;
     r.check_full = o->check_full;
@@ -92,6 +94,7 @@ bool parse_options(const rcm_options* o, Opts* out, bool batched = false) {
     r.label_mode = o->label_mode;
     if (o->async_search) r.async_search = o->async_search > 0 ? 1 : 0;
     if (o->label_team) r.label_team = o->label_team;
+    if (o->search_round) r.search_round = o->search_round;
   }
   *out = r;
   return true;
@@ -337,6 +340,7 @@ rcm_status run(const Graph& gin, const int32_t* seg_off_host, const Opts& opt, c
   P.slots = slots;
   P.sub_slots = reinterpret_cast<TeamSlots*>(ws + L.sub_slots);
   P.label_team = opt.label_team;
+  P.search_round = opt.search_round;
   P.small_teams = small_ctl;
   P.queues = misc + 16;
   const int team_auto = team_for(opt, g.n);

@@ -995,7 +995,7 @@ __device__ __forceinline__ int32_t ring_pos(int32_t o, int32_t ring, int32_t v) 
 
 // One level structure of the component whose label block is [o, end), from
 // `root`, for a team of several work-groups.  Rounds: every work-group
-// expands its share of the frontier and then, for up to `rebalance` steps,
+// expands its share of the frontier and then, for up to `search_round` steps,
 // the vertices it reached itself (records carry their tentative distance;
 // an improved vertex is expanded again by whoever improved it, a superseded
 // record is skipped), with no team barrier between the steps.  One barrier
@@ -1044,7 +1044,7 @@ __device__ __forceinline__ bool async_bfs_pass(const BfsParams& P, Team& t, Shar
       S.spill = 0;
       S.ovf = 0;
     }
-    for (int step = 0; step < P.rebalance; ++step) {
+    for (int step = 0; step < P.search_round; ++step) {
       if (threadIdx.x == 0) S.cnt = 0;
       __syncthreads();
       for (int32_t i = threadIdx.x; i < n_glob + own_n; i += B) {

@@ -302,6 +302,7 @@ struct BfsParams {
   int32_t async_search;       // 1: large components' searches run asynchronous passes
   TeamSlots* sub_slots;       // barrier slots of the labelling sub-teams
   int32_t label_team;         // work-groups of a team that run the labelled BFS
+  int32_t search_round;       // steps per round of the asynchronous passes
   const int32_t* seg_off;     // vertex offsets of the graphs (segments), nseg + 1
   int32_t nseg;
   unsigned long long* dkey;   // per vertex: pass tag << 32 | ~distance (asynchronous passes)

@@ -78,7 +78,8 @@ class Options(ctypes.Structure):
         ("label_mode", ctypes.c_int32),
         ("async_search", ctypes.c_int32),
         ("label_team", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 3),
+        ("search_round", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 2),
     ]
 
 
@@ -141,7 +142,7 @@ def status_string(status: int) -> str:
 def make_options(*, pp_variant=0, reverse_mode=0, check_full=False, team_size=0,
                  block_threads=0, small_cutoff=0, narrow_cutoff=0, small_threads=0,
                  max_teams=0, rebalance_levels=0, label_mode=0, async_search=0,
-                 label_team=0) -> Options:
+                 label_team=0, search_round=0) -> Options:
     o = Options()
     o.pp_variant = int(pp_variant)
     o.reverse_mode = int(reverse_mode)
@@ -156,6 +157,7 @@ def make_options(*, pp_variant=0, reverse_mode=0, check_full=False, team_size=0,
     o.label_mode = int(label_mode)
     o.async_search = int(async_search)
     o.label_team = int(label_team)
+    o.search_round = int(search_round)
     return o
 
 

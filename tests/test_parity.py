@@ -308,17 +308,18 @@ def test_async_search_random(seed):
     g = _random_graph(700 + seed)
     check(g, async_search=1, small_cutoff=1, team_size=2 + seed % 7, pp_variant=seed % 2,
           reverse_mode=(seed // 2) % 2)
-    check(g, async_search=1, small_cutoff=1, team_size=8, rebalance_levels=1 + seed % 4,
-          narrow_cutoff=16, label_mode=seed % 3)
+    check(g, async_search=1, small_cutoff=1, team_size=8, search_round=1 + seed % 4,
+          rebalance_levels=1 + seed % 3, narrow_cutoff=16, label_mode=seed % 3)
 
 
 def test_async_search_grids():
     check(I.config(0, seed=4), async_search=1, small_cutoff=1)
-    check(I.config(0, seed=4), async_search=1, small_cutoff=1, team_size=3, rebalance_levels=2)
+    check(I.config(0, seed=4), async_search=1, small_cutoff=1, team_size=3, search_round=2)
     # the 128^3 grid at full size, in the benchmark's launch configuration
     check(I.config(1), async_search=1)
     check(I.config(1), async_search=1, label_mode=2)
-    check(I.config(1), async_search=1, pp_variant=1, reverse_mode=1, rebalance_levels=3)
+    check(I.config(1), async_search=1, pp_variant=1, reverse_mode=1, search_round=3,
+          team_size=200, label_team=40)
 
 
 def test_async_search_batched():
