@@ -18,6 +18,13 @@
  *     Table I) and labelled consecutively;
  *   - the labels are reversed (last line of Algorithm 1).
  *
+ * The search's BFSs of a large component run by default as a
+ * label-correcting BFS without a barrier per level (the non-level-
+ * synchronous BFS that Section VI leaves as future work; option
+ * async_search): its distances, and so the search's result, equal those of
+ * the level-synchronous BFS.  Option label_mode selects the other future
+ * work of Section VI, labelling each level without the per-level sort.
+ *
  * Every tie is broken deterministically, so the permutation is unique:
  * degree = number of off-diagonal entries in the row; "minimum degree"
  * ties go to the lower vertex id; the start vertex of a component is its

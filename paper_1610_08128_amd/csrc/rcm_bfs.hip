@@ -4,18 +4,24 @@
 // the labelled level-synchronous BFS of Algorithm 3, then the reversal.
 //
 // One persistent kernel does all of it.  A "team" of W work-groups owns one
-// component at a time and walks its levels; between levels the team meets at
-// a barrier (a monotone arrival counter with device-scope release/acquire
-// fences; for W = 1 the barrier is just __syncthreads).  In one launch:
+// component at a time.  Its work-groups meet at team barriers: every
+// work-group stores (barrier number, payload) into a slot of its own and
+// polls the others' slots, so a barrier also exchanges one count per
+// work-group (for W = 1 it is just __syncthreads).  In one launch:
 //   - large components: teams of W co-resident work-groups (cooperative
-//     launch; default W = 64, eight work-groups on each of the 8 XCDs) take
-//     them from a queue, largest first;
+//     launch; by default one work-group per CU for a large graph) take them
+//     from a queue, largest first;
 //   - small components: single-work-group teams take them from a second
 //     queue, largest first; team work-groups join them once the large
 //     queue is empty.
-// Narrow levels (fewer vertices than the narrow cutoff) are expanded by the
-// team's first work-group alone, level after level with only __syncthreads,
-// while the others sleep until the frontier widens again or the pass ends.
+// The search's level structures of a large component are asynchronous: a
+// label-correcting BFS with one team barrier per round of steps instead of
+// one per level (async_bfs_pass).  The labelled BFS is level-synchronous and
+// runs on the team's first label_team work-groups.  Narrow levels (fewer
+// vertices than the narrow cutoff) of the level-synchronous passes are
+// expanded by the team's first work-group alone, level after level with only
+// __syncthreads, while the others sleep until the frontier widens again or
+// the pass ends.
 //
 // Frontier entries are (vertex, row begin, row end): the row bounds of a
 // vertex are fetched when it is discovered, in the shadow of the append, so
@@ -116,11 +122,11 @@ struct Shared {
   int32_t total;                   // own-frontier level: next level size
   int32_t nspill;                  // own-frontier level: records in qi
 
-  int32_t wsum[kMaxTeam];
-  int32_t wpre;                    // team_counts: this work-group's prefix
-  int32_t wtot;                    // team_counts: the team's total
-  int32_t wmax;                    // team_counts: the largest count
-  int32_t wspill;                  // team_counts: work-groups that flagged a spill
+  int32_t wsum[kMaxTeam];          // slot_exchange: every work-group's count
+  int32_t wpre;                    // slot_exchange: this work-group's prefix
+  int32_t wtot;                    // slot_exchange: the team's total
+  int32_t wmax;                    // slot_exchange: the largest count
+  int32_t wspill;                  // slot_exchange: work-groups that flagged a spill
   int32_t ovf;                     // asynchronous passes: a record found no ring slot
   int32_t lown_base;               // wide labelled level: the label range of the
   int32_t lown_len;                // children this work-group placed (its list
