@@ -137,18 +137,20 @@ __global__ void k_full_check(int32_t n, const int32_t* __restrict__ rowptr,
 }
 
 // ---------------------------------------------------------------------------
-// Connected components: union-find where a root is only ever hooked under a
-// smaller root, so the final root of each tree is the component's lowest id.
-// parent[] is read and written with device-scope atomics (it changes under
-// other work-groups' feet).
+// Connected components: a forest in which every parent is a smaller id of
+// the same component, so the final root of each tree is the component's
+// lowest id.  Every vertex starts at its smallest neighbour; a few
+// contraction rounds (each vertex hooks its root under the smallest root next
+// to it, then the forest is flattened) merge most of each component; one
+// large set per graph is marked; exact union-find hooking of the other
+// vertices' edges finishes the job.  parent[] changes under other
+// work-groups' feet, so it is only read with atomic loads.
 // ---------------------------------------------------------------------------
 
-// Root of x without writing anything on the way.  The compression below must
-// not halve paths: a halving store into parent[i] from another thread could
-// land after i's own root store and leave i pointing at a non-root.  The
-// hooking uses it too: the smallest-neighbour start leaves shallow trees, and
-// halving stores there cost more (device-scope writes on every hop) than the
-// hops they save.
+// Root of x without writing anything on the way, through agent-scope loads
+// (current values).  The compression below must not halve paths: a halving
+// store into parent[i] from another thread could land after i's own root
+// store and leave i pointing at a non-root.
 __device__ __forceinline__ int32_t uf_root(const int32_t* parent, int32_t x) {
   while (true) {
     const int32_t p = ld_relaxed(parent + x);
@@ -157,44 +159,119 @@ __device__ __forceinline__ int32_t uf_root(const int32_t* parent, int32_t x) {
   }
 }
 
-// Union-find start: every vertex points at the smallest of itself and its
-// neighbours (skipped vertices and edges into them excluded).  That is
-// already a forest inside the components -- every link goes to a smaller id
-// in the same component -- and most vertices start next to their root.
-__global__ void k_cc_init(int32_t n, const int32_t* __restrict__ rowptr,
-                          const int32_t* __restrict__ colidx, const int32_t* __restrict__ skip,
-                          int32_t* __restrict__ parent) {
-  for (int32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += gridDim.x * blockDim.x) {
-    int32_t m = u;
-    if (!(skip && skip[u] != 0)) {
-      for (int32_t k = rowptr[u]; k < rowptr[u + 1]; ++k) {
-        const int32_t v = colidx[k];
-        if (v < m && !(skip && skip[v] != 0)) m = v;
-      }
-    }
-    parent[u] = m;
+// The root as seen through workgroup-scope loads, which the cache may serve
+// with an older value than another work-group's store.  The rounds and the
+// hooking below tolerate that: every value parent[x] ever holds is x or a
+// smaller id in x's set, and a link, once made, is never replaced (hooks
+// only swap a root's own entry; flattening only moves an entry up to the
+// root).  So an old value is still an ancestor in the same set and a walk
+// over old values still descends to smaller ids and ends; a find may stop at
+// a vertex that is no longer a root, and the compare-and-swap on that vertex
+// then fails and returns its current parent.  Agent-scope loads, which must
+// not come from the cache, made every hop of a find a trip to memory.
+__device__ __forceinline__ int32_t ld_cached(const int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ int32_t uf_root_cached(const int32_t* parent, int32_t x) {
+  while (true) {
+    const int32_t p = ld_cached(parent + x);
+    if (p == x) return x;
+    x = p;
   }
 }
 
-__global__ void k_cc_hook(int32_t n, const int32_t* __restrict__ rowptr,
+// Union-find start: every vertex points at the smallest of itself and its
+// neighbours (skipped vertices and edges into them excluded).  That is
+// already a forest inside the components -- every link goes to a smaller id
+// in the same component -- and most vertices start next to their root.  The
+// same pass reads every row once, so it also clears the pick marks and
+// reports edges into the skipped set: a skipped (already ordered) component
+// is closed under adjacency in a symmetric pattern, so such an edge (u, v)
+// lacks its (v, u).
+__global__ void k_cc_init(int32_t n, const int32_t* __restrict__ rowptr,
                           const int32_t* __restrict__ colidx, const int32_t* __restrict__ skip,
-                          int32_t* parent, int32_t* __restrict__ err) {
+                          int32_t* __restrict__ parent, int32_t* __restrict__ pick,
+                          int32_t* __restrict__ done, int32_t* __restrict__ err) {
   for (int32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += gridDim.x * blockDim.x) {
-    if (skip && skip[u] != 0) continue;
-    // root of u, found once and kept while it stays u's root
-    int32_t a = uf_root(parent, u);
+    int32_t m = u;
+    if (!(skip && skip[u] != 0)) {
+      bool bad = false;
+      for (int32_t k = rowptr[u]; k < rowptr[u + 1]; ++k) {
+        const int32_t v = colidx[k];
+        if (skip && skip[v] != 0) {
+          bad = true;
+          continue;
+        }
+        if (v < m) m = v;
+      }
+      if (bad) atomicOr(err, 1);
+    }
+    parent[u] = m;
+    pick[u] = 0;
+    done[u] = 0;
+  }
+}
+
+// One contraction round on a flat forest (every parent a root): each vertex
+// takes the smallest parent among itself and its neighbours and hooks its
+// root under it, with one compare-and-swap from the root itself and no
+// retry, so a root is hooked at most once per round and no link is ever
+// replaced: sets only grow, and any parent value ever read stays an ancestor
+// of the same set.  There are no finds, so a round costs one pass over the
+// rows; hooks lost to a failed swap only wait for the next round or the exact
+// hooking.  A vertex whose neighbours all showed its own parent has edges
+// inside one set only, for good: done[u] = 1 takes it out of the later
+// rounds and of the exact hooking.
+__global__ void k_cc_round(int32_t n, const int32_t* __restrict__ rowptr,
+                           const int32_t* __restrict__ colidx, const int32_t* __restrict__ skip,
+                           int32_t* __restrict__ done, int32_t* parent) {
+  for (int32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += gridDim.x * blockDim.x) {
+    if (done[u] != 0 || (skip && skip[u] != 0)) continue;
+    const int32_t pu = ld_cached(parent + u);
+    int32_t m = pu;
+    bool inside = true;
     for (int32_t k = rowptr[u]; k < rowptr[u + 1]; ++k) {
       const int32_t v = colidx[k];
-      // a skipped (already ordered) component is closed under adjacency in a
-      // symmetric pattern, so an edge into it means (u, v) lacks (v, u)
-      if (skip && skip[v] != 0) {
-        atomicOr(err, 1);
-        continue;
-      }
-      if (v >= u) continue;  // each undirected edge once
-      int32_t b = uf_root(parent, v);
+      if (skip && skip[v] != 0) continue;
+      const int32_t pv = ld_cached(parent + v);
+      inside = inside && pv == pu;
+      m = pv < m ? pv : m;
+    }
+    if (inside) done[u] = 1;
+    // all the vertices of a tree aim at one root: read it first, so that only
+    // the ones that may still hook it queue an atomic there
+    if (m < pu && ld_cached(parent + pu) == pu) {
+      int32_t expected = pu;
+      __hip_atomic_compare_exchange_strong(parent + pu, &expected, m, __ATOMIC_RELAXED,
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
+// The exact hooking: every edge of every vertex, except the vertices whose
+// edges the rounds found inside one set (done) and those whose parent is
+// marked in pick (see k_cc_pick for why that loses no connection).
+// A root is only ever hooked under a smaller root, so whatever the rounds
+// before it left undone, the final root of each tree is its component's
+// lowest id.
+__global__ void k_cc_link(int32_t n, const int32_t* __restrict__ rowptr,
+                          const int32_t* __restrict__ colidx, const int32_t* __restrict__ skip,
+                          const int32_t* __restrict__ done, const int32_t* __restrict__ pick,
+                          int32_t* parent) {
+  for (int32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += gridDim.x * blockDim.x) {
+    if (done[u] != 0 || (skip && skip[u] != 0)) continue;
+    if (pick && pick[ld_cached(parent + u)] != 0) continue;
+    const int32_t rb = rowptr[u], re = rowptr[u + 1];
+    if (rb == re) continue;
+    // root of u, found once and kept while it stays u's root
+    int32_t a = uf_root_cached(parent, u);
+    for (int32_t k = rb; k < re; ++k) {
+      const int32_t v = colidx[k];
+      if (skip && skip[v] != 0) continue;  // reported by k_cc_init
+      int32_t b = uf_root_cached(parent, v);
       if (a == b) continue;
-      a = uf_root(parent, a);  // a may have been hooked meanwhile
+      a = uf_root_cached(parent, a);  // a may have been hooked meanwhile
       while (a != b) {
         if (a < b) { const int32_t t = a; a = b; b = t; }
         // hook the larger root a under the smaller root b
@@ -202,23 +279,65 @@ __global__ void k_cc_hook(int32_t n, const int32_t* __restrict__ rowptr,
         if (__hip_atomic_compare_exchange_strong(parent + a, &expected, b, __ATOMIC_RELAXED,
                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
           break;
-        a = uf_root(parent, expected);
-        b = uf_root(parent, b);
+        a = uf_root_cached(parent, expected);
+        b = uf_root_cached(parent, b);
       }
     }
   }
 }
 
-// After hooking: every parent[i] becomes its root (the only store into
-// parent[i] is this one, by the thread that owns i; concurrent readers see
-// either the old parent or the root, both ancestors of i).
+// Every parent[i] becomes its root (the only store into parent[i] is this
+// one, by the thread that owns i; concurrent readers see either the old
+// parent or the root, both ancestors of i).  With flags, the final pass also
+// marks the roots of the components to order.
 __global__ void k_cc_compress(int32_t n, int32_t* parent, const int32_t* __restrict__ skip,
                               int32_t* __restrict__ flags) {
   for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     const int32_t r = uf_root(parent, i);
     __hip_atomic_store(parent + i, r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    flags[i] = (r == i) && !(skip && skip[i] != 0);
+    if (flags) flags[i] = (r == i) && !(skip && skip[i] != 0);
   }
+}
+
+// After the contraction rounds and a flattening, one work-group per graph
+// segment takes kPickSamples evenly spaced vertices and marks the most
+// frequent of their roots: in a graph with a giant component that root's set
+// already holds most of the vertices.  The exact hooking then passes over
+// every vertex whose parent is a marked root, without losing a connection:
+// that set is connected already; an edge with an endpoint outside it is
+// hooked from that endpoint; and an edge both of whose endpoints are passed
+// over joins two vertices that each had the marked root as an ancestor when
+// read, so both already lie in one set.  One mark per segment keeps it so:
+// segments share no edges, while two marked sets in one component could be
+// joined only by edges between them that nobody hooks.
+constexpr int kPickSamples = 64;
+constexpr int kContractRounds = 4;
+
+__global__ void __launch_bounds__(kPickSamples)
+k_cc_pick(const int32_t* __restrict__ seg_off, const int32_t* __restrict__ skip,
+          const int32_t* parent, int32_t* __restrict__ pick) {
+  __shared__ int32_t roots[kPickSamples];
+  const int32_t b = seg_off[blockIdx.x], len = seg_off[blockIdx.x + 1] - b;
+  const int j = threadIdx.x;
+  int32_t r = -1;
+  if (len > 0) {
+    const int32_t x = b + static_cast<int32_t>(static_cast<int64_t>(len) * (2 * j + 1) /
+                                               (2 * kPickSamples));
+    if (!(skip && skip[x] != 0)) r = uf_root(parent, x);
+  }
+  roots[j] = r;
+  __syncthreads();
+  int32_t c = 0;
+  if (r >= 0)
+    for (int i = 0; i < kPickSamples; ++i) c += roots[i] == r;
+  // most samples first, then the smaller root
+  uint64_t key = r >= 0 ? (static_cast<uint64_t>(c) << 32) | static_cast<uint32_t>(0x7FFFFFFF - r)
+                        : 0;
+  for (int off = kPickSamples / 2; off > 0; off >>= 1) {
+    const uint64_t o = __shfl_xor(key, off, kPickSamples);
+    key = o > key ? o : key;
+  }
+  if (j == 0 && key != 0) pick[0x7FFFFFFF - static_cast<int32_t>(key & 0xFFFFFFFFu)] = 1;
 }
 
 // Component sizes: histogram of roots with a small LDS hash per block, so a
@@ -541,8 +660,17 @@ hipError_t launch_components(const Graph& g, const int32_t* skip, int32_t* paren
                              int32_t* flags, int32_t* scan_tmp, int32_t* seeds,
                              int32_t* num_comps, int32_t* err_asym, hipStream_t s) {
   const int nb = grid_for(g.n, kThreads);
-  k_cc_init<<<nb, kThreads, 0, s>>>(g.n, g.rowptr, g.colidx, skip, parent);
-  k_cc_hook<<<nb, kThreads, 0, s>>>(g.n, g.rowptr, g.colidx, skip, parent, err_asym);
+  // flags holds the pick marks until the last compression overwrites it;
+  // csize the done marks until it is cleared for the sizes
+  k_cc_init<<<nb, kThreads, 0, s>>>(g.n, g.rowptr, g.colidx, skip, parent, flags, csize,
+                                    err_asym);
+  for (int r = 0; r < kContractRounds; ++r) {
+    k_cc_compress<<<nb, kThreads, 0, s>>>(g.n, parent, skip, nullptr);
+    k_cc_round<<<nb, kThreads, 0, s>>>(g.n, g.rowptr, g.colidx, skip, csize, parent);
+  }
+  k_cc_compress<<<nb, kThreads, 0, s>>>(g.n, parent, skip, nullptr);
+  if (g.nseg > 0) k_cc_pick<<<g.nseg, kPickSamples, 0, s>>>(g.seg_off, skip, parent, flags);
+  k_cc_link<<<nb, kThreads, 0, s>>>(g.n, g.rowptr, g.colidx, skip, csize, flags, parent);
   k_cc_compress<<<nb, kThreads, 0, s>>>(g.n, parent, skip, flags);
   hipError_t e = hipMemsetAsync(csize, 0, sizeof(int32_t) * static_cast<size_t>(g.n), s);
   if (e != hipSuccess) return e;

@@ -260,6 +260,30 @@ def test_batched_512():
     _check_batch(graphs)
 
 
+def test_batched_components_repeated():
+    """The component search of a batch hooks roots from many work-groups at
+    once; mid-size relabelled grids and random geometric patches give it many
+    roots to merge.  Several calls on one workspace must all agree with the
+    oracle (a union lost to a race splits a component, which the ordering
+    reports as an unsymmetric pattern)."""
+    import torch
+    from paper_1610_08128_amd import rcm
+
+    graphs = I.batch_graphs(64, seed=12, lo=2e4, hi=2e5)
+    vo, no, rp, ci = I.concat_batch(graphs)
+    want = [oracle.rcm(g.n, g.rowptr, g.colidx) for g in graphs]
+    rpd, cid = torch.from_numpy(rp).cuda(), torch.from_numpy(ci).cuda()
+    ws = torch.empty(rcm.batched_workspace_bytes(len(graphs), int(vo[-1]), int(no[-1])),
+                     dtype=torch.uint8, device="cuda")
+    for call in range(4):
+        _say(f"batch of {len(graphs)} graphs, {vo[-1]} vertices, call {call}")
+        perm, stats = rcm.order_batched(vo, no, rpd, cid, workspace=ws)
+        perm = perm.cpu().numpy()
+        for i, w in enumerate(want):
+            assert np.array_equal(perm[vo[i]:vo[i + 1]], w.perm), (call, i)
+            assert stats[i] == w.stats, (call, i)
+
+
 # ---------------------------------------------------------------------------
 # Level orders (label_mode 1: no sort, 2: one global sort at the end)
 # ---------------------------------------------------------------------------
