@@ -196,6 +196,15 @@ def test_status_codes_on_gpu():
         rcm.order(torch.from_numpy(rp).cuda(), torch.from_numpy(ci).cuda(), check_full=True)
     assert e.value.status == rcm.ERR_NOT_SYMMETRIC
     assert oracle.validate(5, rp, ci, True) == oracle.ERR_NOT_SYMMETRIC
+    # vertex 1 points into vertex 0's component {0, 2} without the way back:
+    # the ordering of that component never reaches 1, and the component
+    # search of the rest reports the edge, without the full check
+    rp = np.array([0, 1, 3, 4, 5], np.int32)
+    ci = np.array([2, 0, 3, 0, 1], np.int32)
+    assert oracle.validate(4, rp, ci, True) == oracle.ERR_NOT_SYMMETRIC
+    with pytest.raises(rcm.RcmError) as e:
+        rcm.order(torch.from_numpy(rp).cuda(), torch.from_numpy(ci).cuda())
+    assert e.value.status == rcm.ERR_NOT_SYMMETRIC
 
 
 def test_caller_workspace_and_stream():
