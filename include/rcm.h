@@ -108,8 +108,10 @@ typedef struct {
   int32_t team_size;     /* work-groups cooperating on one large component;
                             0 = auto (256, one per compute unit, for graphs
                             of at least 2^18 vertices, else 64; 8 in batched
-                            calls); 1..256, capped at the number of
-                            work-groups resident at once                      */
+                            calls, 4 for a batch with more large components
+                            than 8-wide teams start at once and no graph of
+                            2^18 vertices or more); 1..256, capped at the
+                            number of work-groups resident at once           */
   int32_t block_threads; /* threads per work-group of the large-component
                             team; 0 = auto (256); 256 or 512                   */
   int32_t small_cutoff;  /* components with at most this many vertices are
@@ -123,7 +125,13 @@ typedef struct {
   int32_t small_threads; /* threads per work-group of the single-work-group
                             teams; 0 = auto (512); 256 or 512                  */
   int32_t max_teams;     /* most large-component teams run at once; 0 = auto
-                            (16; 32 in batched calls), at most 64              */
+                            (16; 32 in batched calls), at most 64.  With small
+                            components too, half of the resident work-groups
+                            are left to them, except in a batch that takes
+                            teams of 4 by the auto rule above: there the
+                            teams fill every resident work-group and take
+                            the small components once the large ones are
+                            gone                                              */
   int32_t rebalance_levels; /* wide levels of the level-synchronous passes keep
                             each work-group's share of the frontier in LDS
                             and redistribute it evenly every this many

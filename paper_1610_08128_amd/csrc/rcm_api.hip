@@ -39,6 +39,9 @@ struct Opts {
   int small_cutoff = 1 << 18;
   int narrow_cutoff = 256;
   int max_teams = 16;
+  // batched call with team_size and max_teams left to auto: a batch of many
+  // large components, none of them very large, gets many small teams
+  bool batch_auto = false;
   int rebalance = 8;
   int label_mode = 0;
   int async_search = 1;
@@ -56,13 +59,15 @@ inline int team_for(const Opts& o, int64_t n) {
 
 // Auto values differ for batched calls: many components of many graphs share
 // one launch, so more, smaller teams take the larger ones (measured on the
-// 512-graph batch and on the request pool of the serving benchmark).
+// 512-graph batch and on the request pool of the serving benchmark); see
+// also batch_auto.
 bool parse_options(const rcm_options* o, Opts* out, bool batched = false) {
   Opts r;
   if (batched) {
     r.small_cutoff = 1 << 16;
     r.team_size = 8;
     r.max_teams = 32;
+    r.batch_auto = !o || (o->team_size == 0 && o->max_teams == 0);
   }
   if (o) {
     if (o->pp_variant != 0 && o->pp_variant != 1) return false;
@@ -159,6 +164,7 @@ Layout make_layout(int64_t n, int64_t nnz, int64_t nseg, bool batched, int teams
 }
 
 constexpr int kSmallTeams = 1024;
+constexpr int kWideBatchTeam = 4;  // team size of a batch's many-teams layout
 
 // Phase timing with HIP events on the call's stream (RCM_TIMING=1).
 // Event slots: 0 start, 1 checks done, 2/3 around the component search,
@@ -351,6 +357,19 @@ rcm_status run(const Graph& gin, const int32_t* seg_off_host, const Opts& opt, c
   // empty.  With large components the launch is cooperative, so it is sized
   // to what is resident at once, half of it left to single-work-group blocks
   // when there are small components too.
+  //
+  // A batch's large components differ in time far more than in size (a 2D
+  // grid has many more levels than a 3D grid of the same size).  With more
+  // of them than teams, a largest-first queue sometimes hands a long one to
+  // a team late, and the call runs a whole task longer (two modes, 55 and
+  // 90 ms, on the 512-graph batch).  So when an auto-configured batch has
+  // more large components than that layout starts at once and no graph of
+  // 2^18 vertices or more (those want large teams), it runs teams of 4 over
+  // every resident work-group instead: all large components start at once,
+  // and the small ones follow when the team work-groups turn to them.
+  int32_t largest_graph = 0;
+  for (int i = 0; i < g.nseg; ++i)
+    largest_graph = std::max(largest_graph, seg_off_host[i + 1] - seg_off_host[i]);
   auto launch = [&](const CompTask* big, int32_t n_big, const CompTask* small, int32_t n_small,
                     int kslot, bool copy_clk) -> rcm_status {
     P.big_tasks = big;
@@ -364,10 +383,16 @@ rcm_status run(const Graph& gin, const int32_t* seg_off_host, const Opts& opt, c
       if (resident < 1) return RCM_ERR_HIP;
       // a team never exceeds what is resident at once (the launch is
       // cooperative)
-      const int team = std::min(team_auto, resident);
+      int team = std::min(team_auto, resident);
+      int room = n_small > 0 ? std::max(resident / 2, team) : resident;
+      int cap = opt.max_teams;
+      if (opt.batch_auto && largest_graph < (1 << 18) && n_big > room / team) {
+        team = std::min(kWideBatchTeam, resident);
+        room = resident;
+        cap = kMaxConcurrentTeams;
+      }
       P.team_size = team;
-      const int room = n_small > 0 ? std::max(resident / 2, team) : resident;
-      nteams = std::max(1, std::min({n_big, opt.max_teams, room / team}));
+      nteams = std::max(1, std::min({n_big, cap, room / team}));
       P.big_blocks = nteams * team;
       const int extra = n_small > 0 ? std::min(n_small, resident - P.big_blocks) : 0;
       blocks = std::min(P.big_blocks + std::max(extra, 0), kSmallTeams);
