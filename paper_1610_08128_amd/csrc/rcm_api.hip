@@ -525,28 +525,47 @@ rcm_status run(const Graph& gin, const int32_t* seg_off_host, const Opts& opt, c
   return RCM_OK;
 }
 
-__global__ void k_globalize(int32_t G, const int32_t* __restrict__ vo, const int32_t* __restrict__ no,
-                            const int32_t* __restrict__ rowptr_cat,
-                            const int32_t* __restrict__ colidx_cat, int32_t N, int32_t NNZ,
-                            int32_t* __restrict__ rowptr_g, int32_t* __restrict__ colidx_g,
-                            int32_t* __restrict__ err) {
-  const int32_t stride = gridDim.x * blockDim.x;
-  const int32_t t0 = blockIdx.x * blockDim.x + threadIdx.x;
-  for (int32_t v = t0; v < N; v += stride) {
-    const int g = find_segment(vo, G, v);
-    const int32_t local = v - vo[g];
-    rowptr_g[v] = no[g] + rowptr_cat[vo[g] + g + local];
+// Turns the graphs' local CSR into the union's.  Each block takes tiles of
+// kGlobTile consecutive vertices or entries; a tile finds the graph of its
+// first element by binary search once, and its threads step forward over the
+// (rare) graph boundaries inside it, so the loads and stores stay coalesced.
+constexpr int kGlobThreads = 256;
+constexpr int kGlobPer = 8;
+constexpr int32_t kGlobTile = kGlobThreads * kGlobPer;
+
+__global__ void __launch_bounds__(kGlobThreads)
+k_globalize(int32_t G, const int32_t* __restrict__ vo, const int32_t* __restrict__ no,
+            const int32_t* __restrict__ rowptr_cat, const int32_t* __restrict__ colidx_cat,
+            int32_t N, int32_t NNZ, int32_t* __restrict__ rowptr_g,
+            int32_t* __restrict__ colidx_g, int32_t* __restrict__ err) {
+  const int64_t v_tiles = (static_cast<int64_t>(N) + kGlobTile - 1) / kGlobTile;
+  const int64_t k_tiles = (static_cast<int64_t>(NNZ) + kGlobTile - 1) / kGlobTile;
+  for (int64_t t = blockIdx.x; t < v_tiles + k_tiles; t += gridDim.x) {
+    const bool rows = t < v_tiles;
+    const int64_t base = (rows ? t : t - v_tiles) * kGlobTile;
+    const int32_t end = rows ? N : NNZ;
+    const int32_t* off = rows ? vo : no;
+    int g = find_segment(off, G, static_cast<int32_t>(base));
+    for (int j = 0; j < kGlobPer; ++j) {
+      const int64_t x = base + static_cast<int64_t>(j) * kGlobThreads + threadIdx.x;
+      if (x >= end) break;
+      const int32_t i = static_cast<int32_t>(x);
+      while (g + 1 < G && i >= off[g + 1]) ++g;
+      if (rows) {
+        rowptr_g[i] = no[g] + rowptr_cat[vo[g] + g + (i - vo[g])];
+      } else {
+        colidx_g[i] = colidx_cat[i] + vo[g];
+      }
+    }
   }
+  const int32_t t0 = blockIdx.x * blockDim.x + threadIdx.x;
+  const int32_t stride = gridDim.x * blockDim.x;
   if (t0 == 0) rowptr_g[N] = NNZ;
   for (int32_t g = t0; g < G; g += stride) {
     const int32_t n_g = vo[g + 1] - vo[g];
     const int32_t first = rowptr_cat[vo[g] + g];
     const int32_t last = rowptr_cat[vo[g] + g + n_g];
     if (first != 0 || last != no[g + 1] - no[g]) atomicOr(err, 1);
-  }
-  for (int32_t k = t0; k < NNZ; k += stride) {
-    const int g = find_segment(no, G, k);
-    colidx_g[k] = colidx_cat[k] + vo[g];
   }
 }
 
@@ -698,11 +717,11 @@ rcm_status rcm_order_batched(int32_t num_graphs, const int64_t* vtx_offsets,
       st = RCM_ERR_HIP;
       break;
     }
-    const int threads = 256;
-    const int64_t work = std::max<int64_t>(N, NNZ);
-    const int blocks = static_cast<int>(std::min<int64_t>((work + threads - 1) / threads, 8192));
-    k_globalize<<<blocks, threads, 0, s>>>(num_graphs, d_vo, d_no, rowptr_cat, colidx_cat, N, NNZ,
-                                           rowptr_g, colidx_g, err);
+    const int64_t tiles = (static_cast<int64_t>(N) + kGlobTile - 1) / kGlobTile +
+                          (static_cast<int64_t>(NNZ) + kGlobTile - 1) / kGlobTile;
+    const int blocks = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(tiles, 8192)));
+    k_globalize<<<blocks, kGlobThreads, 0, s>>>(num_graphs, d_vo, d_no, rowptr_cat, colidx_cat, N,
+                                                NNZ, rowptr_g, colidx_g, err);
     int32_t herr = 0;
     if (hipGetLastError() != hipSuccess || read_ints(&herr, err, 1, s) != RCM_OK) {
       st = RCM_ERR_HIP;
