@@ -586,10 +586,25 @@ __global__ void k_comp_seg_bounds(int nseg, const int32_t* __restrict__ seg_off,
 
 // labelled_bfs: 1 when a labelled BFS ran after the search (its entries
 // are counted too), 0 when the search's last level structure was used.
+// Per-graph sums over the component results.  A block takes a chunk of
+// components, which may span several graphs of a batch; each wave reduces
+// its lanes' share of one graph with shuffles and adds it with atomics, so
+// the walk over the graphs needs no block-wide barrier.
+__device__ __forceinline__ long long wave_sum_i64(long long x) {
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+  return x;
+}
+__device__ __forceinline__ long long wave_max_i64(long long x) {
+  for (int off = 32; off > 0; off >>= 1) {
+    const long long o = __shfl_xor(x, off, 64);
+    x = o > x ? o : x;
+  }
+  return x;
+}
+
 __global__ void k_comp_stats(int32_t ncomp, int32_t chunk, const CompResult* __restrict__ res,
                              const int32_t* __restrict__ comp_seg_off, int nseg,
                              int32_t labelled_bfs, SegStats* __restrict__ out) {
-  __shared__ long long red[16];
   const int32_t c0 = blockIdx.x * chunk;
   if (c0 >= ncomp) return;
   const int32_t c1 = min(ncomp, c0 + chunk);
@@ -597,20 +612,23 @@ __global__ void k_comp_stats(int32_t ncomp, int32_t chunk, const CompResult* __r
   for (; s < nseg && comp_seg_off[s] < c1; ++s) {
     const int32_t lo = max(c0, comp_seg_off[s]);
     const int32_t hi = min(c1, comp_seg_off[s + 1]);
-    long long diam = 0, nb = 0, nl = 0, edges = 0;
+    long long diam = 0, nb = 0, nl = 0, edges = 0, cnt = 0;
     for (int32_t c = lo + threadIdx.x; c < hi; c += blockDim.x) {
       const CompResult r = res[c];
       diam = (r.levels - 1) > diam ? (r.levels - 1) : diam;
       nb += r.nbfs;
       nl += r.levels;
       edges += static_cast<long long>(r.nbfs + labelled_bfs) * r.m;
+      ++cnt;
     }
-    diam = block_max_i64(diam, red);
-    nb = block_sum_i64(nb, red);
-    nl = block_sum_i64(nl, red);
-    edges = block_sum_i64(edges, red);
-    if (threadIdx.x == 0 && hi > lo) {
-      atomicAdd(&out[s].ncomp, hi - lo);
+    cnt = wave_sum_i64(cnt);
+    if (cnt == 0) continue;  // uniform across the wave
+    diam = wave_max_i64(diam);
+    nb = wave_sum_i64(nb);
+    nl = wave_sum_i64(nl);
+    edges = wave_sum_i64(edges);
+    if (threadIdx.x % 64 == 0) {
+      atomicAdd(&out[s].ncomp, static_cast<int32_t>(cnt));
       atomicMax(&out[s].diameter, static_cast<int32_t>(diam));
       atomicAdd(&out[s].nbfs, static_cast<int32_t>(nb));
       atomicAdd(&out[s].nlevels, static_cast<int32_t>(nl));
@@ -732,9 +750,10 @@ hipError_t launch_comp_stats(const Graph& g, int32_t ncomp, const int32_t* seeds
   if (ncomp <= 0) return hipSuccess;
   k_comp_seg_bounds<<<grid_for(g.nseg + 1, kThreads), kThreads, 0, s>>>(g.nseg, g.seg_off, seeds,
                                                                        ncomp, comp_seg_off);
-  constexpr int32_t chunk = 4096;
+  // one wave per chunk of 64 components: a chunk spans few graphs
+  constexpr int32_t chunk = 64;
   const int nb = (ncomp + chunk - 1) / chunk;
-  k_comp_stats<<<nb, kThreads, 0, s>>>(ncomp, chunk, results, comp_seg_off, g.nseg, labelled_bfs,
+  k_comp_stats<<<nb, chunk, 0, s>>>(ncomp, chunk, results, comp_seg_off, g.nseg, labelled_bfs,
                                        seg);
   return hipGetLastError();
 }
