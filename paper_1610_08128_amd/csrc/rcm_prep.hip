@@ -144,7 +144,7 @@ __global__ void k_full_check(int32_t n, const int32_t* __restrict__ rowptr,
 // to it, then the forest is flattened) merge most of each component; one
 // large set per graph is marked; exact union-find hooking of the other
 // vertices' edges finishes the job.  parent[] changes under other
-// work-groups' feet, so it is only read with atomic loads.
+// work-groups' feet, so while it does it is only read with atomic loads.
 // ---------------------------------------------------------------------------
 
 // Root of x without writing anything on the way, through agent-scope loads
@@ -185,8 +185,8 @@ __device__ __forceinline__ int32_t uf_root_cached(const int32_t* parent, int32_t
 // neighbours (skipped vertices and edges into them excluded).  That is
 // already a forest inside the components -- every link goes to a smaller id
 // in the same component -- and most vertices start next to their root.  The
-// same pass reads every row once, so it also clears the pick marks and
-// reports edges into the skipped set: a skipped (already ordered) component
+// same pass reads every row once, so it also clears the pick and done marks
+// and reports edges into the skipped set: a skipped (already ordered) component
 // is closed under adjacency in a symmetric pattern, so such an edge (u, v)
 // lacks its (v, u).
 __global__ void k_cc_init(int32_t n, const int32_t* __restrict__ rowptr,
