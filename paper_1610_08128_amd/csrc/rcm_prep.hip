@@ -62,19 +62,33 @@ __global__ void k_validate_scan(int32_t n, int32_t nnz, const int32_t* __restric
 // inside its row's segment.  Rows whose bounds are invalid are left to
 // k_validate_scan's error (this kernel runs before the host reads it, so it
 // must not follow them).
+// Every column of a graph's rows lies inside that graph.  Blocks take tiles
+// of kSegTile consecutive rows, find the graph of a tile's first row once and
+// step forward over the graph boundaries inside it.
+constexpr int kSegPer = 8;
+constexpr int32_t kSegTile = kThreads * kSegPer;
+
 __global__ void k_check_segments(int32_t n, int32_t nnz, const int32_t* __restrict__ rowptr,
                                  const int32_t* __restrict__ colidx,
                                  const int32_t* __restrict__ seg_off, int nseg,
                                  int32_t* __restrict__ err) {
-  for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    const int s = find_segment(seg_off, nseg, i);
-    const int32_t lo = seg_off[s], hi = seg_off[s + 1];
-    const int32_t a = rowptr[i];
-    const int32_t b = rowptr[i + 1];
-    if (a < 0 || b < a || b > nnz) continue;
-    for (int32_t k = a; k < b; ++k) {
-      const int32_t c = colidx[k];
-      if (c < lo || c >= hi) { atomicOr(err, 1); break; }
+  const int64_t tiles = (static_cast<int64_t>(n) + kSegTile - 1) / kSegTile;
+  for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+    const int64_t base = t * kSegTile;
+    int s = find_segment(seg_off, nseg, static_cast<int32_t>(base));
+    for (int j = 0; j < kSegPer; ++j) {
+      const int64_t x = base + static_cast<int64_t>(j) * kThreads + threadIdx.x;
+      if (x >= n) break;
+      const int32_t i = static_cast<int32_t>(x);
+      while (s + 1 < nseg && i >= seg_off[s + 1]) ++s;
+      const int32_t lo = seg_off[s], hi = seg_off[s + 1];
+      const int32_t a = rowptr[i];
+      const int32_t b = rowptr[i + 1];
+      if (a < 0 || b < a || b > nnz) continue;
+      for (int32_t k = a; k < b; ++k) {
+        const int32_t c = colidx[k];
+        if (c < lo || c >= hi) { atomicOr(err, 1); break; }
+      }
     }
   }
 }
@@ -660,8 +674,8 @@ hipError_t launch_validate_scan(const Graph& g, int4* vinfo, int32_t* beta, SegS
   k_validate_scan<<<grid_for(g.n, kThreads), kThreads, 0, s>>>(g.n, g.nnz, g.rowptr, g.colidx,
                                                                 vinfo, beta, err);
   if (g.nseg > 1)
-    k_check_segments<<<grid_for(g.n, kThreads), kThreads, 0, s>>>(g.n, g.nnz, g.rowptr, g.colidx,
-                                                                   g.seg_off, g.nseg, err);
+    k_check_segments<<<grid_for((static_cast<int64_t>(g.n) + kSegTile - 1) / kSegTile, 1),
+                       kThreads, 0, s>>>(g.n, g.nnz, g.rowptr, g.colidx, g.seg_off, g.nseg, err);
   constexpr int32_t chunk = 8192;
   const int nb = (g.n + chunk - 1) / chunk;
   k_seg_reduce<<<nb, kThreads, 0, s>>>(beta, g.n, chunk, g.seg_off, g.nseg, seg, 0);

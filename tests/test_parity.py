@@ -253,6 +253,27 @@ def test_batched_small():
     _check_batch(graphs, small_cutoff=1, team_size=4)
 
 
+@pytest.mark.parametrize("where", ["past_end", "before_start"])
+def test_batched_column_outside_its_graph(where):
+    """A column index outside its own graph becomes, in the union's ids, a
+    vertex of the neighbouring graph: still in range, so only the check that
+    every row stays inside its graph rejects it."""
+    import torch
+    from paper_1610_08128_amd import rcm
+
+    graphs = [I.grid2d(5, 6, seed=1), I.path(7, seed=3), I.grid2d(4, 4, seed=2)]
+    vo, no, rp, ci = I.concat_batch(graphs)
+    bad = ci.copy()
+    if where == "past_end":
+        bad[no[2] - 1] = graphs[1].n  # last entry of graph 1's last row
+    else:
+        bad[no[1]] = -1  # first entry of graph 1's first row
+    _say(f"batch with a column outside graph 1 ({where})")
+    with pytest.raises(rcm.RcmError) as e:
+        rcm.order_batched(vo, no, torch.from_numpy(rp).cuda(), torch.from_numpy(bad).cuda())
+    assert e.value.status == rcm.ERR_BAD_CSR
+
+
 def test_batched_concurrent_teams():
     # several large-component teams in one cooperative launch, tasks taken
     # largest first; single-work-group teams with 512 threads
