@@ -236,16 +236,21 @@ __global__ void k_cc_init(int32_t n, const int32_t* __restrict__ rowptr,
 // rows; hooks lost to a failed swap only wait for the next round or the exact
 // hooking.  A vertex whose neighbours all showed its own parent has edges
 // inside one set only, for good: done[u] = 1 takes it out of the later
-// rounds and of the exact hooking.
+// rounds and of the exact hooking.  The first rounds look at only the first
+// cap entries of a row (cap 0: all): their gathers are the cost, and a few
+// neighbours per vertex already merge most of a component; a vertex is only
+// marked done after a look at its whole row.
 __global__ void k_cc_round(int32_t n, const int32_t* __restrict__ rowptr,
                            const int32_t* __restrict__ colidx, const int32_t* __restrict__ skip,
-                           int32_t* __restrict__ done, int32_t* parent) {
+                           int32_t cap, int32_t* __restrict__ done, int32_t* parent) {
   for (int32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += gridDim.x * blockDim.x) {
     if (done[u] != 0 || (skip && skip[u] != 0)) continue;
     const int32_t pu = ld_cached(parent + u);
     int32_t m = pu;
-    bool inside = true;
-    for (int32_t k = rowptr[u]; k < rowptr[u + 1]; ++k) {
+    const int32_t rb = rowptr[u], len = rowptr[u + 1] - rb;
+    const int32_t look = cap > 0 && cap < len ? cap : len;
+    bool inside = look == len;
+    for (int32_t k = rb; k < rb + look; ++k) {
       const int32_t v = colidx[k];
       if (skip && skip[v] != 0) continue;
       const int32_t pv = ld_cached(parent + v);
@@ -326,6 +331,8 @@ __global__ void k_cc_compress(int32_t n, int32_t* parent, const int32_t* __restr
 // joined only by edges between them that nobody hooks.
 constexpr int kPickSamples = 64;
 constexpr int kContractRounds = 4;
+constexpr int kCappedRounds = 2;  // the first rounds look at kRoundCap entries
+constexpr int32_t kRoundCap = 4;
 
 __global__ void __launch_bounds__(kPickSamples)
 k_cc_pick(const int32_t* __restrict__ seg_off, const int32_t* __restrict__ skip,
@@ -698,7 +705,8 @@ hipError_t launch_components(const Graph& g, const int32_t* skip, int32_t* paren
                                     err_asym);
   for (int r = 0; r < kContractRounds; ++r) {
     k_cc_compress<<<nb, kThreads, 0, s>>>(g.n, parent, skip, nullptr);
-    k_cc_round<<<nb, kThreads, 0, s>>>(g.n, g.rowptr, g.colidx, skip, csize, parent);
+    k_cc_round<<<nb, kThreads, 0, s>>>(g.n, g.rowptr, g.colidx, skip,
+                                       r < kCappedRounds ? kRoundCap : 0, csize, parent);
   }
   k_cc_compress<<<nb, kThreads, 0, s>>>(g.n, parent, skip, nullptr);
   if (g.nseg > 0) k_cc_pick<<<g.nseg, kPickSamples, 0, s>>>(g.seg_off, skip, parent, flags);
