@@ -15,7 +15,11 @@ from paper_1610_08128_amd import inputs as I
 def _graphs():
     return [I.grid2d(9, 13, seed=3), I.rgg_patches(300, 5), I.path(7, seed=2),
             I.add_random_self_loops(I.random_tree(60, 4), 0.3, 4),
-            I.disjoint_union([I.complete(5), I.grid3d(3, 4, 2, seed=1)], seed=9)]
+            I.disjoint_union([I.complete(5), I.grid3d(3, 4, 2, seed=1)], seed=9),
+            # rows around and well past the register-sort limit of the
+            # permutation (16 entries), and a very long star row
+            I.disjoint_union([I.complete(16), I.complete(17), I.star(40), I.path(3)], seed=5),
+            I.erdos_renyi(120, 0.2, 6)]
 
 
 def _csr(g, vals=None):
@@ -23,7 +27,7 @@ def _csr(g, vals=None):
     return sp.csr_matrix((data, g.colidx, g.rowptr), shape=(g.n, g.n))
 
 
-@pytest.mark.parametrize("gi", range(5))
+@pytest.mark.parametrize("gi", range(7))
 def test_oracle_permute_matches_scipy_indexing(gi):
     g = _graphs()[gi]
     rng = np.random.default_rng(gi)
@@ -36,7 +40,7 @@ def test_oracle_permute_matches_scipy_indexing(gi):
     assert np.array_equal(v, want.data)
 
 
-@pytest.mark.parametrize("gi", range(5))
+@pytest.mark.parametrize("gi", range(7))
 def test_oracle_permute_gives_the_reported_bandwidth(gi):
     # the bandwidth of the permuted pattern (library routine on the dense
     # matrix with the diagonal present) is the ordering's bandwidth_after
@@ -76,7 +80,7 @@ def test_oracle_spmv_matches_scipy():
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("gi", range(5))
+@pytest.mark.parametrize("gi", range(7))
 def test_gpu_permute_and_spmv(gi):
     import torch
     from paper_1610_08128_amd import apply, rcm
