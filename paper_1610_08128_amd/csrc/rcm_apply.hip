@@ -86,57 +86,88 @@ __global__ void k_new_degrees(int32_t n, const int32_t* __restrict__ rowptr,
 // Row k of B: row perm[k] of A with its columns renamed by iperm.  A row of
 // at most kSortReg entries is sorted in registers by one thread, with a fixed
 // network of compare-and-swaps of neighbours on strictly greater keys (the
-// insertion order, so equal keys keep their input order), and written out.
-// A longer row goes to keys / vals_tmp for the segmented sort, and end[k]
-// marks it: end[k] = its end, while a short row gets an empty segment.
+// insertion order, so equal keys keep their input order).  A longer row goes
+// to keys / vals_tmp for the segmented sort, and end[k] marks it: end[k] = its
+// end, while a short row gets an empty segment.
+//
+// A block takes kMoveRows consecutive rows of B, whose entries are one
+// contiguous range of the output.  If that range fits kStage entries, the
+// sorted rows are staged in LDS and the range is written out coalesced (the
+// slots of long rows carry nothing; the segmented sort, later on the same
+// stream, writes them); otherwise each thread writes its row itself.
 constexpr int kSortReg = 16;
+constexpr int kMoveRows = 256;
+constexpr int kStage = kMoveRows * kSortReg;
 
-__global__ void k_move_rows(int32_t n, const int32_t* __restrict__ rowptr,
-                            const int32_t* __restrict__ colidx, const double* __restrict__ vals,
-                            const int32_t* __restrict__ perm, const int32_t* __restrict__ iperm,
-                            const int32_t* __restrict__ rowptr_out, int32_t* __restrict__ keys,
-                            double* __restrict__ vals_tmp, int32_t* __restrict__ colidx_out,
-                            double* __restrict__ vals_out, int32_t* __restrict__ end) {
-  for (int32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
-    const int32_t v = perm[k];
-    const int32_t a = rowptr[v], len = rowptr[v + 1] - a;
-    const int32_t o = rowptr_out[k];
-    if (len > kSortReg) {
-      for (int32_t e = 0; e < len; ++e) {
-        keys[o + e] = iperm[colidx[a + e]];
-        if (vals) vals_tmp[o + e] = vals[a + e];
+__global__ void __launch_bounds__(kMoveRows)
+k_move_rows(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colidx,
+            const double* __restrict__ vals, const int32_t* __restrict__ perm,
+            const int32_t* __restrict__ iperm, const int32_t* __restrict__ rowptr_out,
+            int32_t* __restrict__ keys, double* __restrict__ vals_tmp,
+            int32_t* __restrict__ colidx_out, double* __restrict__ vals_out,
+            int32_t* __restrict__ end) {
+  __shared__ int32_t sc[kStage];
+  __shared__ double sx[kStage];
+  for (int64_t t = blockIdx.x; t * kMoveRows < n; t += gridDim.x) {
+    const int32_t k0 = static_cast<int32_t>(t * kMoveRows);
+    const int32_t k1 = min(n, k0 + kMoveRows);
+    const int32_t O0 = rowptr_out[k0], span = rowptr_out[k1] - O0;
+    const bool stage = span <= kStage;  // the same for the whole block
+    const int32_t k = k0 + static_cast<int32_t>(threadIdx.x);
+    if (k < k1) {
+      const int32_t v = perm[k];
+      const int32_t a = rowptr[v], len = rowptr[v + 1] - a;
+      const int32_t o = rowptr_out[k];
+      if (len > kSortReg) {
+        for (int32_t e = 0; e < len; ++e) {
+          keys[o + e] = iperm[colidx[a + e]];
+          if (vals) vals_tmp[o + e] = vals[a + e];
+        }
+        end[k] = o + len;
+      } else {
+        end[k] = o;
+        int32_t c[kSortReg];
+        double x[kSortReg];
+#pragma unroll
+        for (int j = 0; j < kSortReg; ++j) {
+          // past the row: a key above every column, so it sorts last
+          c[j] = j < len ? iperm[colidx[a + j]] : 0x7FFFFFFF;
+          x[j] = (vals && j < len) ? vals[a + j] : 0.0;
+        }
+#pragma unroll
+        for (int i = 1; i < kSortReg; ++i) {
+#pragma unroll
+          for (int j = i; j > 0; --j) {
+            const bool sw = c[j - 1] > c[j];
+            const int32_t lo = sw ? c[j] : c[j - 1], hi = sw ? c[j - 1] : c[j];
+            const double xl = sw ? x[j] : x[j - 1], xh = sw ? x[j - 1] : x[j];
+            c[j - 1] = lo;
+            c[j] = hi;
+            x[j - 1] = xl;
+            x[j] = xh;
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < kSortReg; ++j) {
+          if (j < len) {
+            if (stage) {
+              sc[o - O0 + j] = c[j];
+              if (vals) sx[o - O0 + j] = x[j];
+            } else {
+              colidx_out[o + j] = c[j];
+              if (vals) vals_out[o + j] = x[j];
+            }
+          }
+        }
       }
-      end[k] = o + len;
-      continue;
     }
-    end[k] = o;
-    int32_t c[kSortReg];
-    double x[kSortReg];
-#pragma unroll
-    for (int j = 0; j < kSortReg; ++j) {
-      // past the row: a key above every column, so it sorts last
-      c[j] = j < len ? iperm[colidx[a + j]] : 0x7FFFFFFF;
-      x[j] = (vals && j < len) ? vals[a + j] : 0.0;
-    }
-#pragma unroll
-    for (int i = 1; i < kSortReg; ++i) {
-#pragma unroll
-      for (int j = i; j > 0; --j) {
-        const bool sw = c[j - 1] > c[j];
-        const int32_t lo = sw ? c[j] : c[j - 1], hi = sw ? c[j - 1] : c[j];
-        const double xl = sw ? x[j] : x[j - 1], xh = sw ? x[j - 1] : x[j];
-        c[j - 1] = lo;
-        c[j] = hi;
-        x[j - 1] = xl;
-        x[j] = xh;
+    if (stage) {
+      __syncthreads();
+      for (int32_t i = threadIdx.x; i < span; i += kMoveRows) {
+        colidx_out[O0 + i] = sc[i];
+        if (vals) vals_out[O0 + i] = sx[i];
       }
-    }
-#pragma unroll
-    for (int j = 0; j < kSortReg; ++j) {
-      if (j < len) {
-        colidx_out[o + j] = c[j];
-        if (vals) vals_out[o + j] = x[j];
-      }
+      __syncthreads();
     }
   }
 }
@@ -201,9 +232,9 @@ rcm_status rcm_permute(int32_t n, int64_t nnz, const int32_t* rowptr, const int3
   if (nnz == 0) return RCM_OK;
   // the degrees are scanned by now: deg holds the long rows' segment ends
   int32_t* seg_end = deg;
-  k_move_rows<<<grid_for(n, kThreads), kThreads, 0, s>>>(n, rowptr, colidx, vals, perm, iperm,
-                                                        rowptr_out, keys, vtmp, colidx_out,
-                                                        vals_out, seg_end);
+  k_move_rows<<<grid_for(n, kMoveRows), kMoveRows, 0, s>>>(n, rowptr, colidx, vals, perm, iperm,
+                                                          rowptr_out, keys, vtmp, colidx_out,
+                                                          vals_out, seg_end);
   if (hipGetLastError() != hipSuccess) return RCM_ERR_HIP;
   size_t sort_bytes = L.sort_bytes;
   hipError_t e;
