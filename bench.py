@@ -9,14 +9,20 @@ HBM, through the library's C ABI.  The default workload is the 128^3 3D
 relabelled with seed 2.
 
 Prints one JSON line.  Besides the throughput it reports:
-  - teps: edges traversed per second, counting every BFS pass of the method
-    (Algorithm 2's searches and Algorithm 3's labelled BFS; the kernel runs
-    the last search as the labelled BFS, so it scans one pass fewer than
-    this count when the search takes three or more passes);
-  - roofline: the dominant kernel (the persistent ordering kernel), its
-    algorithmic bytes per launch over its average duration measured with HIP
-    events recorded by the library on the launch stream (RCM_TIMING=1);
-  - cpu_baseline: the CPU oracle timed on the host on a bounded sample.
+  - teps: edges traversed per second over the BFS passes the kernel runs
+    (it runs the last search of Algorithm 2 as Algorithm 3's labelled BFS,
+    so with three or more searches it scans one pass fewer than the
+    method); teps_method counts every pass of the method (Algorithm 2's
+    searches plus the labelled BFS);
+  - roofline: the dominant kernel (the persistent ordering kernel), the
+    method's algorithmic bytes for what it computes -- k_pp (8m + 20n) for
+    the search's level structures, 8m + 48n for the labelled BFS, 12n for
+    the reversal -- over its average duration, measured with HIP events
+    recorded by the library on the launch stream (RCM_TIMING=1); the bytes
+    of the implementation's own passes (asynchronous search records,
+    superseded-record checks, the fused pass) are reported beside it;
+  - cpu_baseline: the CPU oracle timed on the host on a bounded sample,
+    with the host's core count and CPU model.
 """
 
 from __future__ import annotations
@@ -76,9 +82,20 @@ def unlabelled_passes(k_pp: int) -> int:
     return k_pp - 1 if k_pp >= 3 else k_pp
 
 
+def method_kernel_bytes(n: int, m: int, k_pp: int) -> int:
+    """The method's algorithmic HBM bytes for what one launch of the
+    ordering kernel computes on a component of n vertices and m directed
+    off-diagonal entries: k_pp level structures of Algorithm 2 at 8m + 20n
+    each (rowptr 8n, colidx 4m, visited gather 4m, visited write 4n,
+    frontier write + read 8n), Algorithm 3's labelled BFS at 8m + 48n (adds
+    claims, degrees, the sort keys, labels and the order) and the reversal
+    at 12n.  Independent of how the kernel runs the passes."""
+    return k_pp * (8 * m + 20 * n) + (8 * m + 48 * n) + 12 * n
+
+
 def order_kernel_bytes(n: int, m: int, k_pp: int, asynchronous: bool = True) -> int:
-    """Algorithmic HBM bytes of one launch of the ordering kernel for a
-    component of n vertices and m directed off-diagonal entries:
+    """Bytes of the passes the implementation itself runs for one launch of
+    the ordering kernel (reported beside the method's figure):
       every unlabelled BFS pass, level-synchronous: 8m + 20n (rowptr 8n,
         colidx 4m, visited gather 4m, visited write 4n, frontier write +
         read 8n);
@@ -92,11 +109,26 @@ def order_kernel_bytes(n: int, m: int, k_pp: int, asynchronous: bool = True) -> 
     return unlabelled_passes(k_pp) * per_pass + (8 * m + 48 * n) + 12 * n
 
 
-def whole_call_bytes(n: int, nnz: int, m: int, k_pp: int, asynchronous: bool = True) -> int:
-    """Algorithmic bytes of a whole ordering: the kernel above plus the
-    input scan (4n + 4nnz) and the result scan (8n + 8nnz)."""
-    return (order_kernel_bytes(n, m, k_pp, asynchronous) + (4 * n + 4 * nnz)
-            + (8 * n + 8 * nnz))
+def whole_call_bytes(n: int, nnz: int, m: int, k_pp: int) -> int:
+    """The method's algorithmic bytes of a whole ordering: the kernel's
+    share above plus the input scan (4n + 4nnz) and the result scan
+    (8n + 8nnz)."""
+    return method_kernel_bytes(n, m, k_pp) + (4 * n + 4 * nnz) + (8 * n + 8 * nnz)
+
+
+def host_cpu():
+    """Cores this process may run on and the host's CPU model."""
+    cores = len(os.sched_getaffinity(0))
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"host_cores": cores, "host_cpu": model}
 
 
 def cpu_baseline(g, budget_s: float):
@@ -118,6 +150,7 @@ def cpu_baseline(g, budget_s: float):
         "kind": "oracle",
         "sample": f"{runs} full orderings of the same workload, single-threaded C oracle, "
                   f"{dt:.1f} s",
+        **host_cpu(),
     }, r
 
 
@@ -200,7 +233,7 @@ def run_batched(args):
         value, threads, done, cdt = _pool_oracle(graphs, args.cpu_budget)
         cpu = {"value": value, "unit": "orderings/s", "cores": threads, "kind": "oracle",
                "sample": f"{done} of the 512 graphs, largest first, one oracle call per graph "
-                         f"on a {threads}-thread pool, {cdt:.1f} s"}
+                         f"on a {threads}-thread pool, {cdt:.1f} s", **host_cpu()}
     if not args.no_check:
         import oracle
 
@@ -329,7 +362,8 @@ def run_serve(args):
         value, threads, done, cdt = _pool_oracle(pool, args.cpu_budget)
         cpu = {"value": value, "unit": "orderings/s", "cores": threads, "kind": "oracle",
                "sample": f"{done} of the {len(pool)} pooled requests, largest first, one oracle "
-                         f"call per request on a {threads}-thread pool, {cdt:.1f} s"}
+                         f"call per request on a {threads}-thread pool, {cdt:.1f} s",
+               **host_cpu()}
     if not args.no_check:
         import oracle
 
@@ -612,12 +646,16 @@ def main():
     m = st["edges_traversed"] // (st["num_bfs"] + 1) if st["num_components"] == 1 else None
     ms_per_step = dt * 1000.0 / args.steps
     value = args.steps / dt
-    teps = st["edges_traversed"] * args.steps / dt
+    teps_method = st["edges_traversed"] * args.steps / dt
+    # passes the kernel scans: the unlabelled ones plus the labelled BFS
+    passes_run = unlabelled_passes(k_pp) + 1 if k_pp is not None else None
+    teps = m * passes_run * args.steps / dt if k_pp is not None else teps_method
 
     roofline = None
     asynchronous = args.async_search >= 0
     if k_pp is not None:
-        kbytes = order_kernel_bytes(g.n, m, k_pp, asynchronous)
+        kbytes = method_kernel_bytes(g.n, m, k_pp)
+        ibytes = order_kernel_bytes(g.n, m, k_pp, asynchronous)
         kavg_s = float(np.mean(kern_ms)) / 1000.0
         achieved = kbytes / kavg_s / 1e9
         roofline = {
@@ -630,9 +668,12 @@ def main():
             "frac": round(achieved / HBM_PEAK_GBS, 5),
             "traffic": measured_traffic(args.workload),
             "algorithmic_bytes_per_launch": kbytes,
+            "algorithmic_bytes_model": "k_pp(8m+20n) + (8m+48n) + 12n, k_pp = %d" % k_pp,
             "avg_launch_ms": round(kavg_s * 1000.0, 4),
+            "implementation_bytes_per_launch": ibytes,
+            "implementation_frac": round(ibytes / kavg_s / 1e9 / HBM_PEAK_GBS, 5),
             "whole_call_hbm_frac": round(
-                whole_call_bytes(g.n, g.nnz, m, k_pp, asynchronous) / (ms_per_step / 1000.0) / 1e9
+                whole_call_bytes(g.n, g.nnz, m, k_pp) / (ms_per_step / 1000.0) / 1e9
                 / HBM_PEAK_GBS, 5),
         }
 
@@ -660,12 +701,14 @@ def main():
             "n": g.n,
             "nnz": g.nnz,
             "pseudo_diameter": st["pseudo_diameter"],
-            "bfs_passes": st["num_bfs"] + 1,
+            "bfs_passes": passes_run if passes_run is not None else st["num_bfs"] + 1,
+            "method_bfs_passes": st["num_bfs"] + 1,
             "team_size": args.team_size or (256 if g.n >= (1 << 18) else 64),
             "block_threads": args.block_threads or 256,
             "search_passes": "asynchronous" if asynchronous else "level-synchronous",
         },
         "teps": round(teps, 1),
+        "teps_method": round(teps_method, 1),
         "nnz_per_s": round(g.nnz * args.steps / dt, 1),
         "edges_traversed_per_ordering": st["edges_traversed"],
         "bandwidth": [st["bandwidth_before"], st["bandwidth_after"]],

@@ -36,8 +36,10 @@
  * Conventions shared by every entry point:
  *   - CSR arrays are DEVICE pointers owned by the caller (int32 rowptr[n+1],
  *     int32 colidx[nnz], nnz = rowptr[n] < 2^31).  Rows need not be sorted;
- *     self loops are allowed and ignored.  The library never frees caller
- *     memory and keeps no state between calls.
+ *     self loops are allowed and ignored.  A pattern is a set of positions:
+ *     a column repeated within a row is malformed and always rejected with
+ *     RCM_ERR_BAD_CSR.  The library never frees caller memory and keeps no
+ *     state between calls except the parsed tuning table (tuning_file).
  *   - perm_out[k] (device, int32[n]) receives the original vertex placed at
  *     position k (new -> old), so that B = A[perm][:, perm] = P A P^T.
  *   - iperm_out (device, int32[n], optional) receives old -> new.
@@ -63,7 +65,7 @@ typedef enum {
   RCM_OK = 0,
   RCM_ERR_INVALID_ARGUMENT = 1,    /* n < 0, NULL pointer with n > 0, bad option */
   RCM_ERR_BAD_CSR = 2,             /* rowptr[0] != 0, decreasing rowptr, colidx out of
-                                      range, or (full check) a duplicate entry      */
+                                      range, or a column repeated within a row     */
   RCM_ERR_NOT_SYMMETRIC = 3,       /* (i,j) present without (j,i): always when a
                                       traversal leaves its component's label block,
                                       exhaustively with check_full                  */
@@ -102,9 +104,10 @@ typedef struct {
                                level (Algorithm 4's return value)              */
   int32_t reverse_mode;  /* 0: reverse each component's label block (default)
                             1: reverse the whole label sequence (Algorithm 1)  */
-  int32_t check_full;    /* 1: also reject duplicate entries (BAD_CSR) and
-                            asymmetric patterns (NOT_SYMMETRIC); costs
-                            O(sum of squared row lengths)                      */
+  int32_t check_full;    /* 1: also check symmetry exhaustively and reject an
+                            asymmetric pattern (NOT_SYMMETRIC) before any
+                            ordering; costs O(sum over entries of the
+                            partner row's length)                              */
   int32_t team_size;     /* work-groups cooperating on one large component;
                             0 = auto (256, one per compute unit, for graphs
                             of at least 2^18 vertices, else 64; 8 in batched

@@ -31,7 +31,7 @@
  *       last level of the last BFS (Algorithm 4); the level counter of
  *       Algorithm 4 is taken per BFS, so both run the same BFS sequence;
  *   R4  degree = number of off-diagonal entries of the row (self loops do
- *       not count; duplicate entries are rejected by the full check);
+ *       not count; duplicate entries are a malformed input, always rejected);
  *   R5  within a level, vertices are ordered by (parent label, degree, id),
  *       the id being the caller's vertex id;
  *   R6  components are processed in increasing order of their lowest id and
@@ -80,8 +80,10 @@ static int row_contains(const int32_t* rowptr, const int32_t* colidx, int32_t ro
     return 0;
 }
 
-/* Structural checks always; duplicates and symmetry (the paper's RCM is
- * defined for symmetric matrices, Section V matrix suite) when full_check. */
+/* Structural checks and duplicate entries always (reading R4: a pattern is a
+ * set of positions, so a repeated position is a malformed input); symmetry
+ * (the paper's RCM is defined for symmetric matrices, Section V matrix
+ * suite) when full_check. */
 int orc_validate(int32_t n, const int32_t* rowptr, const int32_t* colidx, int full_check)
 {
     if (n < 0) return ORC_ERR_INVALID_ARGUMENT;
@@ -93,11 +95,11 @@ int orc_validate(int32_t n, const int32_t* rowptr, const int32_t* colidx, int fu
     if (rowptr[n] > 0 && colidx == NULL) return ORC_ERR_INVALID_ARGUMENT;
     for (int32_t k = 0; k < rowptr[n]; ++k)
         if (colidx[k] < 0 || colidx[k] >= n) return ORC_ERR_BAD_CSR;
-    if (!full_check) return ORC_OK;
     for (int32_t i = 0; i < n; ++i)
         for (int32_t a = rowptr[i]; a < rowptr[i + 1]; ++a)
             for (int32_t b = a + 1; b < rowptr[i + 1]; ++b)
                 if (colidx[a] == colidx[b]) return ORC_ERR_BAD_CSR;
+    if (!full_check) return ORC_OK;
     for (int32_t i = 0; i < n; ++i)
         for (int32_t a = rowptr[i]; a < rowptr[i + 1]; ++a)
             if (!row_contains(rowptr, colidx, colidx[a], i)) return ORC_ERR_NOT_SYMMETRIC;
@@ -401,7 +403,7 @@ int32_t orc_cm_level_order(const int32_t* rowptr, const int32_t* colidx, const i
 /* Whole ordering.                                                          */
 /*   pp_variant   0 = Algorithm 2 root (default), 1 = Algorithm 4 pick      */
 /*   reverse_mode 0 = reverse each component's block (default), 1 = global  */
-/*   full_check   also reject duplicate entries and asymmetric patterns     */
+/*   full_check   also reject asymmetric patterns                          */
 /*   cm_mode      0 = Algorithm 1 queue, 1 = Algorithm 3 level-synchronous, */
 /*                2 = level order by id, 3 = level order by (degree, id)    */
 /* perm_out[k] = original vertex placed at position k (new -> old).         */

@@ -299,11 +299,18 @@ rcm_status run(const Graph& gin, const int32_t* seg_off_host, const Opts& opt, c
 
   timer.mark(0);
   // 2. checks, degrees, input bandwidth/profile
-  HIP_TRY(launch_validate_scan(g, vinfo, beta, segstats, misc + 0, s));
+  HIP_TRY(launch_validate_scan(g, vinfo, beta, segstats, misc + 0, misc + 3, s));
   int32_t h[4];
-  rcm_status st = read_ints(h, misc, 1, s);
+  rcm_status st = read_ints(h, misc, 4, s);
   if (st != RCM_OK) return st;
   if (h[0]) return RCM_ERR_BAD_CSR;
+  if (h[3]) {
+    // rows too long for the scan's own duplicate check
+    HIP_TRY(launch_dup_long(g, misc + 0, s));
+    st = read_ints(h, misc, 1, s);
+    if (st != RCM_OK) return st;
+    if (h[0]) return RCM_ERR_BAD_CSR;
+  }
   // 3. optional full check
   if (opt.check_full) {
     HIP_TRY(launch_full_check(g, misc + 1, misc + 2, s));

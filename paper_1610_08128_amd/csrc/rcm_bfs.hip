@@ -46,6 +46,8 @@
 // the pass number (no reset between passes) and appended to the next level
 // through an LDS stage and one global atomic per work-group.
 
+#include <mutex>
+
 #include "rcm_common.hpp"
 
 namespace rcm {
@@ -880,11 +882,11 @@ __device__ __forceinline__ void own_bfs_levels(const BfsParams& P, Team& t, Shar
 // One level structure (Section II-A) of the component whose label block is
 // [o, end), rooted at `root`.  Vertices are written level by level into qi.
 // Returns the eccentricity of root and the minimum (degree << 32 | id) over
-// the last level.  With found_end, the block end is unknown (end bounds it)
+// the last level.  With find_end, the block end is unknown (end bounds it)
 // and the pass reports where the component ended.
 __device__ __forceinline__ void bfs_pass(const BfsParams& P, Team& t, Shared& S, int32_t o, int32_t end,
                          int32_t root, int32_t epoch, int parity, int32_t& ecc,
-                         uint64_t& lastkey, int32_t* found_end) {
+                         uint64_t& lastkey, bool find_end, int32_t& found_end) {
   const long long clk0 = wall_clock64();
   int32_t* tail = t.ctl->tail + parity * 3;
   unsigned long long* minkey = t.ctl->minkey + parity * 3;
@@ -949,9 +951,9 @@ __device__ __forceinline__ void bfs_pass(const BfsParams& P, Team& t, Shared& S,
     t.aborted = true;
     return;
   }
-  if (found_end != nullptr) {
+  if (find_end) {
     // size discovery: the component is whatever this pass reached
-    *found_end = cur_e;
+    found_end = cur_e;
   } else if (cur_e != end) {
     if (threadIdx.x == 0 && t.wid == 0)
       flag_error(t.g, RCM_ERR_NOT_SYMMETRIC, 2, t.comp, epoch, level, cur_b, cur_e, end);
@@ -1009,14 +1011,14 @@ __device__ __forceinline__ int32_t ring_pos(int32_t o, int32_t ring, int32_t v) 
 // frontier records) and detects the end.  Finally a sweep over the vertices
 // of the component's graph [seg_b, seg_e) (a component never leaves its
 // graph) carrying this pass's tag yields the eccentricity, the last level's minimum
-// key, the number of vertices reached (the component's size when found_end
+// key, the number of vertices reached (the component's size when find_end
 // is given) and, for level orders, the keys.  Returns false if the ring
 // would overflow (a frontier and its successor above the block size), having
 // computed nothing: the caller then runs bfs_pass.
 __device__ __forceinline__ bool async_bfs_pass(const BfsParams& P, Team& t, Shared& S, int32_t o,
                                                int32_t end, int32_t root, uint32_t tag, int parity,
                                                int32_t seg_b, int32_t seg_e, int32_t& ecc,
-                                               uint64_t& lastkey, int32_t* found_end) {
+                                               uint64_t& lastkey, bool find_end, int32_t& found_end) {
   const long long clk0 = wall_clock64();
   const int B = blockDim.x;
   int32_t* tail = t.ctl->tail + parity * 3;
@@ -1228,8 +1230,8 @@ __device__ __forceinline__ bool async_bfs_pass(const BfsParams& P, Team& t, Shar
   const int32_t count = ld_relaxed(&t.ctl->a_cnt[parity]);
   if (P.label_mode != 0)
     t.pm = __hip_atomic_load(&t.ctl->pass_m[parity], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  if (found_end != nullptr) {
-    *found_end = o + count;
+  if (find_end) {
+    found_end = o + count;
   } else if (count != end - o) {
     // the pass reached more or fewer vertices than the component holds
     if (threadIdx.x == 0 && t.wid == 0)
@@ -1714,11 +1716,12 @@ __device__ __forceinline__ void global_label_level(const BfsParams& P, Team& t, 
 }
 
 // The labelled BFS of Algorithm 3 from `root`; labels are the positions in
-// qi[o, end).  Returns the number of levels; *msum = sum of degrees.  With
-// lastkey, it also reports the minimum (degree << 32 | id) over its last
+// qi[o, end).  Returns the number of levels; msum = sum of degrees.  With
+// want_lastkey, it also reports (in lastkey) the minimum (degree << 32 | id) over its last
 // level, so that it can stand in for a level structure of the search.
 __device__ __forceinline__ int32_t label_pass(const BfsParams& P, Team& t, Shared& S, int32_t o, int32_t end,
-                              int32_t root, long long* msum, uint64_t* lastkey) {
+                              int32_t root, long long& msum, bool want_lastkey,
+                              uint64_t& lastkey) {
   const long long clk0 = wall_clock64();
   const int B = blockDim.x;
   const int4 rinf = P.vinfo[root];
@@ -1783,7 +1786,7 @@ __device__ __forceinline__ int32_t label_pass(const BfsParams& P, Team& t, Share
     t.aborted = true;
     return 0;
   }
-  if (lastkey != nullptr) {
+  if (want_lastkey) {
     // the last level is qi[cur_b, cur_e): its records carry the degree
     int32_t lo, hi;
     my_chunk(cur_b, cur_e, t.W, t.wid, lo, hi);
@@ -1800,9 +1803,9 @@ __device__ __forceinline__ int32_t label_pass(const BfsParams& P, Team& t, Share
   if (threadIdx.x == 0 && tot_m != 0)
     __hip_atomic_fetch_add(&t.ctl->msum, tot_m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   team_barrier(t, S, false);
-  *msum = __hip_atomic_load(&t.ctl->msum, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  if (lastkey != nullptr)
-    *lastkey = __hip_atomic_load(&t.ctl->lastkey, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  msum = __hip_atomic_load(&t.ctl->msum, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (want_lastkey)
+    lastkey = __hip_atomic_load(&t.ctl->lastkey, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (t.wid == 0 && threadIdx.x == 0) {
     t.ctl->clk[1] += wall_clock64() - clk0;
     t.ctl->clk[3] += levels;
@@ -1816,10 +1819,10 @@ __device__ __forceinline__ int32_t label_pass(const BfsParams& P, Team& t, Share
 // barrier slots of their own; the others sleep until it is done and then
 // take its results from the team's control block.
 __device__ __forceinline__ int32_t labelled_pass(const BfsParams& P, Team& t, Shared& S, int32_t o,
-                                                 int32_t end, int32_t root, long long* msum,
-                                                 uint64_t* lastkey) {
+                                                 int32_t end, int32_t root, long long& msum,
+                                                 bool want_lastkey, uint64_t& lastkey) {
   const int Wl = P.label_team < t.W ? P.label_team : t.W;
-  if (Wl >= t.W) return label_pass(P, t, S, o, end, root, msum, lastkey);
+  if (Wl >= t.W) return label_pass(P, t, S, o, end, root, msum, want_lastkey, lastkey);
   t.ldone += 1;
   if (t.wid < Wl) {
     const int W0 = t.W;
@@ -1828,7 +1831,7 @@ __device__ __forceinline__ int32_t labelled_pass(const BfsParams& P, Team& t, Sh
     t.W = Wl;
     t.slots = t.sub_slots;
     t.seq = t.sub_seq;
-    const int32_t levels = label_pass(P, t, S, o, end, root, msum, lastkey);
+    const int32_t levels = label_pass(P, t, S, o, end, root, msum, want_lastkey, lastkey);
     t.sub_seq = t.seq;
     t.W = W0;
     t.slots = slots0;
@@ -1855,9 +1858,9 @@ __device__ __forceinline__ int32_t labelled_pass(const BfsParams& P, Team& t, Sh
   __syncthreads();
   t.aborted = S.flag != 0;
   if (t.aborted) return 0;
-  *msum = __hip_atomic_load(&t.ctl->msum, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  if (lastkey != nullptr)
-    *lastkey = __hip_atomic_load(&t.ctl->lastkey, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  msum = __hip_atomic_load(&t.ctl->msum, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (want_lastkey)
+    lastkey = __hip_atomic_load(&t.ctl->lastkey, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   return S.state[0];
 }
 
@@ -1887,17 +1890,18 @@ __device__ __forceinline__ void order_component(const BfsParams& P, Team& t, Sha
       P.async_search != 0 && t.W > 1 && task.index < (1 << 25) &&
       (size < 0 || static_cast<long long>(size) * 8 >= static_cast<long long>(seg_e - seg_b));
   auto search_pass = [&](int32_t from, int32_t epoch, int parity, int32_t& e, uint64_t& lk,
-                         int32_t* found_at) {
+                         bool find_end) {
     if (try_async && epoch < 64) {
       const uint32_t tag =
           (static_cast<uint32_t>(task.index + 1) << 6) | static_cast<uint32_t>(epoch);
-      if (async_bfs_pass(P, t, S, o, end, from, tag, parity, seg_b, seg_e, e, lk, found_at))
+      if (async_bfs_pass(P, t, S, o, end, from, tag, parity, seg_b, seg_e, e, lk, find_end,
+                         found))
         return;
       if (t.aborted) return;
     }
-    bfs_pass(P, t, S, o, end, from, epoch, parity, e, lk, found_at);
+    bfs_pass(P, t, S, o, end, from, epoch, parity, e, lk, find_end, found);
   };
-  search_pass(task.seed, 1, 0, ecc, lastkey, size >= 0 ? nullptr : &found);
+  search_pass(task.seed, 1, 0, ecc, lastkey, size < 0);
   if (t.aborted) return;
   if (size < 0) {
     size = found - o;
@@ -1927,12 +1931,12 @@ __device__ __forceinline__ void order_component(const BfsParams& P, Team& t, Sha
         team_barrier(t, S, false);
         if (t.aborted) return;
       }
-      levels = labelled_pass(P, t, S, o, end, v, &m, &lastkey);
+      levels = labelled_pass(P, t, S, o, end, v, m, true, lastkey);
       if (t.aborted) return;
       ecc = levels - 1;
       labelled = true;
     } else {
-      search_pass(v, nbfs, (nbfs - 1) & 1, ecc, lastkey, nullptr);
+      search_pass(v, nbfs, (nbfs - 1) & 1, ecc, lastkey, false);
       if (t.aborted) return;
     }
   }
@@ -1944,14 +1948,15 @@ __device__ __forceinline__ void order_component(const BfsParams& P, Team& t, Sha
     // the search's last one or, for Algorithm 4's pick, one more
     if (P.pp_variant == 1) {
       uint64_t k2 = 0;
-      search_pass(root, nbfs + 1, nbfs & 1, ecc, k2, nullptr);
+      search_pass(root, nbfs + 1, nbfs & 1, ecc, k2, false);
       if (t.aborted) return;
     }
     // every vertex now holds its level and block start; the host sorts
     levels = ecc + 1;
     m = t.pm;
   } else if (!labelled) {
-    levels = labelled_pass(P, t, S, o, end, root, &m, nullptr);
+    uint64_t unused_key = 0;
+    levels = labelled_pass(P, t, S, o, end, root, m, false, unused_key);
     if (t.aborted) return;
   }
   if (t.wid == 0 && threadIdx.x == 0) {
@@ -1976,7 +1981,7 @@ __device__ __forceinline__ void order_component(const BfsParams& P, Team& t, Sha
 // components from a queue (largest first); every other block, and the team
 // blocks once that queue is empty, orders small components alone, also
 // largest first.
-__global__ void __launch_bounds__(512) k_order(BfsParams P) {
+__device__ __forceinline__ void order_main(const BfsParams& P) {
   __shared__ Shared S;
   Team t;
   t.g = P.gctl;
@@ -2031,11 +2036,30 @@ __global__ void __launch_bounds__(512) k_order(BfsParams P) {
   }
 }
 
+// One instance per work-group size, so that the compiler sizes registers for
+// it: with 256 threads a wave may hold twice the registers of a 512-thread
+// work-group's.
+template <int kThreads>
+__global__ void __launch_bounds__(kThreads) k_order(BfsParams P) {
+  order_main(P);
+}
+
+const void* order_kernel(int32_t threads) {
+  return threads > 256 ? reinterpret_cast<const void*>(k_order<512>)
+                       : reinterpret_cast<const void*>(k_order<256>);
+}
+
+// Cooperative launches of this library in one process never overlap: each
+// is sized to what the device holds at once, and two of them resident side
+// by side could each hold part of the other's team slots and wait forever.
+std::mutex g_coop_mutex;
+
 }  // namespace
 
 int max_team_blocks(int32_t threads) {
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_order, threads, 0) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, order_kernel(threads), threads, 0) !=
+      hipSuccess)
     return 0;
   int dev = 0;
   (void)hipGetDevice(&dev);
@@ -2046,13 +2070,24 @@ int max_team_blocks(int32_t threads) {
 
 hipError_t launch_order(const BfsParams& p, int32_t blocks, int32_t threads, hipStream_t s) {
   if (blocks <= 0 || (p.n_big <= 0 && p.ntasks <= 0)) return hipSuccess;
+  if (threads != 256 && threads != 512) return hipErrorInvalidValue;
   BfsParams q = p;
   if (q.big_blocks > 0 && q.team_size > 1) {
+    // held until the kernel has finished, so that another thread's
+    // cooperative launch (a second stream of the serving engine, say) cannot
+    // take part of the device while this one's teams wait for each other
+    std::lock_guard<std::mutex> lk(g_coop_mutex);
     void* args[] = {&q};
-    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_order), dim3(blocks),
-                                      dim3(threads), args, 0, s);
+    hipError_t e = hipLaunchCooperativeKernel(order_kernel(threads), dim3(blocks), dim3(threads),
+                                              args, 0, s);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(s);
   }
-  k_order<<<blocks, threads, 0, s>>>(q);
+  if (threads > 256) {
+    k_order<512><<<blocks, threads, 0, s>>>(q);
+  } else {
+    k_order<256><<<blocks, threads, 0, s>>>(q);
+  }
   return hipGetLastError();
 }
 

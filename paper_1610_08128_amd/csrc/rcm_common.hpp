@@ -228,8 +228,12 @@ struct Graph {
   const int32_t* seg_off; // device int32[nseg+1] vertex offsets of segments
 };
 
+// err: malformed rows (bounds, columns out of range, repeated columns in
+// rows of up to 64 entries); long_rows: set when a row is longer, whose
+// repeated columns launch_dup_long then checks (into err).
 hipError_t launch_validate_scan(const Graph& g, int4* vinfo, int32_t* beta, SegStats* seg,
-                                int32_t* err, hipStream_t s);
+                                int32_t* err, int32_t* long_rows, hipStream_t s);
+hipError_t launch_dup_long(const Graph& g, int32_t* err, hipStream_t s);
 hipError_t launch_full_check(const Graph& g, int32_t* err_dup, int32_t* err_sym, hipStream_t s);
 // Components of the vertices with skip[v] == 0 (skip may be null: all).
 hipError_t launch_components(const Graph& g, const int32_t* skip, int32_t* parent, int32_t* csize,

@@ -31,9 +31,19 @@ inline int grid_for(int64_t work, int threads, int max_blocks = 8192) {
 // ---------------------------------------------------------------------------
 // vinfo[i] = (row begin, row end, degree, 0): one 16-byte record per vertex,
 // read by the traversal in a single load.
+//
+// A pattern is a set of positions, so a column repeated within a row is a
+// malformed input (rows may come in any order).  Rows of up to kDupRegs
+// entries are loaded into registers at once and compared pairwise there;
+// rows of up to kDupShort entries are compared by re-reading the row (from
+// the cache); longer rows raise *long_rows and are checked by k_dup_long.
+constexpr int kDupRegs = 16;
+constexpr int kDupShort = 64;
+
 __global__ void k_validate_scan(int32_t n, int32_t nnz, const int32_t* __restrict__ rowptr,
                                 const int32_t* __restrict__ colidx, int4* __restrict__ vinfo,
-                                int32_t* __restrict__ beta, int32_t* __restrict__ err) {
+                                int32_t* __restrict__ beta, int32_t* __restrict__ err,
+                                int32_t* __restrict__ long_rows) {
   for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     const int32_t a = rowptr[i];
     const int32_t b = rowptr[i + 1];
@@ -43,18 +53,75 @@ __global__ void k_validate_scan(int32_t n, int32_t nnz, const int32_t* __restric
       atomicOr(err, 1);
       continue;
     }
+    const int32_t len = b - a;
     int32_t d = 0;
     int32_t mn = i;
     bool bad = false;
-    for (int32_t k = a; k < b; ++k) {
-      const int32_t c = colidx[k];
-      if (c < 0 || c >= n) { bad = true; continue; }
-      d += (c != i);
-      mn = c < mn ? c : mn;
+    if (len <= kDupRegs) {
+      // all loads of the row in flight together (indices clamped into the
+      // row; lanes past its end take distinct negative fillers)
+      int32_t r[kDupRegs];
+#pragma unroll
+      for (int j = 0; j < kDupRegs; ++j) {
+        const int32_t k = a + (j < len ? j : (len > 0 ? len - 1 : 0));
+        const int32_t c = len > 0 ? colidx[k] : 0;
+        r[j] = j < len ? c : -1 - j;
+      }
+#pragma unroll
+      for (int j = 0; j < kDupRegs; ++j) {
+        if (j >= len) continue;
+        const int32_t c = r[j];
+        if (c < 0 || c >= n) { bad = true; continue; }
+        d += (c != i);
+        mn = c < mn ? c : mn;
+      }
+#pragma unroll
+      for (int j = 0; j < kDupRegs; ++j)
+#pragma unroll
+        for (int k = j + 1; k < kDupRegs; ++k) bad |= r[j] == r[k];
+    } else {
+      for (int32_t k = a; k < b; ++k) {
+        const int32_t c = colidx[k];
+        if (c < 0 || c >= n) { bad = true; continue; }
+        d += (c != i);
+        mn = c < mn ? c : mn;
+      }
+      if (len <= kDupShort) {
+        for (int32_t k = a + 1; k < b && !bad; ++k) {
+          const int32_t c = colidx[k];
+          for (int32_t k2 = a; k2 < k; ++k2) bad |= colidx[k2] == c;
+        }
+      } else {
+        atomicOr(long_rows, 1);
+      }
     }
     if (bad) atomicOr(err, 1);
     vinfo[i] = make_int4(a, b, d, 0);
     beta[i] = i - mn;
+  }
+}
+
+// Duplicates in the rows longer than kDupShort: one work-group per row, each
+// thread comparing its entries with the ones after them.  Only launched when
+// k_validate_scan saw such a row; rows with invalid bounds were reported
+// there and are skipped.
+__global__ void k_dup_long(int32_t n, int32_t nnz, const int32_t* __restrict__ rowptr,
+                           const int32_t* __restrict__ colidx, int32_t* __restrict__ err) {
+  __shared__ int found;
+  for (int32_t i = blockIdx.x; i < n; i += gridDim.x) {
+    const int32_t a = rowptr[i];
+    const int32_t b = rowptr[i + 1];
+    if (a < 0 || b < a || b > nnz || b - a <= kDupShort) continue;
+    if (threadIdx.x == 0) found = 0;
+    __syncthreads();
+    for (int32_t k = a + threadIdx.x; k < b; k += blockDim.x) {
+      const int32_t c = colidx[k];
+      bool dup = false;
+      for (int32_t k2 = k + 1; k2 < b && !dup; ++k2) dup = colidx[k2] == c;
+      if (dup) found = 1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && found) atomicOr(err, 1);
   }
 }
 
@@ -677,15 +744,20 @@ hipError_t launch_exclusive_scan(const int32_t* in, int32_t* out, int32_t count,
 }
 
 hipError_t launch_validate_scan(const Graph& g, int4* vinfo, int32_t* beta, SegStats* seg,
-                                int32_t* err, hipStream_t s) {
+                                int32_t* err, int32_t* long_rows, hipStream_t s) {
   k_validate_scan<<<grid_for(g.n, kThreads), kThreads, 0, s>>>(g.n, g.nnz, g.rowptr, g.colidx,
-                                                                vinfo, beta, err);
+                                                                vinfo, beta, err, long_rows);
   if (g.nseg > 1)
     k_check_segments<<<grid_for((static_cast<int64_t>(g.n) + kSegTile - 1) / kSegTile, 1),
                        kThreads, 0, s>>>(g.n, g.nnz, g.rowptr, g.colidx, g.seg_off, g.nseg, err);
   constexpr int32_t chunk = 8192;
   const int nb = (g.n + chunk - 1) / chunk;
   k_seg_reduce<<<nb, kThreads, 0, s>>>(beta, g.n, chunk, g.seg_off, g.nseg, seg, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_dup_long(const Graph& g, int32_t* err, hipStream_t s) {
+  k_dup_long<<<grid_for(g.n, 1, 2048), kThreads, 0, s>>>(g.n, g.nnz, g.rowptr, g.colidx, err);
   return hipGetLastError();
 }
 

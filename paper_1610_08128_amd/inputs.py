@@ -19,7 +19,8 @@ stand-ins of the same kind are generated here:
 * batches and arrival streams of the above.
 
 Every generator writes rows sorted by column with the diagonal present unless
-asked otherwise.  Vertex ids are randomly relabelled from a seed with
+asked otherwise; ``shuffle_rows`` puts each row's entries in a seeded random
+order (the interface accepts rows in any order).  Vertex ids are randomly relabelled from a seed with
 ``numpy.random.default_rng(seed).permutation(n)`` applied to both endpoints.
 """
 
@@ -48,6 +49,7 @@ __all__ = [
     "disjoint_union",
     "drop_diagonal",
     "add_random_self_loops",
+    "shuffle_rows",
     "config",
     "CONFIG_NAMES",
     "batch_graphs",
@@ -297,6 +299,19 @@ def add_random_self_loops(g: Graph, frac: float, seed: int) -> Graph:
     rowptr = np.zeros(g.n + 1, dtype=np.int64)
     np.cumsum(np.bincount(r, minlength=g.n), out=rowptr[1:])
     return Graph(g.n, rowptr.astype(np.int32), c, g.name + "_loops")
+
+
+def shuffle_rows(g: Graph, seed: int) -> Graph:
+    """The same pattern with every row's entries in a random order: one
+    random key per entry from ``default_rng(seed)``, then a stable sort of
+    the entries by (row, key).  The set of entries of each row is unchanged,
+    so this only exercises the "rows need not be sorted" promise."""
+    rng = np.random.default_rng(seed)
+    lens = np.diff(g.rowptr).astype(np.int64)
+    rows = np.repeat(np.arange(g.n, dtype=np.int64), lens)
+    keys = rng.random(rows.size)
+    order = np.lexsort((keys, rows))
+    return Graph(g.n, g.rowptr.copy(), g.colidx[order].astype(np.int32), g.name + "_shuf")
 
 
 # --------------------------------------------------------------------------

@@ -111,3 +111,38 @@ def test_gpu_permute_and_spmv(gi):
     rows = np.repeat(np.arange(g.n), np.diff(want_rp))
     bw = int(np.max(np.maximum(rows - want_ci, 0))) if want_ci.size else 0
     assert bw == st["bandwidth_after"]
+
+
+def _check_gpu_permute(g, seed):
+    import torch
+    from paper_1610_08128_amd import apply, rcm
+
+    rng = np.random.default_rng(seed)
+    vals = rng.standard_normal(g.nnz)
+    rp = torch.from_numpy(g.rowptr).cuda()
+    ci = torch.from_numpy(g.colidx).cuda()
+    perm, iperm, _ = rcm.order(rp, ci, return_iperm=True)
+    want_rp, want_ci, want_v = oracle.permute_csr(g.n, g.rowptr, g.colidx, perm.cpu().numpy(),
+                                                  vals)
+    brp, bci, bv = apply.permute(rp, ci, perm, iperm, torch.from_numpy(vals).cuda())
+    assert np.array_equal(brp.cpu().numpy(), want_rp)
+    assert np.array_equal(bci.cpu().numpy(), want_ci)
+    assert np.array_equal(bv.cpu().numpy(), want_v)
+
+
+@pytest.mark.gpu
+def test_gpu_permute_dense_rows():
+    """About 60 entries per row: a block's 256 rows then hold more entries than
+    its LDS stage, so the rows are written directly; rows in random order."""
+    g = I.shuffle_rows(I.erdos_renyi(600, 0.1, 11), 2)
+    assert int(g.rowptr[256]) > 256 * 16
+    _check_gpu_permute(g, 1)
+
+
+@pytest.mark.gpu
+def test_gpu_permute_many_tiles():
+    """More rows than one pass of the grid covers (8,192 blocks of 256 rows),
+    so blocks take a second tile."""
+    g = I.grid2d(1500, 1500, seed=12)
+    assert g.n > 8192 * 256
+    _check_gpu_permute(g, 2)

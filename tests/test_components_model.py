@@ -267,3 +267,26 @@ def test_edge_into_the_skipped_set_is_reported():
     skip = np.array([True, False, True, False])
     _, err = search(4, rowptr, colidx, [0, 4], skip, random.Random(0))
     assert err
+
+
+@pytest.mark.parametrize("seed", range(16))
+def test_shuffled_rows_under_interleavings(seed):
+    """Rows in a random order: the capped contraction rounds then see an
+    arbitrary subset of each row, which must not change the result."""
+    parts = [I.shuffle_rows(p, seed + i) for i, p in enumerate(_parts(2000 + seed))]
+    n, rowptr, colidx, seg = _union(parts)
+    skip = np.zeros(n, bool)
+    want = _lowest_ids(n, rowptr, colidx, skip)
+    for schedule in range(3):
+        got, err = search(n, rowptr, colidx, seg, skip, random.Random(seed * 100 + schedule))
+        assert not err
+        assert np.array_equal(np.array(got), want), (seed, schedule)
+    g = I.shuffle_rows(I.disjoint_union(_parts(3000 + seed), seed=seed), seed)
+    n, rowptr, colidx = g.n, g.rowptr.astype(np.int64), g.colidx.astype(np.int64)
+    A = sp.csr_matrix((np.ones(colidx.size), colidx, rowptr), shape=(n, n))
+    _, lab = connected_components(A, directed=False)
+    skip = lab == lab[0]
+    want = _lowest_ids(n, rowptr, colidx, skip)
+    got, err = search(n, rowptr, colidx, [0, n], skip, random.Random(seed))
+    assert not err
+    assert np.array_equal(np.array(got)[~skip], want[~skip])

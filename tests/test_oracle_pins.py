@@ -134,10 +134,15 @@ def test_validate_statuses():
     assert oracle.validate(5, g.rowptr, badc) == oracle.ERR_BAD_CSR
     badc = g.colidx.copy(); badc[3] = -1
     assert oracle.validate(5, g.rowptr, badc) == oracle.ERR_BAD_CSR
-    # duplicate entry: only the full check sees it
+    # duplicate entry: a pattern is a set of positions, so a repeated one is
+    # malformed with or without the full check (reading R4)
     dup = g.colidx.copy(); dup[1] = dup[0]
-    assert oracle.validate(5, g.rowptr, dup, False) == oracle.OK
+    assert oracle.validate(5, g.rowptr, dup, False) == oracle.ERR_BAD_CSR
     assert oracle.validate(5, g.rowptr, dup, True) == oracle.ERR_BAD_CSR
+    # symmetric as a set but with (0, 1) twice in row 0
+    rp = np.array([0, 3, 6, 8], np.int32)
+    ci = np.array([0, 1, 1, 0, 1, 2, 1, 2], np.int32)
+    assert oracle.validate(3, rp, ci, False) == oracle.ERR_BAD_CSR
     # asymmetric pattern: row 0 -> 4 without 4 -> 0
     rp = np.array([0, 2, 3, 4, 5, 6], np.int32)
     ci = np.array([0, 4, 1, 2, 3, 4], np.int32)
@@ -145,6 +150,28 @@ def test_validate_statuses():
     assert oracle.validate(5, rp, ci, True) == oracle.ERR_NOT_SYMMETRIC
     r = oracle.rcm(5, rp, ci, full_check=True)
     assert r.status == oracle.ERR_NOT_SYMMETRIC
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_validate_duplicates_against_row_sets(seed):
+    """Duplicates anywhere in a row, rows in any order: the oracle's status
+    equals the plain definition (some row has fewer distinct columns than
+    entries), for short rows and for rows far longer than a register batch."""
+    rng = np.random.default_rng(seed)
+    g = I.shuffle_rows(I.erdos_renyi(120, 0.02 + 0.1 * (seed % 3), seed), seed)
+    assert oracle.validate(g.n, g.rowptr, g.colidx) == oracle.OK
+    ci = g.colidx.copy()
+    lens = np.diff(g.rowptr)
+    rows = np.nonzero(lens >= 2)[0]
+    r = int(rows[rng.integers(0, rows.size)])
+    a, b = int(g.rowptr[r]), int(g.rowptr[r + 1])
+    i, j = rng.choice(np.arange(a, b), 2, replace=False)
+    ci[j] = ci[i]
+    distinct = all(np.unique(ci[g.rowptr[v]:g.rowptr[v + 1]]).size == lens[v]
+                   for v in range(g.n))
+    assert not distinct
+    assert oracle.validate(g.n, g.rowptr, ci) == oracle.ERR_BAD_CSR
+    assert oracle.rcm(g.n, g.rowptr, ci).status == oracle.ERR_BAD_CSR
 
 
 # ---------------------------------------------------------------------------
@@ -311,6 +338,80 @@ def test_grid_root_is_a_corner(seed):
     sizes = np.bincount(level)
     want = [min(d + 1, k, m, k + m - 1 - d) for d in range(k + m - 1)]
     assert sizes.tolist() == want
+
+
+# ---------------------------------------------------------------------------
+# Statistics of the search: how many level structures Algorithm 2 builds, and
+# the edges those and the labelled BFS scan
+# ---------------------------------------------------------------------------
+
+def _george_liu_bfs_count(g, A, members):
+    """Algorithm 2 on one component, with scipy's unweighted BFS distances
+    in place of the oracle's own: start at the lowest id, and while the
+    newest level structure is deeper than the one before, restart from the
+    minimum-(degree, id) vertex of its last level.  Returns the number of
+    level structures built."""
+    deg = np.array([np.count_nonzero(g.colidx[g.rowptr[v]:g.rowptr[v + 1]] != v)
+                    for v in range(g.n)])
+    def last_level(root):
+        d = shortest_path(A, method="D", unweighted=True, indices=root)
+        ecc = int(np.max(d[members]))
+        ring = members[d[members] == ecc]
+        return ecc, int(min(ring, key=lambda v: (deg[v], v)))
+    r = int(members.min())
+    ecc, pick = last_level(r)
+    count, nlvl = 1, ecc - 1
+    while ecc > nlvl:
+        nlvl = ecc
+        r = pick
+        ecc, pick = last_level(r)
+        count += 1
+    return count
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_edges_traversed_counts_search_and_labelling(seed):
+    """edges_traversed = sum over components of (level structures of the
+    search + 1 labelled BFS) x (directed off-diagonal entries of the
+    component), with the search's count taken from scipy's BFS and the
+    entries counted from the CSR, for both root variants (which build the
+    same level structures)."""
+    rng = np.random.default_rng(seed)
+    parts = [I.erdos_renyi(int(rng.integers(2, 60)), 0.08, seed),
+             I.grid2d(int(rng.integers(2, 9)), int(rng.integers(2, 9)), seed=seed),
+             I.random_tree(int(rng.integers(1, 40)), seed), I.path(1)]
+    g = I.disjoint_union(parts, seed=seed)
+    A = _sp(g)
+    _, lab = connected_components(A, directed=False)
+    rows = np.repeat(np.arange(g.n), np.diff(g.rowptr))
+    off = rows != g.colidx
+    want_bfs, want_edges = 0, 0
+    for c in np.unique(lab):
+        members = np.nonzero(lab == c)[0]
+        k = _george_liu_bfs_count(g, A, members)
+        m_c = int(np.count_nonzero(off & (lab[rows] == c)))
+        want_bfs += k
+        want_edges += (k + 1) * m_c
+    for pp in (0, 1):
+        st = oracle.rcm(g.n, g.rowptr, g.colidx, pp_variant=pp).stats
+        assert st["num_bfs"] == want_bfs, (pp, st)
+        assert st["edges_traversed"] == want_edges, (pp, st)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_edges_traversed_grid_closed_form(seed):
+    """On a relabelled k x m grid, Algorithm 2 started at a vertex that is
+    not a corner builds 3 level structures (the start, the far corner it
+    finds, the opposite corner, which is no deeper); started at a corner it
+    builds 2.  With the labelled BFS: 4 (or 3) sweeps over the 2(k(m-1) +
+    m(k-1)) directed edges."""
+    k, m = 5 + seed % 3, 9 + seed
+    g = I.grid2d(k, m, seed=seed)
+    deg = oracle.degrees(g.n, g.rowptr, g.colidx)
+    sweeps = 3 if deg[0] == 2 else 4
+    st = oracle.rcm(g.n, g.rowptr, g.colidx).stats
+    assert st["num_bfs"] == sweeps - 1
+    assert st["edges_traversed"] == sweeps * 2 * (k * (m - 1) + m * (k - 1))
 
 
 # ---------------------------------------------------------------------------

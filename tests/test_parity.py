@@ -176,19 +176,23 @@ def test_status_codes_on_gpu():
         rcm.order(torch.from_numpy(badr).cuda(), torch.from_numpy(g.colidx).cuda())
     assert e.value.status == rcm.ERR_BAD_CSR
     # a duplicated entry (0, 1) that keeps the pattern symmetric as a set:
-    # only the full check rejects it
+    # malformed with or without the full check
     rp = np.array([0, 3, 6, 8], np.int32)
     ci = np.array([0, 1, 1, 0, 1, 2, 1, 2], np.int32)
-    assert oracle.validate(3, rp, ci, True) == oracle.ERR_BAD_CSR
-    with pytest.raises(rcm.RcmError) as e:
-        rcm.order(torch.from_numpy(rp).cuda(), torch.from_numpy(ci).cuda(), check_full=True)
-    assert e.value.status == rcm.ERR_BAD_CSR
+    assert oracle.validate(3, rp, ci, False) == oracle.ERR_BAD_CSR
+    for full in (False, True):
+        with pytest.raises(rcm.RcmError) as e:
+            rcm.order(torch.from_numpy(rp).cuda(), torch.from_numpy(ci).cuda(), check_full=full)
+        assert e.value.status == rcm.ERR_BAD_CSR
     # an asymmetric pattern without the full check: the traversal notices that
     # it leaves a component and reports it instead of writing out of bounds
-    dup = g.colidx.copy()
-    dup[1] = dup[0]
+    # (row 0 of the path loses its entry (0, 1); no row repeats a column)
+    rp = np.array([0, 1, 4, 6, 8, 10, 12], np.int32)
+    ci = np.array([0, 0, 1, 2, 2, 3, 3, 4, 4, 5, 4, 5], np.int32)
+    assert oracle.validate(6, rp, ci, False) == oracle.OK
+    assert oracle.validate(6, rp, ci, True) == oracle.ERR_NOT_SYMMETRIC
     with pytest.raises(rcm.RcmError) as e:
-        rcm.order(torch.from_numpy(g.rowptr).cuda(), torch.from_numpy(dup).cuda())
+        rcm.order(torch.from_numpy(rp).cuda(), torch.from_numpy(ci).cuda())
     assert e.value.status == rcm.ERR_NOT_SYMMETRIC
     rp = np.array([0, 2, 3, 4, 5, 6], np.int32)
     ci = np.array([0, 4, 1, 2, 3, 4], np.int32)
@@ -396,3 +400,122 @@ def test_level_synchronous_search(seed):
 def test_level_synchronous_grid_128_cubed(team, threads, narrow):
     check(I.config(1), async_search=-1, team_size=team, block_threads=threads,
           narrow_cutoff=narrow)
+
+
+# ---------------------------------------------------------------------------
+# Rows in any order, rows without a diagonal (the interface promises both)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("idx", range(17))
+def test_tiny_graphs_shuffled_rows(idx):
+    g = I.shuffle_rows(_tiny_graphs()[idx], 50 + idx)
+    check(g)
+    check(g, pp_variant=1, reverse_mode=1)
+    check(g, small_cutoff=1, team_size=3, narrow_cutoff=-1)
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_random_graphs_shuffled_rows(seed):
+    """Shuffled rows on the single-work-group path and on the team path (the
+    component search's capped contraction rounds read only the first row
+    entries, whichever they are)."""
+    g = I.shuffle_rows(_random_graph(1200 + seed), seed)
+    check(g, pp_variant=seed % 2, reverse_mode=(seed // 2) % 2)
+    check(g, small_cutoff=1, team_size=2 + seed % 7, narrow_cutoff=16 * (seed % 3),
+          async_search=1 - 2 * (seed % 2))
+    h = I.shuffle_rows(I.drop_diagonal(_random_graph(1300 + seed)), seed)
+    check(h)
+    check(h, small_cutoff=1, team_size=4, label_mode=seed % 3)
+
+
+def test_grid_128_cubed_shuffled_rows():
+    """The 3D grid at full size in the benchmark's launch configuration, with
+    each row in a random order."""
+    check(I.shuffle_rows(I.config(1), 7))
+
+
+def test_grid_128_cubed_without_diagonal():
+    """No row holds its diagonal entry (degree = row length), rows shuffled,
+    at full size; also on teams of 64 with the level-synchronous search."""
+    g = I.shuffle_rows(I.drop_diagonal(I.config(1)), 8)
+    g.name = "grid3d_128_nodiag_shuf"
+    check(g)
+    check(g, async_search=-1, team_size=64)
+
+
+def test_batched_shuffled_rows():
+    graphs = [I.shuffle_rows(_random_graph(1400 + i), i) for i in range(8)]
+    graphs += [I.shuffle_rows(I.drop_diagonal(I.grid2d(30 + 4 * i, 25, seed=i)), i)
+               for i in range(4)]
+    graphs += [I.path(1), I.shuffle_rows(I.complete(6), 1)]
+    _check_batch(graphs)
+    _check_batch(graphs, small_cutoff=500, team_size=4, pp_variant=1)
+    _check_batch(graphs, small_cutoff=1 << 30, small_threads=256)
+
+
+# ---------------------------------------------------------------------------
+# rcm_order itself (the binding's order() goes through rcm_order_ex)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("which", ["grid64", "union", "grid128"])
+def test_rcm_order_entry_point(which):
+    import ctypes
+    import torch
+    from paper_1610_08128_amd import rcm
+
+    if which == "grid64":
+        g = I.config(0, seed=5)
+    elif which == "union":
+        g = I.shuffle_rows(_random_graph(1500), 3)
+    else:
+        g = I.config(1)
+    _say(f"rcm_order on {g.name} n={g.n}")
+    want = oracle.rcm(g.n, g.rowptr, g.colidx)
+    rp = torch.from_numpy(g.rowptr).cuda()
+    ci = torch.from_numpy(g.colidx).cuda()
+    perm = torch.full((g.n,), -1, dtype=torch.int32, device="cuda")
+    st = rcm.Stats()
+    stream = torch.cuda.current_stream().cuda_stream
+    status = rcm.lib().rcm_order(g.n, rp.data_ptr(), ci.data_ptr(), perm.data_ptr(),
+                                 ctypes.byref(st), stream)
+    assert status == rcm.OK, rcm.status_string(status)
+    assert np.array_equal(perm.cpu().numpy(), want.perm)
+    assert st.to_dict() == want.stats
+    # stats is nullable
+    status = rcm.lib().rcm_order(g.n, rp.data_ptr(), ci.data_ptr(), perm.data_ptr(), None, stream)
+    assert status == rcm.OK
+    assert np.array_equal(perm.cpu().numpy(), want.perm)
+
+
+# ---------------------------------------------------------------------------
+# Repeated columns are malformed on every path, rows of any length
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("row_len", [2, 7, 16, 17, 64, 65, 300])
+def test_duplicates_rejected_without_full_check(row_len):
+    """A column repeated within a row gives RCM_ERR_BAD_CSR whatever the row
+    length (register check up to 16 entries, re-read up to 64, a work-group
+    per row beyond), as the oracle's validation does."""
+    import torch
+    from paper_1610_08128_amd import rcm
+
+    g = I.shuffle_rows(I.disjoint_union([I.star(row_len + 1), I.grid2d(5, 7, seed=1)], seed=4),
+                       row_len)
+    lens = np.diff(g.rowptr)
+    r = int(np.nonzero(lens == row_len + 1)[0][0])  # the star's centre (diagonal included)
+    ci = g.colidx.copy()
+    a, b = int(g.rowptr[r]), int(g.rowptr[r + 1])
+    ci[b - 1] = ci[a]
+    assert oracle.validate(g.n, g.rowptr, ci) == oracle.ERR_BAD_CSR
+    _say(f"duplicate in a row of {b - a} entries")
+    for opts in ({}, {"small_cutoff": 1, "team_size": 4}, {"check_full": True}):
+        with pytest.raises(rcm.RcmError) as e:
+            rcm.order(torch.from_numpy(g.rowptr).cuda(), torch.from_numpy(ci).cuda(), **opts)
+        assert e.value.status == rcm.ERR_BAD_CSR, opts
+    graphs = [I.grid2d(4, 4, seed=2), g]
+    vo, no, rpc, cic = I.concat_batch(graphs)
+    cic = cic.copy()
+    cic[no[1] + a:no[1] + b] = ci[a:b]
+    with pytest.raises(rcm.RcmError) as e:
+        rcm.order_batched(vo, no, torch.from_numpy(rpc).cuda(), torch.from_numpy(cic).cuda())
+    assert e.value.status == rcm.ERR_BAD_CSR

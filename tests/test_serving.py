@@ -154,3 +154,38 @@ def test_concurrent_submitters_and_repeated_requests():
     _say(f"counters {c}")
     assert not errors, errors
     assert c["completed"] == 18
+
+
+def test_served_team_path_and_large_requests():
+    """Requests above the batched small-component cutoff (teams of
+    work-groups, cooperative launches from two executors' streams) and
+    requests of the serving workload's large end (at least 5M entries),
+    mixed with small ones; every result and its statistics equal the
+    oracle's for the same pattern alone."""
+    from paper_1610_08128_amd.serve import Server
+
+    big = [I.grid3d(100, 100, 100, seed=21),                 # 6.9M entries
+           I.shuffle_rows(I.grid2d(1100, 1000, seed=22), 3),  # 5.5M entries, rows shuffled
+           I.rgg_patches(420_000, 23)]                       # about 5.5M entries
+    team = [I.grid2d(300, 300, seed=24), I.grid3d(70, 70, 70, seed=25),
+            I.rgg_patches(90_000, 26), I.grid2d(400, 260, seed=27)]
+    small = _mixed_requests(15, 20)
+    graphs = []
+    for i in range(max(len(big), len(team), len(small))):
+        for lst in (small, team, big, small):
+            if i < len(lst):
+                graphs.append(lst[i])
+    assert any(g.nnz >= 5_000_000 for g in graphs)
+    assert sum(g.n > 65536 for g in graphs) >= 4
+    _say(f"serving {len(graphs)} requests, largest {max(g.nnz for g in graphs)} entries")
+    wants = [_expect(g) for g in graphs]
+    with Server(mem_budget_bytes=4 << 30, max_batch=8, executors=2) as srv:
+        tickets = [srv.submit(g.rowptr, g.colidx) for g in graphs]
+        for g, t, want in zip(graphs, tickets, wants):
+            perm, info = srv.wait(t, timeout_ms=120000)
+            assert info["status"] == 0, (g.name, info)
+            assert np.array_equal(perm, want.perm), g.name
+            assert info["stats"] == want.stats, (g.name, info["stats"], want.stats)
+        c = srv.counters()
+    _say(f"counters {c}")
+    assert c["completed"] == len(graphs) and c["failed"] == 0
