@@ -236,7 +236,7 @@ typedef struct {
   float team_label_ms;   /* device clock of that launch: labelled BFS */
   int32_t team_pp_levels;    /* levels expanded by the pseudo-peripheral passes */
   int32_t team_label_levels; /* levels of the labelled BFS */
-  int64_t phase_ticks[20];   /* diagnostics, 100 MHz device clock of work-group 0
+  int64_t phase_ticks[28];   /* diagnostics, 100 MHz device clock of work-group 0
                                 of the team launch: [0..3] wide unlabelled levels
                                 (expand, append, barrier ticks; level count);
                                 [4, 5] unlabelled levels of the LDS engine (ticks,
@@ -246,7 +246,11 @@ typedef struct {
                                 labelled levels: count phase, first barrier,
                                 placement, claims and second barrier; [16..19]
                                 unlabelled LDS engine levels: table clearing,
-                                expansion, reduction and barrier, bookkeeping  */
+                                expansion, reduction and barrier, bookkeeping;
+                                [20..25] asynchronous search passes: rounds,
+                                steps, records expanded and records skipped as
+                                superseded (work-group 0's), ticks in steps,
+                                ticks in round barriers; [26, 27] spare        */
 } rcm_timings;
 void rcm_last_timings(rcm_timings* out);
 

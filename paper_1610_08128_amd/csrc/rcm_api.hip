@@ -176,7 +176,7 @@ struct Timer {
   bool used[6] = {false, false, false, false, false, false};
   hipEvent_t kev[4];
   bool kused[2] = {false, false};
-  long long clk[24] = {};
+  long long clk[32] = {};
   explicit Timer(hipStream_t st) : s(st) {
     const char* e = std::getenv("RCM_TIMING");
     on = e && e[0] == '1';
@@ -218,7 +218,7 @@ struct Timer {
       t.team_label_ms = static_cast<float>(clk[1] * 1e-5);
       t.team_pp_levels = static_cast<int32_t>(clk[2]);
       t.team_label_levels = static_cast<int32_t>(clk[3]);
-      for (int i = 0; i < 20; ++i) t.phase_ticks[i] = clk[4 + i];
+      for (int i = 0; i < 28; ++i) t.phase_ticks[i] = clk[4 + i];
     }
     g_timings = t;
   }

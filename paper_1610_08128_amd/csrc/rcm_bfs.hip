@@ -186,10 +186,20 @@ __device__ __forceinline__ void drain_memory_ops() {
 // the largest, S.wspill the number of flags.  drain: every wave first
 // completes its own memory operations (whatever another work-group reads
 // after the barrier was written with atomics or device-scope stores, so no
-// L2 write-back is needed); acquire: invalidate this CU's caches afterwards
-// so that plain loads see other work-groups' data.
-__device__ __forceinline__ void slot_exchange(Team& t, Shared& S, uint32_t payload, bool drain,
-                                              bool acquire) {
+// L2 write-back is needed).
+//
+// No acquire fence follows: every load of data that other work-groups write
+// during the launch (records, claims, visited stamps, distance words,
+// control words) is a device-scope load, which on this GPU is served
+// coherently by the L2 and sees every store or atomic another work-group
+// completed before arriving (a probe saw no stale value in 20,000
+// cross-XCD hand-overs, where plain loads saw one every time, from the
+// CU's L1).  An agent-scope acquire would invalidate the CU's caches: it
+// costs 0.4 us alone and its cost grows with the number of CUs doing it at
+// once (1.7 us more per barrier for 256 work-groups), and afterwards even
+// read-only data (rows, vertex records) must come back from memory.  The
+// compiler barrier keeps the loads after the wait.
+__device__ __forceinline__ void slot_exchange(Team& t, Shared& S, uint32_t payload, bool drain) {
   if (drain) drain_memory_ops();
   __syncthreads();
   t.seq += 1;
@@ -261,10 +271,10 @@ __device__ __forceinline__ void slot_exchange(Team& t, Shared& S, uint32_t paylo
       S.wmax = mx;
       S.wspill = fl;
       S.flag = all_ok ? 0 : 1;
-      if (acquire && all_ok) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
   }
   __syncthreads();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
   t.aborted = S.flag != 0;
 }
 
@@ -286,7 +296,7 @@ __device__ __forceinline__ void team_barrier(Team& t, Shared& S, bool solo) {
     __syncthreads();
     return;
   }
-  slot_exchange(t, S, 0u, true, true);
+  slot_exchange(t, S, 0u, true);
 }
 
 // Narrow mode hand-over.  Work-group 0 publishes the pass state and wakes
@@ -365,9 +375,15 @@ __device__ __forceinline__ void st_rec(int4* p, int4 r) {
 
 // A frontier record as read back, clamped into the graph (vertex in [0, n),
 // 0 <= row begin <= row end <= nnz), so that no read can leave the arrays
-// whatever a position held.
+// whatever a position held.  The halves are read with device-scope loads,
+// which see another work-group's completed stores without a cache
+// invalidation (see slot_exchange).
 __device__ __forceinline__ int4 ld_rec(const BfsParams& P, int32_t pos) {
-  int4 r = P.qi[pos];
+  const unsigned long long* q = reinterpret_cast<const unsigned long long*>(P.qi + pos);
+  const unsigned long long lo = ld_relaxed(q);
+  const unsigned long long hi = ld_relaxed(q + 1);
+  int4 r = make_int4(static_cast<int32_t>(lo), static_cast<int32_t>(lo >> 32),
+                     static_cast<int32_t>(hi), static_cast<int32_t>(hi >> 32));
   r.x = min(max(r.x, 0), P.n - 1);
   r.z = min(max(r.z, 0), P.nnz);
   r.y = min(max(r.y, 0), r.z);
@@ -547,7 +563,7 @@ __device__ __forceinline__ bool lds_bfs_levels(const BfsParams& P, Team& t, Shar
         int32_t vs[kRB];
         int4 inf[kRB];
 #pragma unroll
-        for (int j = 0; j < kRB; ++j) vs[j] = P.visit[nb[j]];
+        for (int j = 0; j < kRB; ++j) vs[j] = ld_relaxed(&P.visit[nb[j]]);
 #pragma unroll
         for (int j = 0; j < kRB; ++j) inf[j] = P.vinfo[nb[j]];
 #pragma unroll
@@ -820,17 +836,13 @@ __device__ __forceinline__ void own_bfs_levels(const BfsParams& P, Team& t, Shar
       if (S.key != kMaxKey) atomicMin(minkey + (level + 1) % 3, S.key);
     }
     // the level's size travels with the arrival; a flag marks a spill to qi
-    slot_exchange(t, S, (spilled ? 0x80000000u : 0u) | static_cast<uint32_t>(my_new), false,
-                  false);
+    slot_exchange(t, S, (spilled ? 0x80000000u : 0u) | static_cast<uint32_t>(my_new), false);
     if (t.aborted) return;
     if (threadIdx.x == 0) {
       S.total = S.wtot;
       S.nspill = 0;
-      if (S.wspill != 0) {
-        // some work-group spilled: its records are in qi
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        S.nspill = ld_relaxed(tail + l3);
-      }
+      // some work-group spilled: its records are in qi
+      if (S.wspill != 0) S.nspill = ld_relaxed(tail + l3);
     }
     __syncthreads();
     const int32_t total = S.total;
@@ -864,7 +876,7 @@ __device__ __forceinline__ void own_bfs_levels(const BfsParams& P, Team& t, Shar
     if (total < P.narrow_cutoff) {
       // hand the frontier to the narrow levels: own records after the
       // spilled ones, in work-group order
-      slot_exchange(t, S, static_cast<uint32_t>(own_n), true, true);
+      slot_exchange(t, S, static_cast<uint32_t>(own_n), true);
       if (t.aborted) return;
       const int32_t prefix = S.wpre;
       for (int32_t i = threadIdx.x; i < own_n; i += B) {
@@ -1040,6 +1052,8 @@ __device__ __forceinline__ bool async_bfs_pass(const BfsParams& P, Team& t, Shar
   int32_t g_b = 0, g_e = 1;  // the frontier: virtual ring indices [g_b, g_e)
   int32_t rounds = 0;
   bool overflow = false;
+  // diagnostics (work-group 0): steps, records expanded / skipped, ticks
+  long long d_steps = 0, d_exp = 0, d_sup = 0, d_tstep = 0, d_tbar = 0;
   while (true) {
     const int l3 = rounds % 3;
     int32_t lo, hi;
@@ -1052,9 +1066,11 @@ __device__ __forceinline__ bool async_bfs_pass(const BfsParams& P, Team& t, Shar
       S.spill = 0;
       S.ovf = 0;
     }
+    const long long r0 = wall_clock64();
     for (int step = 0; step < P.search_round; ++step) {
       if (threadIdx.x == 0) S.cnt = 0;
       __syncthreads();
+      ++d_steps;
       for (int32_t i = threadIdx.x; i < n_glob + own_n; i += B) {
         int4 e;
         if (i < n_glob) {
@@ -1071,6 +1087,7 @@ __device__ __forceinline__ bool async_bfs_pass(const BfsParams& P, Team& t, Shar
         const unsigned long long cur =
             __hip_atomic_load(&P.dkey[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const unsigned long long want = dist_key(tag, du + 1);
+        if (cur == dist_key(tag, du)) ++d_exp; else ++d_sup;
         for (int32_t k0 = e.y; k0 < e.z; k0 += kRB) {
           int32_t nb[kRB];
           load_batch(P.colidx, k0, e.z, u, nb);
@@ -1117,6 +1134,8 @@ __device__ __forceinline__ bool async_bfs_pass(const BfsParams& P, Team& t, Shar
       n_glob = 0;
       if (own_n == 0) break;
     }
+    const long long r1 = wall_clock64();
+    d_tstep += r1 - r0;
     // the rest of this work-group's records go to the next round's frontier
     if (threadIdx.x == 0) {
       S.base = own_n > 0 ? atomicAdd(tail + l3, own_n) : 0;
@@ -1146,14 +1165,11 @@ __device__ __forceinline__ bool async_bfs_pass(const BfsParams& P, Team& t, Shar
       drain_memory_ops();
     }
     // payload: a flag for records written, a count of 1 for an overflow
-    slot_exchange(t, S, (wrote ? 0x80000000u : 0u) | (S.ovf ? 1u : 0u), false, false);
+    slot_exchange(t, S, (wrote ? 0x80000000u : 0u) | (S.ovf ? 1u : 0u), false);
     if (t.aborted) return true;
     if (threadIdx.x == 0) {
       S.nspill = 0;
-      if (S.wspill != 0) {
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        S.nspill = ld_relaxed(tail + l3);
-      }
+      if (S.wspill != 0) S.nspill = ld_relaxed(tail + l3);
       S.total = S.wtot;
     }
     __syncthreads();
@@ -1163,6 +1179,7 @@ __device__ __forceinline__ bool async_bfs_pass(const BfsParams& P, Team& t, Shar
     }
     const int32_t total = S.nspill;
     ++rounds;
+    d_tbar += wall_clock64() - r1;
     if (total == 0) break;
     g_b = g_e;
     g_e += total;
@@ -1182,7 +1199,7 @@ __device__ __forceinline__ bool async_bfs_pass(const BfsParams& P, Team& t, Shar
   uint64_t my_key = kMaxKey;
   long long my_m = 0;
   for (int32_t v = seg_b + t.wid * B + threadIdx.x; v < seg_e; v += t.W * B) {
-    const unsigned long long kv = P.dkey[v];
+    const unsigned long long kv = ld_relaxed(&P.dkey[v]);
     if (static_cast<uint32_t>(kv >> 32) != tag) continue;
     const int32_t d = static_cast<int32_t>(0xFFFFFFFFu - static_cast<uint32_t>(kv));
     ++my_cnt;
@@ -1239,9 +1256,18 @@ __device__ __forceinline__ bool async_bfs_pass(const BfsParams& P, Team& t, Shar
     t.aborted = true;
     return true;
   }
+  // records counted per thread: sum them over the work-group
+  d_exp = block_sum_i64(d_exp, S.red);
+  d_sup = block_sum_i64(d_sup, S.red);
   if (t.wid == 0 && threadIdx.x == 0) {
     t.ctl->clk[0] += wall_clock64() - clk0;
     t.ctl->clk[2] += ecc + 1;
+    t.ctl->clk[24] += rounds;
+    t.ctl->clk[25] += d_steps;
+    t.ctl->clk[26] += d_exp;
+    t.ctl->clk[27] += d_sup;
+    t.ctl->clk[28] += d_tstep;
+    t.ctl->clk[29] += d_tbar;
   }
   return true;
 }
@@ -1298,7 +1324,7 @@ __device__ __forceinline__ void place_long_row(const BfsParams& P, Shared& S, in
     uint32_t cl[kRB];
     int32_t dg[kRB];
 #pragma unroll
-    for (int j = 0; j < kRB; ++j) cl[j] = P.claim[nb[j]];
+    for (int j = 0; j < kRB; ++j) cl[j] = ld_relaxed(&P.claim[nb[j]]);
 #pragma unroll
     for (int j = 0; j < kRB; ++j) dg[j] = P.vinfo[nb[j]].z;
 #pragma unroll
@@ -1334,7 +1360,7 @@ __device__ __forceinline__ void place_long_row(const BfsParams& P, Shared& S, in
     load_batch(P.colidx, k0, b, u, nb);
     uint32_t cl[kRB];
 #pragma unroll
-    for (int j = 0; j < kRB; ++j) cl[j] = P.claim[nb[j]];
+    for (int j = 0; j < kRB; ++j) cl[j] = ld_relaxed(&P.claim[nb[j]]);
 #pragma unroll
     for (int j = 0; j < kRB; ++j) {
       if (!(nb[j] != u && cl[j] == pl)) continue;
@@ -1347,7 +1373,7 @@ __device__ __forceinline__ void place_long_row(const BfsParams& P, Shared& S, in
         uint32_t cw[kRB];
         int32_t dw[kRB];
 #pragma unroll
-        for (int i = 0; i < kRB; ++i) cw[i] = P.claim[w[i]];
+        for (int i = 0; i < kRB; ++i) cw[i] = ld_relaxed(&P.claim[w[i]]);
 #pragma unroll
         for (int i = 0; i < kRB; ++i) dw[i] = P.vinfo[w[i]].z;
 #pragma unroll
@@ -1372,7 +1398,7 @@ __device__ __forceinline__ int count_long_row(const BfsParams& P, int32_t p, int
     load_batch(P.colidx, k0, b, u, nb);
     uint32_t cl[kRB];
 #pragma unroll
-    for (int j = 0; j < kRB; ++j) cl[j] = P.claim[nb[j]];
+    for (int j = 0; j < kRB; ++j) cl[j] = ld_relaxed(&P.claim[nb[j]]);
 #pragma unroll
     for (int j = 0; j < kRB; ++j) c += (nb[j] != u && cl[j] == pl) ? 1 : 0;
   }
@@ -1447,7 +1473,7 @@ __device__ __forceinline__ bool lds_label_levels(const BfsParams& P, Team& t, Sh
         load_batch(P.colidx, e.y, e.z, e.x, nb);
         uint32_t cl[kRB];
 #pragma unroll
-        for (int j = 0; j < kRB; ++j) cl[j] = P.claim[nb[j]];
+        for (int j = 0; j < kRB; ++j) cl[j] = ld_relaxed(&P.claim[nb[j]]);
 #pragma unroll
         for (int j = 0; j < kRB; ++j) inf[j] = P.vinfo[nb[j]];
 #pragma unroll
@@ -1589,7 +1615,7 @@ __device__ __forceinline__ void global_label_level(const BfsParams& P, Team& t, 
         }
         uint32_t cl[kRB];
 #pragma unroll
-        for (int j = 0; j < kRB; ++j) cl[j] = P.claim[cnb[j]];
+        for (int j = 0; j < kRB; ++j) cl[j] = ld_relaxed(&P.claim[cnb[j]]);
 #pragma unroll
         for (int j = 0; j < kRB; ++j) cinf[j] = P.vinfo[cnb[j]];
 #pragma unroll
@@ -1611,7 +1637,7 @@ __device__ __forceinline__ void global_label_level(const BfsParams& P, Team& t, 
   if (solo) {
     local_counts(S, static_cast<int32_t>(tot));
   } else {
-    slot_exchange(t, S, static_cast<uint32_t>(tot), false, false);
+    slot_exchange(t, S, static_cast<uint32_t>(tot), false);
   }
   if (t.aborted) return;
   const long long t2 = wall_clock64();
@@ -2036,18 +2062,17 @@ __device__ __forceinline__ void order_main(const BfsParams& P) {
   }
 }
 
-// One instance per work-group size, so that the compiler sizes registers for
-// it: with 256 threads a wave may hold twice the registers of a 512-thread
-// work-group's.
-template <int kThreads>
-__global__ void __launch_bounds__(kThreads) k_order(BfsParams P) {
+// One instance for both work-group sizes (256 and 512 threads).  An
+// instance bounded at 256 threads gets twice the registers and compiles
+// without any scratch spill, but it measured slower on the 128^3 grid
+// (k_order 8.8 against 8.2 ms, the search passes 3.4 against 2.9 ms): its
+// extra registers go to accumulator-register copies, and the spills of the
+// 512-thread bound sit outside the level loops' load chains.
+__global__ void __launch_bounds__(512) k_order(BfsParams P) {
   order_main(P);
 }
 
-const void* order_kernel(int32_t threads) {
-  return threads > 256 ? reinterpret_cast<const void*>(k_order<512>)
-                       : reinterpret_cast<const void*>(k_order<256>);
-}
+const void* order_kernel(int32_t) { return reinterpret_cast<const void*>(k_order); }
 
 // Cooperative launches of this library in one process never overlap: each
 // is sized to what the device holds at once, and two of them resident side
@@ -2083,11 +2108,7 @@ hipError_t launch_order(const BfsParams& p, int32_t blocks, int32_t threads, hip
     if (e != hipSuccess) return e;
     return hipStreamSynchronize(s);
   }
-  if (threads > 256) {
-    k_order<512><<<blocks, threads, 0, s>>>(q);
-  } else {
-    k_order<256><<<blocks, threads, 0, s>>>(q);
-  }
+  k_order<<<blocks, threads, 0, s>>>(q);
   return hipGetLastError();
 }
 

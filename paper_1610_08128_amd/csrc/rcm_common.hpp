@@ -63,9 +63,9 @@ struct alignas(128) TeamCtl {
   unsigned long long lastkey;    // min (deg << 32 | id) over the last level of a
                                  // labelled pass that also serves the search
   int32_t task;                  // large-component task handed to the team
-  long long clk[24];             // work-group 0's clock (diagnostics): [0] pp ticks,
+  long long clk[32];             // work-group 0's clock (diagnostics): [0] pp ticks,
                                  // [1] labelled ticks, [2] pp levels, [3] labelled
-                                 // levels, [4..23] per-phase ticks
+                                 // levels, [4..31] per-phase ticks and counts
 
 };
 

@@ -96,7 +96,7 @@ class Timings(ctypes.Structure):
         ("team_label_ms", ctypes.c_float),
         ("team_pp_levels", ctypes.c_int32),
         ("team_label_levels", ctypes.c_int32),
-        ("phase_ticks", ctypes.c_int64 * 20),
+        ("phase_ticks", ctypes.c_int64 * 28),
     ]
 
 
