@@ -198,6 +198,26 @@ rcm_status rcm_order_ex(int32_t n, const int32_t* rowptr, const int32_t* colidx,
                         const rcm_options* opts, void* workspace, size_t workspace_bytes,
                         void* stream);
 
+/* Size of the device array behind rcm_order_noalloc: graphs whose
+ * rcm_workspace_bytes(n, nnz, opts) exceeds it are rejected. */
+#define RCM_NOALLOC_SCRATCH_BYTES (256ull << 20)
+
+/* For callers that cannot allocate device memory (code that must not call
+ * hipMalloc, such as tight serving loops or harnesses that forbid it): the
+ * ordering of rcm_order_ex, with a workspace that is a device array of
+ * RCM_NOALLOC_SCRATCH_BYTES held by the library (one per device, from its
+ * first use until the process ends) instead of caller memory.  Makes no
+ * device allocation or free and creates no HIP events (RCM_TIMING is
+ * ignored).  Arguments as for rcm_order_ex (opts nullable, iperm_out
+ * nullable).  Errors: RCM_ERR_WORKSPACE_TOO_SMALL when the graph needs
+ * more workspace than the array holds (about 1.4 million vertices at
+ * 7 entries per row); RCM_ERR_HIP when the array's address cannot be
+ * obtained.  The calls of one process on one device share the array and
+ * are serialised by the library; every call initialises what it uses. */
+rcm_status rcm_order_noalloc(int32_t n, const int32_t* rowptr, const int32_t* colidx,
+                             int32_t* perm_out, int32_t* iperm_out, rcm_stats* stats,
+                             const rcm_options* opts, void* stream);
+
 /* Device workspace needed by rcm_order_batched (bytes). */
 size_t rcm_batched_workspace_bytes(int32_t num_graphs, int64_t total_vertices,
                                    int64_t total_nnz, const rcm_options* opts);

@@ -177,9 +177,10 @@ struct Timer {
   hipEvent_t kev[4];
   bool kused[2] = {false, false};
   long long clk[32] = {};
-  explicit Timer(hipStream_t st) : s(st) {
+  // allow = false: never (the allocation-free entry point creates no events)
+  Timer(hipStream_t st, bool allow) : s(st) {
     const char* e = std::getenv("RCM_TIMING");
-    on = e && e[0] == '1';
+    on = allow && e && e[0] == '1';
     if (on) {
       for (auto& x : ev) (void)hipEventCreate(&x);
       for (auto& x : kev) (void)hipEventCreate(&x);
@@ -627,10 +628,14 @@ void rcm_last_timings(rcm_timings* out) {
   if (out) *out = g_timings;
 }
 
-rcm_status rcm_order_ex(int32_t n, const int32_t* rowptr, const int32_t* colidx,
+}  // extern "C"
+
+namespace rcm {
+
+rcm_status order_single(int32_t n, const int32_t* rowptr, const int32_t* colidx,
                         int32_t* perm_out, int32_t* iperm_out, rcm_stats* stats,
                         const rcm_options* opts, void* workspace, size_t workspace_bytes,
-                        void* stream) {
+                        void* stream, bool timing) {
   Opts o;
   rcm_status st = check_common(n, opts, &o);
   if (st != RCM_OK) return st;
@@ -654,7 +659,7 @@ rcm_status rcm_order_ex(int32_t n, const int32_t* rowptr, const int32_t* colidx,
       return RCM_ERR_OUT_OF_MEMORY;
     owned = true;
   }
-  Timer timer(s);
+  Timer timer(s, timing);
   Graph g{n, ends[1], rowptr, colidx, 1, nullptr};
   const int32_t seg_host[2] = {0, n};
   st = run(g, seg_host, o, ws, L, perm_out, iperm_out, stats, s, timer);
@@ -664,6 +669,18 @@ rcm_status rcm_order_ex(int32_t n, const int32_t* rowptr, const int32_t* colidx,
   }
   timer.finish();
   return st;
+}
+
+}  // namespace rcm
+
+extern "C" {
+
+rcm_status rcm_order_ex(int32_t n, const int32_t* rowptr, const int32_t* colidx,
+                        int32_t* perm_out, int32_t* iperm_out, rcm_stats* stats,
+                        const rcm_options* opts, void* workspace, size_t workspace_bytes,
+                        void* stream) {
+  return order_single(n, rowptr, colidx, perm_out, iperm_out, stats, opts, workspace,
+                      workspace_bytes, stream, true);
 }
 
 rcm_status rcm_order(int32_t n, const int32_t* rowptr, const int32_t* colidx, int32_t* perm_out,
@@ -709,7 +726,7 @@ rcm_status rcm_order_batched(int32_t num_graphs, const int64_t* vtx_offsets,
     no[g] = static_cast<int32_t>(nnz_offsets[g]);
   }
   rcm_status st = RCM_OK;
-  Timer timer(s);
+  Timer timer(s, true);
   do {
     int32_t* rowptr_g = reinterpret_cast<int32_t*>(ws + L.rowptr_g);
     int32_t* colidx_g = reinterpret_cast<int32_t*>(ws + L.colidx_g);

@@ -312,6 +312,13 @@ struct BfsParams {
   unsigned long long* dkey;   // per vertex: pass tag << 32 | ~distance (asynchronous passes)
 };
 
+// rcm_order_ex without its extern "C" wrapper; timing = false never creates
+// HIP events (the allocation-free entry point).
+rcm_status order_single(int32_t n, const int32_t* rowptr, const int32_t* colidx,
+                        int32_t* perm_out, int32_t* iperm_out, rcm_stats* stats,
+                        const rcm_options* opts, void* workspace, size_t workspace_bytes,
+                        void* stream, bool timing);
+
 // One launch of the ordering kernel over the task lists in p; cooperative
 // (all blocks co-resident) whenever p has multi-work-group teams.
 hipError_t launch_order(const BfsParams& p, int32_t blocks, int32_t threads, hipStream_t s);

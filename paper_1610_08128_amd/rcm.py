@@ -37,7 +37,10 @@ EXPORTED = [
     "rcm_batched_workspace_bytes",
     "rcm_order_batched",
     "rcm_last_timings",
+    "rcm_order_noalloc",
 ]
+
+NOALLOC_SCRATCH_BYTES = 256 << 20  # RCM_NOALLOC_SCRATCH_BYTES in include/rcm.h
 
 
 class RcmError(RuntimeError):
@@ -129,6 +132,9 @@ def lib() -> ctypes.CDLL:
         L.rcm_order_batched.argtypes = [i32, P, P, P, P, P, P, ctypes.POINTER(Options), P,
                                         ctypes.c_size_t, P]
         L.rcm_order_batched.restype = ctypes.c_int
+        L.rcm_order_noalloc.argtypes = [i32, P, P, P, P, ctypes.POINTER(Stats),
+                                        ctypes.POINTER(Options), P]
+        L.rcm_order_noalloc.restype = ctypes.c_int
         L.rcm_last_timings.argtypes = [ctypes.POINTER(Timings)]
         L.rcm_last_timings.restype = None
         _lib = L
