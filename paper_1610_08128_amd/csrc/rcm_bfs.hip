@@ -1094,6 +1094,10 @@ __device__ __forceinline__ bool async_bfs_pass(const BfsParams& P, Team& t, Shar
           if (cur != dist_key(tag, du)) break;
           int4 inf[kRB];
           unsigned long long old[kRB];
+          // the records are gathered alongside the atomics: reading the
+          // words first to spare the atomics of edges into vertices already
+          // as close adds a dependent round trip per step, which measured
+          // slower (3.5 -> 5.6 us per step on the 128^3 grid)
 #pragma unroll
           for (int j = 0; j < kRB; ++j) inf[j] = P.vinfo[nb[j]];
           // past-the-row lanes and self loops hit u, whose word beats want
@@ -1280,13 +1284,26 @@ __device__ __forceinline__ bool async_bfs_pass(const BfsParams& P, Team& t, Shar
 // label becomes a claim on every neighbour.  Lanes past the row end and
 // already labelled neighbours hold smaller claims, so the min leaves them
 // alone (the Select(R == -1) step).  Fire-and-forget atomics.
+__device__ __forceinline__ void claim_batch(const BfsParams& P, const int32_t* nb,
+                                            uint32_t label) {
+  // claims only decrease, so a neighbour whose claim is already at most
+  // `label` (every labelled vertex, and every vertex a smaller label has
+  // claimed) needs no atomic: reading the claims first trades random
+  // atomics for random loads, which the chip does about twice as fast
+  uint32_t cl[kRB];
+#pragma unroll
+  for (int j = 0; j < kRB; ++j) cl[j] = ld_relaxed(&P.claim[nb[j]]);
+#pragma unroll
+  for (int j = 0; j < kRB; ++j)
+    if (cl[j] > label) atomicMin(&P.claim[nb[j]], label);
+}
+
 __device__ __forceinline__ void claim_row(const BfsParams& P, int32_t v, int4 info,
                                           uint32_t label) {
   for (int32_t k0 = info.x; k0 < info.y; k0 += kRB) {
     int32_t nb[kRB];
     load_batch(P.colidx, k0, info.y, v, nb);
-#pragma unroll
-    for (int j = 0; j < kRB; ++j) atomicMin(&P.claim[nb[j]], label);
+    claim_batch(P, nb, label);
   }
 }
 
@@ -1699,8 +1716,7 @@ __device__ __forceinline__ void global_label_level(const BfsParams& P, Team& t, 
       int32_t nb[kRB];
       if (c.z > c.y) {
         load_batch(P.colidx, c.y, c.z, c.x, nb);
-#pragma unroll
-        for (int j = 0; j < kRB; ++j) atomicMin(&P.claim[nb[j]], static_cast<uint32_t>(c.w));
+        claim_batch(P, nb, static_cast<uint32_t>(c.w));
       } else {
 #pragma unroll
         for (int j = 0; j < kRB; ++j) nb[j] = c.x;
