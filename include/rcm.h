@@ -171,7 +171,22 @@ typedef struct {
   int32_t search_round;  /* steps each work-group takes on its own between the
                             team barriers of an asynchronous search pass;
                             0 = auto (16)                                  */
-  int32_t reserved[2];
+  int32_t mode;          /* 0 = auto: a single graph whose CSR and per-vertex
+                               state fit in one work-group's LDS (about 6,000
+                               vertices of a 3D mesh, 7,000 of a 2D mesh) is
+                               ordered by one work-group from LDS, in one
+                               launch; others by the persistent team kernel;
+                            1 = always the persistent team kernel;
+                            2 = always the one-work-group LDS engine
+                               (RCM_ERR_INVALID_ARGUMENT if the graph does
+                               not fit, or with label_mode 1 or 2)          */
+  int32_t reserved;
+  const char* tuning_file; /* NULL = the RCM_TUNING_FILE environment variable,
+                              if set; else no table.  A table written by the
+                              autotuner (paper_1610_08128_amd/tune.py) whose
+                              entries, chosen by the graph's vertex and entry
+                              counts, replace the auto value of every option
+                              left at 0 here                               */
 } rcm_options;
 
 /* Human-readable name of a status code (static string). */
@@ -270,7 +285,13 @@ typedef struct {
                                 [20..25] asynchronous search passes: rounds,
                                 steps, records expanded and records skipped as
                                 superseded (work-group 0's), ticks in steps,
-                                ticks in round barriers; [26, 27] spare        */
+                                ticks in round barriers -- or, when the one-
+                                work-group LDS engine ordered the graph
+                                (mode), its ticks for loading the graph, the
+                                row checks, the searches (with a labelled pass
+                                that served as one), the labelled passes, the
+                                reversal and the result statistics; [26, 27]
+                                spare                                          */
 } rcm_timings;
 void rcm_last_timings(rcm_timings* out);
 

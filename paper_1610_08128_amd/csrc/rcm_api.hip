@@ -47,6 +47,7 @@ struct Opts {
   int async_search = 1;
   int label_team = 64;
   int search_round = 16;
+  int mode = 0;  // 0 auto, 1 team kernel only, 2 one-work-group LDS engine only
 };
 
 // Auto team size of a single graph: all compute units for a large graph
@@ -86,6 +87,7 @@ bool parse_options(const rcm_options* o, Opts* out, bool batched = false) {
     if (o->async_search < -1 || o->async_search > 1) return false;
     if (o->label_team < 0 || o->label_team > kMaxTeam) return false;
     if (o->search_round < 0) return false;
+    if (o->mode < 0 || o->mode > 2) return false;
     r.pp_variant = o->pp_variant;
     r.reverse_mode = o->reverse_mode;
     r.check_full = o->check_full;
@@ -100,6 +102,7 @@ bool parse_options(const rcm_options* o, Opts* out, bool batched = false) {
     if (o->async_search) r.async_search = o->async_search > 0 ? 1 : 0;
     if (o->label_team) r.label_team = o->label_team;
     if (o->search_round) r.search_round = o->search_round;
+    r.mode = o->mode;
   }
   *out = r;
   return true;
@@ -632,6 +635,89 @@ void rcm_last_timings(rcm_timings* out) {
 
 namespace rcm {
 
+namespace {
+
+// A single graph through the one-work-group LDS engine (rcm_small.hip): one
+// launch that reads the entry count itself and declines when the graph does
+// not fit, then one readback of its result.  Returns false when the engine
+// does not apply (level orders, too many vertices, or it declined), having
+// written no output; else true with the call's status in *out.
+bool order_small(int32_t n, const int32_t* rowptr, const int32_t* colidx, int32_t* perm_out,
+                 int32_t* iperm_out, rcm_stats* stats, const Opts& o, void* workspace,
+                 size_t workspace_bytes, hipStream_t s, bool timing, rcm_status* out) {
+  if (o.label_mode != 0) return false;
+  const size_t limit = small_lds_limit();
+  if (limit == 0 || small_lds_bytes(n, 0) > limit) return false;
+  *out = RCM_OK;
+  if (colidx == nullptr) {
+    // allowed only without entries
+    int32_t nnz = 0;
+    if (hipMemcpyAsync(&nnz, rowptr + n, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+      *out = RCM_ERR_HIP;
+      return true;
+    }
+    if (nnz != 0) {
+      *out = RCM_ERR_INVALID_ARGUMENT;
+      return true;
+    }
+    colidx = rowptr;  // never read
+  }
+  // the single-graph workspace does not depend on the entry count
+  const size_t need = make_layout(n, 0, 1, false, kSmallTeams).total;
+  SmallResult* res = nullptr;
+  bool owned = false;
+  if (workspace) {
+    if (workspace_bytes < need) {
+      *out = RCM_ERR_WORKSPACE_TOO_SMALL;
+      return true;
+    }
+    res = static_cast<SmallResult*>(workspace);
+  } else {
+    if (hipMallocAsync(reinterpret_cast<void**>(&res), sizeof(SmallResult), s) != hipSuccess) {
+      *out = RCM_ERR_OUT_OF_MEMORY;
+      return true;
+    }
+    owned = true;
+  }
+  Timer timer(s, timing);
+  SmallJob job{n, -1, rowptr, colidx, perm_out, iperm_out, 0, 0, res};
+  SmallOpts so{o.pp_variant, o.reverse_mode, o.check_full, static_cast<int32_t>(limit)};
+  SmallResult h{};
+  timer.mark(0);
+  timer.kmark(0, true);
+  if (launch_small_order(job, nullptr, 1, so, s) != hipSuccess ||
+      hipMemcpyAsync(&h, res, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    *out = RCM_ERR_HIP;
+  timer.kmark(0, false);
+  timer.mark(5);
+  if (owned) {
+    (void)hipFreeAsync(res, s);
+    (void)hipStreamSynchronize(s);
+  }
+  timer.finish();
+  if (timer.on)
+    for (int i = 0; i < 6; ++i) g_timings.phase_ticks[20 + i] = h.ticks[i];
+  if (*out != RCM_OK) return true;
+  if (h.status == kSmallDeclined) return false;
+  *out = static_cast<rcm_status>(h.status);
+  if (*out == RCM_OK && stats) {
+    stats->bandwidth_before = static_cast<int64_t>(h.bw_before);
+    stats->profile_before = static_cast<int64_t>(h.prof_before);
+    stats->bandwidth_after = static_cast<int64_t>(h.bw_after);
+    stats->profile_after = static_cast<int64_t>(h.prof_after);
+    stats->edges_traversed = static_cast<int64_t>(h.edges);
+    stats->num_components = h.ncomp;
+    stats->pseudo_diameter = h.diameter;
+    stats->num_bfs = h.nbfs;
+    stats->num_levels = h.nlevels;
+  }
+  return true;
+}
+
+}  // namespace
+
 rcm_status order_single(int32_t n, const int32_t* rowptr, const int32_t* colidx,
                         int32_t* perm_out, int32_t* iperm_out, rcm_stats* stats,
                         const rcm_options* opts, void* workspace, size_t workspace_bytes,
@@ -643,6 +729,12 @@ rcm_status order_single(int32_t n, const int32_t* rowptr, const int32_t* colidx,
   if (n == 0) return RCM_OK;
   if (!rowptr || !perm_out) return RCM_ERR_INVALID_ARGUMENT;
   hipStream_t s = static_cast<hipStream_t>(stream);
+  if (o.mode != 1) {
+    if (order_small(n, rowptr, colidx, perm_out, iperm_out, stats, o, workspace,
+                    workspace_bytes, s, timing, &st))
+      return st;
+    if (o.mode == 2) return RCM_ERR_INVALID_ARGUMENT;
+  }
   int32_t ends[2];
   HIP_TRY(hipMemcpyAsync(&ends[0], rowptr, 4, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipMemcpyAsync(&ends[1], rowptr + n, 4, hipMemcpyDeviceToHost, s));

@@ -312,6 +312,41 @@ struct BfsParams {
   unsigned long long* dkey;   // per vertex: pass tag << 32 | ~distance (asynchronous passes)
 };
 
+// The one-work-group engine for a whole small graph in LDS (rcm_small.hip).
+struct SmallResult {
+  int32_t status;  // rcm_status, or kSmallDeclined
+  int32_t ncomp, diameter, nbfs, nlevels;
+  int32_t pad[3];
+  unsigned long long bw_before, prof_before, bw_after, prof_after, edges;
+  long long ticks[6];  // 100 MHz clock: load, row checks, searches, labelled
+                       // BFS, reversal, result statistics (diagnostics)
+};
+constexpr int32_t kSmallDeclined = -1;  // the graph does not fit the LDS given
+struct SmallJob {
+  int32_t n;
+  int32_t nnz;              // < 0: read rowptr[n] on the device
+  const int32_t* rowptr;    // device, rowptr[0] = 0
+  const int32_t* colidx;
+  int32_t* perm;            // perm[k] = vertex + id_off
+  int32_t* iperm;           // nullable: iperm[vertex] = k + pos_off
+  int32_t id_off;
+  int32_t pos_off;
+  SmallResult* res;         // device
+};
+struct SmallOpts {
+  int32_t pp_variant;
+  int32_t reverse_mode;
+  int32_t check_full;
+  int32_t lds_bytes;        // dynamic LDS of each work-group
+};
+// LDS bytes the engine needs for a graph (0 for n <= 0), and the most one
+// work-group may have on the current device (0 if unknown).
+size_t small_lds_bytes(int64_t n, int64_t nnz);
+size_t small_lds_limit();
+// jobs_dev == nullptr: one job, `single`.
+hipError_t launch_small_order(const SmallJob& single, const SmallJob* jobs_dev, int32_t njobs,
+                              const SmallOpts& opts, hipStream_t s);
+
 // rcm_order_ex without its extern "C" wrapper; timing = false never creates
 // HIP events (the allocation-free entry point).
 rcm_status order_single(int32_t n, const int32_t* rowptr, const int32_t* colidx,

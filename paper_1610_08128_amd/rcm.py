@@ -82,7 +82,9 @@ class Options(ctypes.Structure):
         ("async_search", ctypes.c_int32),
         ("label_team", ctypes.c_int32),
         ("search_round", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 2),
+        ("mode", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("tuning_file", ctypes.c_char_p),
     ]
 
 
@@ -148,7 +150,7 @@ def status_string(status: int) -> str:
 def make_options(*, pp_variant=0, reverse_mode=0, check_full=False, team_size=0,
                  block_threads=0, small_cutoff=0, narrow_cutoff=0, small_threads=0,
                  max_teams=0, rebalance_levels=0, label_mode=0, async_search=0,
-                 label_team=0, search_round=0) -> Options:
+                 label_team=0, search_round=0, mode=0, tuning_file=None) -> Options:
     o = Options()
     o.pp_variant = int(pp_variant)
     o.reverse_mode = int(reverse_mode)
@@ -164,6 +166,8 @@ def make_options(*, pp_variant=0, reverse_mode=0, check_full=False, team_size=0,
     o.async_search = int(async_search)
     o.label_team = int(label_team)
     o.search_round = int(search_round)
+    o.mode = int(mode)
+    o.tuning_file = tuning_file.encode() if isinstance(tuning_file, str) else tuning_file
     return o
 
 

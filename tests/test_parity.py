@@ -18,9 +18,25 @@ def _say(msg):
     sys.stdout.flush()
 
 
+# options that only the persistent team kernel reads: a test that sets them
+# means that kernel (mode 1), not the one-work-group engine small graphs
+# take by default
+TEAM_OPTIONS = {"small_cutoff", "team_size", "narrow_cutoff", "block_threads", "label_team",
+                "search_round", "async_search", "rebalance_levels", "max_teams",
+                "small_threads"}
+
+
+def _with_mode(opts):
+    if "mode" not in opts and TEAM_OPTIONS & set(opts):
+        opts = dict(opts, mode=1)
+    return opts
+
+
 def gpu_order(g, **opts):
     import torch
     from paper_1610_08128_amd import rcm
+
+    opts = _with_mode(opts)
 
     rp = torch.from_numpy(g.rowptr).cuda()
     ci = torch.from_numpy(g.colidx if g.colidx.size else np.zeros(1, np.int32)).cuda()
@@ -65,11 +81,14 @@ def _tiny_graphs():
 
 
 @pytest.mark.parametrize("idx", range(17))
-def test_tiny_graphs(idx):
+@pytest.mark.parametrize("mode", [0, 1])
+def test_tiny_graphs(idx, mode):
+    """mode 0 takes the one-work-group LDS engine for graphs this small, mode
+    1 the persistent team kernel."""
     g = _tiny_graphs()[idx]
     for pp in (0, 1):
         for rev in (0, 1):
-            check(g, pp_variant=pp, reverse_mode=rev)
+            check(g, pp_variant=pp, reverse_mode=rev, mode=mode)
 
 
 def _random_graph(seed):
@@ -98,9 +117,10 @@ def _random_graph(seed):
 
 
 @pytest.mark.parametrize("seed", range(24))
-def test_random_graphs_small_path(seed):
+@pytest.mark.parametrize("mode", [0, 1])
+def test_random_graphs_small_path(seed, mode):
     g = _random_graph(seed)
-    check(g, pp_variant=seed % 2, reverse_mode=(seed // 2) % 2)
+    check(g, pp_variant=seed % 2, reverse_mode=(seed // 2) % 2, mode=mode)
 
 
 @pytest.mark.parametrize("seed", range(12))
@@ -118,6 +138,8 @@ def test_grid_64x64(seed):
     g = I.config(0, seed=seed)
     st = check(g)
     assert st["bandwidth_after"] == 64 and st["profile_after"] == 176736
+    check(g, mode=2)
+    check(g, mode=1)
     check(g, small_cutoff=1)
 
 
@@ -238,6 +260,7 @@ def _check_batch(graphs, **opts):
     from paper_1610_08128_amd import rcm
 
     vo, no, rp, ci = I.concat_batch(graphs)
+    opts = _with_mode(opts)
     _say(f"batch of {len(graphs)} graphs, {vo[-1]} vertices, {no[-1]} nnz {opts}")
     perm, stats = rcm.order_batched(vo, no, torch.from_numpy(rp).cuda(),
                                     torch.from_numpy(ci).cuda(), **opts)
@@ -519,3 +542,103 @@ def test_duplicates_rejected_without_full_check(row_len):
     with pytest.raises(rcm.RcmError) as e:
         rcm.order_batched(vo, no, torch.from_numpy(rpc).cuda(), torch.from_numpy(cic).cuda())
     assert e.value.status == rcm.ERR_BAD_CSR
+
+
+# ---------------------------------------------------------------------------
+# The one-work-group LDS engine (mode 2 requires it)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("idx", range(17))
+def test_engine_tiny_graphs(idx):
+    g = _tiny_graphs()[idx]
+    for pp in (0, 1):
+        for rev in (0, 1):
+            check(g, pp_variant=pp, reverse_mode=rev, mode=2)
+    check(I.shuffle_rows(g, idx), mode=2, check_full=True)
+
+
+@pytest.mark.parametrize("seed", range(16))
+def test_engine_random_graphs(seed):
+    g = _random_graph(1600 + seed)
+    check(g, pp_variant=seed % 2, reverse_mode=(seed // 2) % 2, mode=2)
+    h = I.shuffle_rows(I.drop_diagonal(_random_graph(1700 + seed)), seed)
+    check(h, mode=2)
+    check(h, mode=2, pp_variant=1, reverse_mode=1)
+
+
+def test_engine_near_its_lds_limit():
+    """The largest meshes the engine takes, and one just past it: mode 2
+    refuses that one, mode 0 gives it to the team kernel, same result."""
+    import torch
+    from paper_1610_08128_amd import rcm
+
+    for g in (I.grid2d(80, 80, seed=41), I.grid3d(18, 18, 18, seed=42),
+              I.shuffle_rows(I.rgg_patches(4000, 43), 3)):
+        check(g, mode=2)
+    big = I.grid2d(85, 85, seed=44)
+    with pytest.raises(rcm.RcmError) as e:
+        rcm.order(torch.from_numpy(big.rowptr).cuda(), torch.from_numpy(big.colidx).cuda(),
+                  mode=2)
+    assert e.value.status == rcm.ERR_INVALID_ARGUMENT
+    check(big)
+    with pytest.raises(rcm.RcmError) as e:
+        rcm.order(torch.from_numpy(big.rowptr).cuda(), torch.from_numpy(big.colidx).cuda(),
+                  mode=2, label_mode=1)
+    assert e.value.status == rcm.ERR_INVALID_ARGUMENT
+
+
+def test_engine_long_rows():
+    """Rows longer than the per-lane duplicate check (64 entries) and parents
+    with more children than the register ranking holds (8)."""
+    graphs = [I.star(300, 17), I.complete(70), I.erdos_renyi(200, 0.3, 45),
+              I.shuffle_rows(I.disjoint_union([I.star(90), I.complete(12), I.path(40)],
+                                              seed=46), 4)]
+    for g in graphs:
+        check(g, mode=2)
+        check(g, mode=2, pp_variant=1, reverse_mode=1)
+
+
+def test_engine_status_codes():
+    import torch
+    from paper_1610_08128_amd import rcm
+
+    def status(rp, ci, **opts):
+        try:
+            rcm.order(torch.from_numpy(np.asarray(rp, np.int32)).cuda(),
+                      torch.from_numpy(np.asarray(ci, np.int32)).cuda(), mode=2, **opts)
+            return rcm.OK
+        except rcm.RcmError as e:
+            return e.status
+
+    g = I.path(6)
+    bad = g.colidx.copy()
+    bad[2] = 6
+    assert status(g.rowptr, bad) == rcm.ERR_BAD_CSR
+    badr = g.rowptr.copy()
+    badr[3] = badr[2] - 1
+    assert status(badr, g.colidx) == rcm.ERR_BAD_CSR
+    # a repeated column in a short row and in a long one
+    assert status([0, 3, 6, 8], [0, 1, 1, 0, 1, 2, 1, 2]) == rcm.ERR_BAD_CSR
+    s = I.star(100, 0)
+    ci = s.colidx.copy()
+    ci[s.rowptr[1] - 1] = ci[s.rowptr[0] + 5]
+    assert status(s.rowptr, ci) == rcm.ERR_BAD_CSR
+    # vertex 1 points at vertex 0 without the way back: found by the
+    # traversal, and by the full check
+    rp = [0, 1, 4, 6, 8, 10, 12]
+    ci = [0, 0, 1, 2, 2, 3, 3, 4, 4, 5, 4, 5]
+    assert status(rp, ci) == rcm.ERR_NOT_SYMMETRIC
+    assert status(rp, ci, check_full=True) == rcm.ERR_NOT_SYMMETRIC
+    assert status([0, 2, 3, 4, 5, 6], [0, 4, 1, 2, 3, 4], check_full=True) == \
+        rcm.ERR_NOT_SYMMETRIC
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_engine_equals_team_kernel(seed):
+    """The two engines agree with each other on the same input (and with the
+    oracle), including graphs with isolated vertices and self loops."""
+    g = I.add_random_self_loops(_random_graph(1800 + seed), 0.3, seed)
+    a = gpu_order(g, mode=2)
+    b = gpu_order(g, mode=1)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and a[2] == b[2]
+    check(g, mode=2)
