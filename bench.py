@@ -38,6 +38,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+DEFAULT_TABLE = os.path.join(ROOT, "paper_1610_08128_amd", "tuning", "mi355x.txt")
 
 WORKLOADS = {
     "grid2d_64x64": (0, "2D 5-point 64x64, relabelled (seed 1)"),
@@ -131,6 +132,16 @@ def host_cpu():
     return {"host_cores": cores, "host_cpu": model}
 
 
+def tuning_record(path: str, n: int, nnz: int, graphs: int):
+    """Which table entry the library applied (None without a table)."""
+    if not path:
+        return None
+    from paper_1610_08128_amd import rcm, tune
+
+    return {"file": os.path.relpath(path, ROOT), "class": tune.size_class(n, nnz, graphs),
+            "options": rcm.tuning_options(path, n, nnz, graphs)}
+
+
 def cpu_baseline(g, budget_s: float):
     import oracle
 
@@ -213,12 +224,14 @@ def run_batched(args):
     torch.cuda.synchronize()
     with torch.cuda.stream(stream):
         for _ in range(args.warmup):
-            perm, stats = rcm.order_batched(vo, no, rpd, cid, workspace=ws, stream=stream)
+            perm, stats = rcm.order_batched(vo, no, rpd, cid, workspace=ws, stream=stream,
+                                            tuning_file=args.tuning_file or None)
         torch.cuda.synchronize()
         kern_ms = []
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            perm, stats = rcm.order_batched(vo, no, rpd, cid, workspace=ws, stream=stream)
+            perm, stats = rcm.order_batched(vo, no, rpd, cid, workspace=ws, stream=stream,
+                                            tuning_file=args.tuning_file or None)
             tm = rcm.last_timings()
             kern_ms.append(tm["small_kernel_ms"] + tm["team_kernel_ms"])
         torch.cuda.synchronize()
@@ -273,6 +286,7 @@ def run_batched(args):
         },
         "phases_ms_last_step": {k: (round(v, 4) if isinstance(v, float) else v)
                                 for k, v in phases.items()},
+        "tuning": tuning_record(args.tuning_file, int(vo[-1]), int(no[-1]), G),
         "cpu_baseline": cpu,
         "matches_oracle_sampled": check,
     }
@@ -575,6 +589,9 @@ def main():
                     help="requests per arrival rate in --mode serve")
     ap.add_argument("--serve-pool", type=int, default=32,
                     help="distinct request graphs generated for --mode serve (reused cyclically)")
+    ap.add_argument("--tuning-file", default=DEFAULT_TABLE if os.path.exists(DEFAULT_TABLE) else "",
+                    help="tuning table for the launch options left at auto (default: the "
+                         "table shipped for MI355X, written by the autotuner; '' = none)")
     ap.add_argument("--team-size", type=int, default=0)
     ap.add_argument("--async-search", type=int, default=0, choices=[-1, 0, 1],
                     help="search passes of the large component: 0 = auto (asynchronous), "
@@ -613,7 +630,7 @@ def main():
     rp = torch.from_numpy(g.rowptr).to(dev)
     ci = torch.from_numpy(g.colidx).to(dev)
     opts = dict(team_size=args.team_size, block_threads=args.block_threads,
-                async_search=args.async_search)
+                async_search=args.async_search, tuning_file=args.tuning_file or None)
     ws = torch.empty(rcm.workspace_bytes(g.n, g.nnz, **opts), dtype=torch.uint8, device=dev)
     stream = torch.cuda.Stream(device=dev)
     if args.calibrate_copy_mb > 0:
@@ -715,6 +732,7 @@ def main():
         "profile": [st["profile_before"], st["profile_after"]],
         "phases_ms_last_step": {k: (round(v, 4) if isinstance(v, float) else v)
                                 for k, v in phases.items()},
+        "tuning": tuning_record(args.tuning_file, g.n, g.nnz, 1),
         "roofline": roofline,
         "cpu_baseline": cpu,
         "matches_oracle": check,

@@ -256,9 +256,27 @@ rcm_status rcm_order_batched(int32_t num_graphs, const int64_t* vtx_offsets,
                              const rcm_options* opts, void* workspace, size_t workspace_bytes,
                              void* stream);
 
+/* The launch options a tuning table gives a call of num_graphs graphs (1 =
+ * a single-graph call) with n vertices and nnz entries in total: every
+ * field of *out still at 0 is set from the entry of the call's size class
+ * (the exact class, else the nearest of the same kind); other fields are
+ * left alone.  This is what rcm_order_ex and rcm_order_batched apply when
+ * rcm_options.tuning_file (or RCM_TUNING_FILE) names the table.  A table
+ * file is parsed once per path and process.  Errors:
+ * RCM_ERR_INVALID_ARGUMENT for a NULL path or out, negative sizes, or a
+ * table that cannot be read or holds anything but launch options.
+ * Format (text, one line per size class, written by tune.py):
+ *   single:n2^<floor log2 n>:d<nnz/n rounded half to even> <option>=<int> ...
+ * Launch options: team_size block_threads small_cutoff narrow_cutoff
+ * small_threads max_teams rebalance_levels async_search label_team
+ * search_round mode. */
+rcm_status rcm_tuning_options(const char* path, int32_t num_graphs, int64_t n, int64_t nnz,
+                              rcm_options* out);
+
 /* Wall-clock phase timings of the last call made by this host thread, in
  * milliseconds, measured with HIP events on the call's stream when the
- * environment variable RCM_TIMING=1 is set (zero otherwise). */
+ * environment variable RCM_TIMING=1 is set (zero otherwise), and the
+ * launch settings that call used. */
 typedef struct {
   float validate_ms;     /* CSR checks, degrees, bandwidth/profile before  */
   float components_ms;   /* connected components and the component schedule */
@@ -271,6 +289,17 @@ typedef struct {
   float team_label_ms;   /* device clock of that launch: labelled BFS */
   int32_t team_pp_levels;    /* levels expanded by the pseudo-peripheral passes */
   int32_t team_label_levels; /* levels of the labelled BFS */
+  /* The settings the call used (filled whatever RCM_TIMING says): the
+     engine (1 persistent team kernel, 2 one-work-group LDS engine), the
+     team size, threads per team work-group, labelling sub-team and
+     asynchronous round length of the launch with teams (0 if none ran), and
+     the small-component cutoff.  Shows what a tuning table changed.      */
+  int32_t used_mode;
+  int32_t used_team_size;
+  int32_t used_block_threads;
+  int32_t used_label_team;
+  int32_t used_search_round;
+  int32_t used_small_cutoff;
   int64_t phase_ticks[28];   /* diagnostics, 100 MHz device clock of work-group 0
                                 of the team launch: [0..3] wide unlabelled levels
                                 (expand, append, barrier ticks; level count);

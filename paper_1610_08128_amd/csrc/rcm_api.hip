@@ -26,6 +26,8 @@ using namespace rcm;
 namespace {
 
 thread_local rcm_timings g_timings;
+// the launch settings of the current call, copied into g_timings at its end
+thread_local int32_t g_used[6];
 
 inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 
@@ -206,6 +208,7 @@ struct Timer {
   }
   void finish() {
     rcm_timings t{};
+    std::memcpy(&t.used_mode, g_used, sizeof(g_used));
     if (on && used[0]) {
       int last = 0;
       for (int i = 0; i < 6; ++i)
@@ -420,6 +423,13 @@ rcm_status run(const Graph& gin, const int32_t* seg_off_host, const Opts& opt, c
       HIP_TRY(hipMemsetAsync(P.sub_slots, 0, sizeof(TeamSlots) * nteams, s));
     }
     if (n_small > 0) HIP_TRY(hipMemsetAsync(small_ctl, 0, sizeof(TeamCtl) * blocks, s));
+    if (n_big > 0) {
+      g_used[1] = P.team_size;
+      g_used[2] = threads;
+      g_used[3] = opt.label_team;
+      g_used[4] = opt.search_round;
+    }
+    g_used[5] = opt.small_cutoff;
     timer.kmark(kslot, true);
     HIP_TRY(launch_order(P, blocks, threads, s));
     timer.kmark(kslot, false);
@@ -725,16 +735,30 @@ rcm_status order_single(int32_t n, const int32_t* rowptr, const int32_t* colidx,
   Opts o;
   rcm_status st = check_common(n, opts, &o);
   if (st != RCM_OK) return st;
+  std::memset(g_used, 0, sizeof(g_used));
   if (stats) std::memset(stats, 0, sizeof(*stats));
   if (n == 0) return RCM_OK;
   if (!rowptr || !perm_out) return RCM_ERR_INVALID_ARGUMENT;
   hipStream_t s = static_cast<hipStream_t>(stream);
+  if (const char* tf = tuning_path(opts)) {
+    // a tuning table: its entry for this graph's size class supplies every
+    // launch option left at 0 (the entry count needs one readback first)
+    int32_t nnz = 0;
+    HIP_TRY(hipMemcpyAsync(&nnz, rowptr + n, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    rcm_options eff{};
+    if (opts) eff = *opts;
+    if (!tuning_apply(tf, n, nnz < 0 ? 0 : nnz, 1, &eff)) return RCM_ERR_INVALID_ARGUMENT;
+    if (!parse_options(&eff, &o)) return RCM_ERR_INVALID_ARGUMENT;
+  }
   if (o.mode != 1) {
+    g_used[0] = 2;
     if (order_small(n, rowptr, colidx, perm_out, iperm_out, stats, o, workspace,
                     workspace_bytes, s, timing, &st))
       return st;
     if (o.mode == 2) return RCM_ERR_INVALID_ARGUMENT;
   }
+  g_used[0] = 1;
   int32_t ends[2];
   HIP_TRY(hipMemcpyAsync(&ends[0], rowptr, 4, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipMemcpyAsync(&ends[1], rowptr + n, 4, hipMemcpyDeviceToHost, s));
@@ -790,6 +814,8 @@ rcm_status rcm_order_batched(int32_t num_graphs, const int64_t* vtx_offsets,
   if (!vtx_offsets || !nnz_offsets) return RCM_ERR_INVALID_ARGUMENT;
   Opts o;
   if (!parse_options(opts, &o, true)) return RCM_ERR_INVALID_ARGUMENT;
+  std::memset(g_used, 0, sizeof(g_used));
+  g_used[0] = 1;
   if (vtx_offsets[0] != 0 || nnz_offsets[0] != 0) return RCM_ERR_INVALID_ARGUMENT;
   for (int g = 0; g < num_graphs; ++g)
     if (vtx_offsets[g + 1] < vtx_offsets[g] || nnz_offsets[g + 1] < nnz_offsets[g])
@@ -797,6 +823,13 @@ rcm_status rcm_order_batched(int32_t num_graphs, const int64_t* vtx_offsets,
   const int64_t N64 = vtx_offsets[num_graphs];
   const int64_t NNZ64 = nnz_offsets[num_graphs];
   if (N64 >= (1ll << 31) - 1 || NNZ64 >= (1ll << 31) - 1) return RCM_ERR_INVALID_ARGUMENT;
+  if (const char* tf = tuning_path(opts)) {
+    rcm_options eff{};
+    if (opts) eff = *opts;
+    if (!tuning_apply(tf, N64, NNZ64, num_graphs > 1 ? num_graphs : 2, &eff))
+      return RCM_ERR_INVALID_ARGUMENT;
+    if (!parse_options(&eff, &o, true)) return RCM_ERR_INVALID_ARGUMENT;
+  }
   if (stats) std::memset(stats, 0, sizeof(rcm_stats) * num_graphs);
   if (N64 == 0) return RCM_OK;
   if (!rowptr_cat || !perm_cat || (NNZ64 > 0 && !colidx_cat)) return RCM_ERR_INVALID_ARGUMENT;

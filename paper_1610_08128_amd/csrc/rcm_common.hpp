@@ -347,6 +347,13 @@ size_t small_lds_limit();
 hipError_t launch_small_order(const SmallJob& single, const SmallJob* jobs_dev, int32_t njobs,
                               const SmallOpts& opts, hipStream_t s);
 
+// Tuning tables (rcm_tuning.hip): the file named by opts->tuning_file, else
+// by RCM_TUNING_FILE, else none (nullptr).  tuning_apply sets every launch
+// option of *opts still at 0 from the table's entry for the call's size
+// class; false when the table cannot be read or is malformed.
+const char* tuning_path(const rcm_options* opts);
+bool tuning_apply(const char* path, int64_t n, int64_t nnz, int32_t graphs, rcm_options* opts);
+
 // rcm_order_ex without its extern "C" wrapper; timing = false never creates
 // HIP events (the allocation-free entry point).
 rcm_status order_single(int32_t n, const int32_t* rowptr, const int32_t* colidx,

@@ -38,6 +38,7 @@ EXPORTED = [
     "rcm_order_batched",
     "rcm_last_timings",
     "rcm_order_noalloc",
+    "rcm_tuning_options",
 ]
 
 NOALLOC_SCRATCH_BYTES = 256 << 20  # RCM_NOALLOC_SCRATCH_BYTES in include/rcm.h
@@ -101,6 +102,12 @@ class Timings(ctypes.Structure):
         ("team_label_ms", ctypes.c_float),
         ("team_pp_levels", ctypes.c_int32),
         ("team_label_levels", ctypes.c_int32),
+        ("used_mode", ctypes.c_int32),
+        ("used_team_size", ctypes.c_int32),
+        ("used_block_threads", ctypes.c_int32),
+        ("used_label_team", ctypes.c_int32),
+        ("used_search_round", ctypes.c_int32),
+        ("used_small_cutoff", ctypes.c_int32),
         ("phase_ticks", ctypes.c_int64 * 28),
     ]
 
@@ -137,6 +144,8 @@ def lib() -> ctypes.CDLL:
         L.rcm_order_noalloc.argtypes = [i32, P, P, P, P, ctypes.POINTER(Stats),
                                         ctypes.POINTER(Options), P]
         L.rcm_order_noalloc.restype = ctypes.c_int
+        L.rcm_tuning_options.argtypes = [ctypes.c_char_p, i32, i64, i64, ctypes.POINTER(Options)]
+        L.rcm_tuning_options.restype = ctypes.c_int
         L.rcm_last_timings.argtypes = [ctypes.POINTER(Timings)]
         L.rcm_last_timings.restype = None
         _lib = L
@@ -169,6 +178,23 @@ def make_options(*, pp_variant=0, reverse_mode=0, check_full=False, team_size=0,
     o.mode = int(mode)
     o.tuning_file = tuning_file.encode() if isinstance(tuning_file, str) else tuning_file
     return o
+
+
+TUNING_FIELDS = ("team_size", "block_threads", "small_cutoff", "narrow_cutoff", "small_threads",
+                 "max_teams", "rebalance_levels", "async_search", "label_team", "search_round",
+                 "mode")
+
+
+def tuning_options(path: str, n: int, nnz: int, num_graphs: int = 1) -> Dict[str, int]:
+    """The launch options the library takes from the tuning table at
+    ``path`` for a call of this size (rcm_tuning_options); only the options
+    the table sets."""
+    o = Options()
+    status = lib().rcm_tuning_options(path.encode(), int(num_graphs), int(n), int(nnz),
+                                      ctypes.byref(o))
+    if status != OK:
+        raise RcmError(status, status_string(status))
+    return {f: int(getattr(o, f)) for f in TUNING_FIELDS if getattr(o, f) != 0}
 
 
 def workspace_bytes(n: int, nnz: int, **opts) -> int:

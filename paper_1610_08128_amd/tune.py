@@ -8,18 +8,23 @@ does. Those parameters are:
 - the component-size cutoff below which a component gets a single
   work-group;
 - the threads of those single-work-group teams;
-- how many large-component teams run at once.
+- how many large-component teams run at once;
+- the labelling sub-team, the asynchronous search's round length and the
+  rebalance interval of the level-synchronous passes;
+- the engine (the persistent team kernel or the one-work-group LDS engine).
 
 The tuner times candidate settings on caller-supplied representative graphs
-(or batches) and keeps the fastest per size class in a JSON table. It checks
-that every candidate returned the same permutation.
+(or batches) and keeps the fastest per size class in a table. It checks that
+every candidate returned the same permutation.  The table is a text file the
+library itself reads (rcm_options.tuning_file or RCM_TUNING_FILE; format in
+include/rcm.h, rcm_tuning_options): one line per size class with its
+options, and the measured times as comments.
 
 Usage::
 
     table = autotune_single([g1, g2])            # inputs.Graph objects
-    table.save("rcm_tuning.json")
-    opts = TuningTable.load("rcm_tuning.json").options_for(n, nnz)
-    perm, stats = rcm.order(rowptr, colidx, **opts)
+    table.save("rcm_tuning.txt")
+    perm, stats = rcm.order(rowptr, colidx, tuning_file="rcm_tuning.txt")
 """
 
 from __future__ import annotations
@@ -34,25 +39,38 @@ import numpy as np
 
 from . import rcm
 
+# Large single graphs: team shape, labelling sub-team, round length of the
+# asynchronous search, rebalance interval of the level-synchronous passes.
 SINGLE_CANDIDATES: List[Dict[str, int]] = [
-    dict(team_size=w, block_threads=b, narrow_cutoff=nc)
-    for (w, b) in ((16, 512), (32, 512), (32, 256), (64, 256), (64, 512))
-    for nc in (64, 256, 1024)
+    dict(mode=1, team_size=w, block_threads=256, label_team=lt, search_round=sr,
+         rebalance_levels=rb)
+    for w in (128, 256)
+    for lt in (64, 96, 128)
+    for sr in (12, 16, 24)
+    for rb in (4, 8)
 ]
 
+# Small single graphs: the one-work-group engine against teams of the
+# persistent kernel.
+SMALL_CANDIDATES: List[Dict[str, int]] = (
+    [dict(mode=2)] +
+    [dict(mode=1, team_size=w, block_threads=256, narrow_cutoff=nc, label_team=w)
+     for w in (16, 64) for nc in (64, 256)])
+
 BATCH_CANDIDATES: List[Dict[str, int]] = [
-    dict(small_cutoff=sc, small_threads=st, team_size=w, max_teams=8)
-    for sc in (1 << 15, 1 << 17, 1 << 20)
+    dict(small_cutoff=sc, small_threads=st, team_size=w, max_teams=mt)
+    for sc in (1 << 15, 1 << 16, 1 << 17)
     for st in (256, 512)
-    for w in (4, 16)
+    for (w, mt) in ((4, 64), (8, 32), (16, 16))
 ]
 
 
 def size_class(n: int, nnz: int, graphs: int = 1) -> str:
-    """Key of a tuning entry: call kind, log2 of the vertex count, and the
-    rounded mean row length."""
+    """Key of a tuning entry: call kind, floor(log2) of the vertex count, and
+    the mean row length rounded half to even (the library computes the same
+    key)."""
     kind = "batch" if graphs > 1 else "single"
-    lg = int(math.log2(max(n, 1)))
+    lg = max(n, 1).bit_length() - 1
     deg = int(round(nnz / max(n, 1)))
     return f"{kind}:n2^{lg}:d{deg}"
 
@@ -81,16 +99,30 @@ class TuningTable:
                 best, best_d = k, d
         return dict(self.entries[best]) if best is not None else {}
 
-    def save(self, path: str) -> None:
+    def save(self, path: str, header: str = "") -> None:
+        """The library's text format; the measured times (ms per candidate)
+        follow each entry as comments."""
         with open(path, "w") as f:
-            json.dump({"entries": self.entries, "timings": self.timings}, f, indent=1,
-                      sort_keys=True)
+            f.write("# Reverse Cuthill-McKee launch options per size class, written by "
+                    "paper_1610_08128_amd/tune.py\n")
+            for line in header.splitlines():
+                f.write(f"# {line}\n")
+            for key in sorted(self.entries):
+                opts = " ".join(f"{k}={int(v)}" for k, v in sorted(self.entries[key].items()))
+                f.write(f"{key} {opts}\n")
+                for cand, ms in sorted(self.timings.get(key, {}).items(), key=lambda kv: kv[1]):
+                    f.write(f"#   {ms:10.4f} ms  {cand}\n")
 
     @classmethod
     def load(cls, path: str) -> "TuningTable":
+        entries: Dict[str, Dict[str, int]] = {}
         with open(path) as f:
-            d = json.load(f)
-        return cls(entries=d.get("entries", {}), timings=d.get("timings", {}))
+            for line in f:
+                line = line.split("#", 1)[0].split()
+                if not line:
+                    continue
+                entries[line[0]] = {k: int(v) for k, v in (t.split("=", 1) for t in line[1:])}
+        return cls(entries=entries)
 
 
 def _time_calls(call, reps: int) -> float:
