@@ -300,9 +300,17 @@ def _percentile(xs, q):
 
 
 def run_serve(args):
-    """Serving sweep: X1 = saturated throughput of one call per request
-    (first come first served, one stream, host CSR copied in per request);
-    then Poisson streams at fractions of X1 through the serving engine."""
+    """Serving sweep.  At each arrival rate the same Poisson stream of
+    requests (host CSR, copied in per request) goes through
+      (a) one call per request, first come first served on one stream (an
+          open-loop queue: latency = completion - arrival), and
+      (b) the serving engine (memory admission, continuous batching, two
+          executors),
+    with p50 / p99 latency and, for the engine, the split into queueing
+    (arrival to admission) and execution (admission to completion).  The
+    rate ladder starts at half of X1, the one-call path's saturated
+    throughput, and climbs until the engine serves less than 90% of the
+    offered rate."""
     import threading
 
     import numpy as np
@@ -317,31 +325,47 @@ def run_serve(args):
     gen_s = time.perf_counter() - t0
     dev = torch.device("cuda", 0)
     torch.cuda.synchronize()
+    tf = args.tuning_file or None
 
-    # X1: one call per request, inputs copied from the host each time
     def one_call(g):
         rp = torch.from_numpy(g.rowptr).to(dev)
         ci = torch.from_numpy(g.colidx).to(dev)
-        perm, _ = rcm.order(rp, ci)
+        perm, _ = rcm.order(rp, ci, tuning_file=tf)
         return perm.cpu().numpy()
 
     for g in pool[:4]:
         one_call(g)
     torch.cuda.synchronize()
+    # X1: one call per request back to back
     t = time.perf_counter()
-    lat1 = []
     for g in pool:
-        a = time.perf_counter()
         one_call(g)
-        lat1.append(time.perf_counter() - a)
     x1 = len(pool) / (time.perf_counter() - t)
 
+    def stream(rate):
+        return inputs.request_stream(args.serve_requests, rate, seed_sizes=5, seed_arrivals=6)
+
+    def run_one_call(rate):
+        """Open-loop first-come-first-served queue of single calls."""
+        arrivals = stream(rate)
+        lat = []
+        start = time.perf_counter()
+        for i, (at, *_rest) in enumerate(arrivals):
+            now = time.perf_counter() - start
+            if at > now:
+                time.sleep(at - now)
+            one_call(pool[i % len(pool)])
+            lat.append(time.perf_counter() - start - at)
+        span = time.perf_counter() - start - arrivals[0][0]
+        return {"served_per_s": round(len(lat) / span, 2),
+                "p50_ms": round(_percentile(lat, 50) * 1e3, 2),
+                "p99_ms": round(_percentile(lat, 99) * 1e3, 2)}
+
     budget = 8 << 30
-    rows = []
-    for frac in (0.5, 1.0, 2.0, 3.0, 4.0, 6.0):
-        rate = frac * x1
-        arrivals = inputs.request_stream(args.serve_requests, rate, seed_sizes=5, seed_arrivals=6)
-        with Server(mem_budget_bytes=budget) as srv:
+
+    def run_engine(rate):
+        arrivals = stream(rate)
+        with Server(mem_budget_bytes=budget, tuning_file=tf) as srv:
             tickets = [None] * len(arrivals)
             start = time.perf_counter()
 
@@ -356,21 +380,63 @@ def run_serve(args):
             th = threading.Thread(target=producer)
             th.start()
             th.join()
-            lat, done_at, first = [], [], None
-            for i, tk in enumerate(tickets):
-                perm, info = srv.wait(tk)
+            lat, queue, execu, done_at, batch, first = [], [], [], [], [], None
+            for tk in tickets:
+                _, info = srv.wait(tk)
                 assert info["status"] == 0, info
                 lat.append(info["latency_s"])
+                queue.append(info["queue_s"])
+                execu.append(info["t_done"] - info["t_admit"])
+                batch.append(info["batch_size"])
                 done_at.append(info["t_done"])
                 first = info["t_submit"] if first is None else min(first, info["t_submit"])
             c = srv.counters()
         span = max(done_at) - first
-        rows.append({"offered_per_s": round(rate, 2), "served_per_s": round(len(lat) / span, 2),
-                     "p50_ms": round(_percentile(lat, 50) * 1e3, 2),
-                     "p99_ms": round(_percentile(lat, 99) * 1e3, 2),
-                     "batches": c["batches"], "max_batch": c["max_batch_seen"]})
-        print(f"# rate {rate:.1f}/s: {rows[-1]}", file=sys.stderr, flush=True)
-    best = max(rows, key=lambda r: r["served_per_s"])
+        slow = int(np.argmax(lat))
+        return {"served_per_s": round(len(lat) / span, 2),
+                "p50_ms": round(_percentile(lat, 50) * 1e3, 2),
+                "p99_ms": round(_percentile(lat, 99) * 1e3, 2),
+                "queue_p50_ms": round(_percentile(queue, 50) * 1e3, 2),
+                "queue_p99_ms": round(_percentile(queue, 99) * 1e3, 2),
+                "exec_p50_ms": round(_percentile(execu, 50) * 1e3, 2),
+                "exec_p99_ms": round(_percentile(execu, 99) * 1e3, 2),
+                "mean_batch": round(float(np.mean(batch)), 2),
+                "batches": c["batches"], "max_batch": c["max_batch_seen"],
+                "slowest": {"ms": round(lat[slow] * 1e3, 1),
+                            "queue_ms": round(queue[slow] * 1e3, 1),
+                            "batch": batch[slow],
+                            "nnz": int(pool[slow % len(pool)].nnz)}}
+
+    rows = []
+    frac = 0.5
+    while True:
+        rate = frac * x1
+        row = {"offered_per_s": round(rate, 2), "engine": run_engine(rate)}
+        if frac <= 1.5:
+            row["one_call"] = run_one_call(rate)
+        rows.append(row)
+        print(f"# rate {rate:.1f}/s: {row}", file=sys.stderr, flush=True)
+        if row["engine"]["served_per_s"] < 0.9 * rate or frac >= 16:
+            break
+        frac = frac * 1.5 if frac < 1 else frac + (1.0 if frac < 4 else 2.0)
+    sat = rows[-1]
+    best = max(rows, key=lambda r: r["engine"]["served_per_s"])
+    # the headline: at each rate both paths ran, who keeps up and at which
+    # p99; then the highest rate at which the engine keeps up with a p99 no
+    # larger than the one-call path's at that same rate
+    both = [r for r in rows if "one_call" in r]
+
+    def keeps_up(x, rate):
+        return x["served_per_s"] >= 0.95 * rate
+
+    wins = [r for r in both if keeps_up(r["engine"], r["offered_per_s"])
+            and r["engine"]["p99_ms"] <= r["one_call"]["p99_ms"]]
+    headline = None
+    if wins:
+        w = max(wins, key=lambda r: r["offered_per_s"])
+        headline = {"offered_per_s": w["offered_per_s"],
+                    "engine": {k: w["engine"][k] for k in ("served_per_s", "p50_ms", "p99_ms")},
+                    "one_call": w["one_call"]}
     cpu = None
     if args.cpu_budget > 0:
         value, threads, done, cdt = _pool_oracle(pool, args.cpu_budget)
@@ -381,22 +447,21 @@ def run_serve(args):
     if not args.no_check:
         import oracle
 
-        srv_check = None
-        with Server(mem_budget_bytes=budget) as srv:
-            ts = [srv.submit(g.rowptr, g.colidx) for g in pool[:8]]
+        with Server(mem_budget_bytes=budget, tuning_file=tf) as srv:
+            ts = [srv.submit(g.rowptr, g.colidx) for g in pool]
             srv_check = all(np.array_equal(srv.wait(t)[0], oracle.rcm(g.n, g.rowptr,
                                                                       g.colidx).perm)
-                            for g, t in zip(pool[:8], ts))
+                            for g, t in zip(pool, ts))
     else:
         srv_check = None
     out = {
         "metric": "served RCM orderings/s",
-        "value": best["served_per_s"],
+        "value": best["engine"]["served_per_s"],
         "unit": "orderings/s",
         "n_gpus": 1,
         "steps": len(rows) * args.serve_requests,
         "warmup": 4,
-        "ms_per_step": round(1000.0 / best["served_per_s"], 3),
+        "ms_per_step": round(1000.0 / best["engine"]["served_per_s"], 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -409,14 +474,16 @@ def run_serve(args):
                    "pool_nnz_mean": int(np.mean([g.nnz for g in pool])),
                    "mem_budget_bytes": budget, "executors": 2, "max_batch": 32,
                    "batch_nnz_limit": "none"},
-        "one_call_per_request": {"orderings_per_s": round(x1, 2),
-                                 "p50_ms": round(_percentile(lat1, 50) * 1e3, 2),
-                                 "p99_ms": round(_percentile(lat1, 99) * 1e3, 2)},
+        "x1_one_call_per_s": round(x1, 2),
         "sweep": rows,
-        "best": best,
+        "saturation": {"offered_per_s": sat["offered_per_s"], **sat["engine"]},
+        "engine_beats_one_call_at": headline,
+        "tuning": ({"file": os.path.relpath(args.tuning_file, ROOT),
+                    "applied": "per request and per batch, by its own size class"}
+                   if args.tuning_file else None),
         "generation_s": round(gen_s, 1),
         "cpu_baseline": cpu,
-        "matches_oracle_sampled": srv_check,
+        "matches_oracle_all_pool": srv_check,
     }
     print(json.dumps(out), flush=True)
 

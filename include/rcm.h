@@ -260,7 +260,9 @@ rcm_status rcm_order_batched(int32_t num_graphs, const int64_t* vtx_offsets,
  * a single-graph call) with n vertices and nnz entries in total: every
  * field of *out still at 0 is set from the entry of the call's size class
  * (the exact class, else the nearest of the same kind); other fields are
- * left alone.  This is what rcm_order_ex and rcm_order_batched apply when
+ * left alone.  mode is taken only from the exact class, and a table's mode 2
+ * is not passed on (it asks for what auto does: the one-work-group engine
+ * where the graph fits).  This is what rcm_order_ex and rcm_order_batched apply when
  * rcm_options.tuning_file (or RCM_TUNING_FILE) names the table.  A table
  * file is parsed once per path and process.  Errors:
  * RCM_ERR_INVALID_ARGUMENT for a NULL path or out, negative sizes, or a

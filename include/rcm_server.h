@@ -58,7 +58,8 @@ typedef struct {
                                 components of all batched requests concurrently,
                                 which keeps the GPU busier than requests run one
                                 by one)                                              */
-  rcm_options order_options; /* options of every ordering (see rcm.h)                */
+  rcm_options order_options; /* options of every ordering (see rcm.h); the server
+                                keeps its own copy of tuning_file               */
 } rcm_server_config;
 
 /* Outcome of one request. Times are seconds on the host's steady clock,

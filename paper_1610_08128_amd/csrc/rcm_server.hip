@@ -16,6 +16,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <string>
 #include <thread>
 #include <unordered_map>
 #include <vector>
@@ -112,6 +113,7 @@ struct Request {
 
 struct rcm_server {
   rcm_server_config cfg{};
+  std::string tuning_file;  // the server's own copy of order_options.tuning_file
   int device = 0;
   char* arena_base = nullptr;
   std::unique_ptr<Arena> arena;
@@ -346,12 +348,22 @@ rcm_status rcm_server_create(const rcm_server_config* cfg_in, rcm_server** out) 
   if (cfg.max_batch == 0) cfg.max_batch = 32;
   if (cfg.executors == 0) cfg.executors = 2;
   if (cfg.batch_nnz_limit == 0) cfg.batch_nnz_limit = (1ll << 31) - 1;
-  // reject bad ordering options now rather than per request
+  // reject bad ordering options (and an unreadable tuning table) now rather
+  // than per request
   if (rcm_order_ex(0, nullptr, nullptr, nullptr, nullptr, nullptr, &cfg.order_options, nullptr, 0,
                    nullptr) != RCM_OK)
     return RCM_ERR_INVALID_ARGUMENT;
+  if (cfg.order_options.tuning_file) {
+    rcm_options probe = cfg.order_options;
+    if (rcm_tuning_options(cfg.order_options.tuning_file, 1, 1, 1, &probe) != RCM_OK)
+      return RCM_ERR_INVALID_ARGUMENT;
+  }
   auto srv = std::make_unique<rcm_server>();
   srv->cfg = cfg;
+  if (cfg.order_options.tuning_file) {
+    srv->tuning_file = cfg.order_options.tuning_file;
+    srv->cfg.order_options.tuning_file = srv->tuning_file.c_str();
+  }
   if (hipGetDevice(&srv->device) != hipSuccess) return RCM_ERR_HIP;
   void* base = nullptr;
   if (hipMalloc(&base, cfg.mem_budget_bytes) != hipSuccess) return RCM_ERR_OUT_OF_MEMORY;

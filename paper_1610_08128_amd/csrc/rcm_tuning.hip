@@ -153,8 +153,13 @@ bool tuning_apply(const char* path, int64_t n, int64_t nnz, int32_t graphs, rcm_
     }
   }
   if (best) {
-    for (const auto& kv : best->set)
+    for (const auto& kv : best->set) {
+      // the engine is taken only from the entry of the call's own class; a
+      // table's mode 2 asks for the one-work-group engine where the graph
+      // fits, as auto does (a caller's own mode 2 requires it)
+      if (kv.first == &rcm_options::mode && (best_d != 0 || kv.second == 2)) continue;
       if (opts->*(kv.first) == 0) opts->*(kv.first) = kv.second;
+    }
   }
   return true;
 }

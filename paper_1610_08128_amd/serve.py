@@ -130,6 +130,7 @@ class Server:
         if status != rcm.OK:
             raise rcm.RcmError(status, rcm.status_string(status))
         self._h = h
+        self._cfg = cfg
         self._held: Dict[int, Tuple[np.ndarray, np.ndarray, np.ndarray]] = {}
 
     def submit(self, rowptr, colidx) -> int:

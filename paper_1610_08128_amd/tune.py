@@ -83,10 +83,13 @@ class TuningTable:
     def options_for(self, n: int, nnz: int, graphs: int = 1) -> Dict[str, int]:
         """Options of the exact size class, else of the nearest class of the
         same kind and row length, else of the nearest of the same kind,
-        else {} (the library's defaults)."""
+        else {} (the library's defaults).  As in the library, the engine
+        (mode) comes only from the exact class, and mode 2 (the
+        one-work-group engine where the graph fits) is what auto does
+        anyway, so it is not passed on."""
         key = size_class(n, nnz, graphs)
         if key in self.entries:
-            return dict(self.entries[key])
+            return {k: v for k, v in self.entries[key].items() if not (k == "mode" and v == 2)}
         kind, lg, deg = key.split(":")
         lg_v, deg_v = int(lg[3:]), int(deg[1:])
         best, best_d = None, None
@@ -97,7 +100,9 @@ class TuningTable:
             d = abs(int(k_lg[3:]) - lg_v) + 4 * abs(int(k_deg[1:]) - deg_v)
             if best_d is None or d < best_d:
                 best, best_d = k, d
-        return dict(self.entries[best]) if best is not None else {}
+        if best is None:
+            return {}
+        return {k: v for k, v in self.entries[best].items() if k != "mode"}
 
     def save(self, path: str, header: str = "") -> None:
         """The library's text format; the measured times (ms per candidate)

@@ -49,6 +49,15 @@ def test_library_reads_the_tuners_table(tmp_path):
     o = rcm.make_options(team_size=4)
     assert rcm.lib().rcm_tuning_options(p.encode(), 1, 4096, 20224, ctypes.byref(o)) == rcm.OK
     assert o.team_size == 4 and o.mode == 1
+    # the engine comes only from the exact class, and never as mode 2
+    t2 = TuningTable(entries={"single:n2^12:d5": {"mode": 2, "team_size": 8},
+                              "single:n2^21:d7": {"mode": 1, "team_size": 256}})
+    p2 = str(tmp_path / "t2.txt")
+    t2.save(p2)
+    assert rcm.tuning_options(p2, 4096, 20224) == {"team_size": 8} == t2.options_for(4096, 20224)
+    assert rcm.tuning_options(p2, 1 << 15, 5 << 15) == {"team_size": 8}
+    assert rcm.tuning_options(p2, 1 << 21, 7 << 21) == {"mode": 1, "team_size": 256}
+    assert rcm.tuning_options(p2, 1 << 20, 7 << 20) == {"team_size": 256}
     # rounding half to even, as the tuner's round(): 2.5 -> 2, 3.5 -> 4
     assert size_class(1000, 2500) == "single:n2^9:d2" and size_class(1000, 3500) == "single:n2^9:d4"
     bad = tmp_path / "bad.txt"
