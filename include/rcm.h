@@ -71,7 +71,8 @@ typedef enum {
                                       exhaustively with check_full                  */
   RCM_ERR_WORKSPACE_TOO_SMALL = 4, /* caller workspace below rcm_workspace_bytes()  */
   RCM_ERR_OUT_OF_MEMORY = 5,       /* internal device allocation failed             */
-  RCM_ERR_ABORTED = 6,             /* a device-side wait exceeded its spin limit    */
+  RCM_ERR_ABORTED = 6,             /* the caller's abort flag was set, or a
+                                      device-side wait exceeded its time limit     */
   RCM_ERR_HIP = 7                  /* a HIP runtime call failed                     */
 } rcm_status;
 
@@ -180,13 +181,33 @@ typedef struct {
                             2 = always the one-work-group LDS engine
                                (RCM_ERR_INVALID_ARGUMENT if the graph does
                                not fit, or with label_mode 1 or 2)          */
-  int32_t reserved;
+  int32_t shuffle_seed;  /* 0 = off.  Otherwise a seed that permutes, by seeded
+                            bijections, which work-group of a launch plays
+                            which team member, the order in which teams and
+                            single work-groups take components (and the LDS
+                            engine's work-groups their graphs), and delays
+                            each work-group by a seeded few microseconds at
+                            every team barrier.  The result must not change:
+                            the knob exists to shake out order dependences
+                            (a race shows up as a different permutation).
+                            Slower; for tests                             */
   const char* tuning_file; /* NULL = the RCM_TUNING_FILE environment variable,
                               if set; else no table.  A table written by the
                               autotuner (paper_1610_08128_amd/tune.py) whose
                               entries, chosen by the graph's vertex and entry
                               counts, replace the auto value of every option
                               left at 0 here                               */
+  const int32_t* abort_flag; /* NULL = none.  A flag from rcm_abort_flag_create
+                              (coherent pinned host memory).  While it is
+                              nonzero, a call returns RCM_ERR_ABORTED: before
+                              its first launch when already set, else soon
+                              after another host thread sets it: the kernels
+                              poll it at component boundaries, every 64th
+                              team barrier, every 64th level a work-group
+                              walks alone, and between the passes of the
+                              one-work-group engine (at least every 4096
+                              levels), and then end normally.  Any other
+                              pointer is RCM_ERR_INVALID_ARGUMENT          */
 } rcm_options;
 
 /* Human-readable name of a status code (static string). */
@@ -274,6 +295,19 @@ rcm_status rcm_order_batched(int32_t num_graphs, const int64_t* vtx_offsets,
  * search_round mode. */
 rcm_status rcm_tuning_options(const char* path, int32_t num_graphs, int64_t n, int64_t nnz,
                               rcm_options* out);
+
+/* Cancellation (for callers that must stop a long ordering: a serving
+ * loop's deadline, an interactive tool).  rcm_abort_flag_create allocates one
+ * int32 of coherent pinned host memory on the current device, zeroed, that
+ * the GPU reads while a call runs; the caller passes it as
+ * rcm_options.abort_flag and sets it (*flag = 1, from any host thread, also
+ * while the call runs) to make the call return RCM_ERR_ABORTED, or back to 0
+ * to let later calls run.  A call's outputs are unspecified after an abort;
+ * its workspace can be reused at once.  Errors: RCM_ERR_INVALID_ARGUMENT for
+ * a NULL out, RCM_ERR_HIP when the allocation fails.  rcm_abort_flag_destroy
+ * frees it (NULL is ignored); no call may still use it. */
+rcm_status rcm_abort_flag_create(int32_t** flag_out);
+void rcm_abort_flag_destroy(int32_t* flag);
 
 /* Wall-clock phase timings of the last call made by this host thread, in
  * milliseconds, measured with HIP events on the call's stream when the

@@ -284,8 +284,9 @@ int32_t orc_cm_queue(const int32_t* rowptr, const int32_t* colidx, const int32_t
             buf[c].v = v;
             ++c;
         }
-        /* ... and number them in increasing order of degree (then id, R2) */
-        qsort(buf, (size_t)c, sizeof(orc_tuple), cmp_tuple);
+        /* ... and number them in increasing order of degree (then id, R2);
+         * with none, buf may still be NULL, which qsort must not be given */
+        if (c > 0) qsort(buf, (size_t)c, sizeof(orc_tuple), cmp_tuple);
         for (int32_t i = 0; i < c; ++i) {
             label[buf[i].v] = tail;
             cm[tail++] = buf[i].v;

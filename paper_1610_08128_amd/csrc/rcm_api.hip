@@ -17,6 +17,8 @@
 #include <cstdlib>
 #include <cstring>
 #include <cstdio>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "rcm_common.hpp"
@@ -50,7 +52,31 @@ struct Opts {
   int label_team = 64;
   int search_round = 16;
   int mode = 0;  // 0 auto, 1 team kernel only, 2 one-work-group LDS engine only
+  uint32_t shuffle = 0;                 // seed of the work-group / task shuffle
+  const int32_t* abort_flag = nullptr;  // the caller's abort flag (host address) ...
+  const int32_t* abort_dev = nullptr;   // ... and the address the kernels read
 };
+
+// Abort flags made by rcm_abort_flag_create, host address -> device
+// address; an option naming any other pointer is rejected, since the
+// kernels read the flag as coherent host memory.
+std::mutex g_flag_mutex;
+std::map<const int32_t*, const int32_t*> g_flags;
+
+bool known_flag(const int32_t* f, const int32_t** dev) {
+  *dev = nullptr;
+  if (!f) return true;
+  std::lock_guard<std::mutex> lk(g_flag_mutex);
+  auto it = g_flags.find(f);
+  if (it == g_flags.end()) return false;
+  *dev = it->second;
+  return true;
+}
+
+// The caller's flag as the host sees it now.
+inline bool abort_set(const Opts& o) {
+  return o.abort_flag && __atomic_load_n(o.abort_flag, __ATOMIC_ACQUIRE) != 0;
+}
 
 // Auto team size of a single graph: all compute units for a large graph
 // (its asynchronous search passes speed up up to one work-group per CU),
@@ -90,6 +116,7 @@ bool parse_options(const rcm_options* o, Opts* out, bool batched = false) {
     if (o->label_team < 0 || o->label_team > kMaxTeam) return false;
     if (o->search_round < 0) return false;
     if (o->mode < 0 || o->mode > 2) return false;
+    if (!known_flag(o->abort_flag, &r.abort_dev)) return false;
     r.pp_variant = o->pp_variant;
     r.reverse_mode = o->reverse_mode;
     r.check_full = o->check_full;
@@ -105,6 +132,8 @@ bool parse_options(const rcm_options* o, Opts* out, bool batched = false) {
     if (o->label_team) r.label_team = o->label_team;
     if (o->search_round) r.search_round = o->search_round;
     r.mode = o->mode;
+    r.shuffle = static_cast<uint32_t>(o->shuffle_seed);
+    r.abort_flag = o->abort_flag;
   }
   *out = r;
   return true;
@@ -298,6 +327,7 @@ rcm_status run(const Graph& gin, const int32_t* seg_off_host, const Opts& opt, c
   int32_t* misc = reinterpret_cast<int32_t*>(ws + L.misc);  // [0..2] errors, [4] ncomp, [8..10] counts
   int32_t* sched = reinterpret_cast<int32_t*>(ws + L.sched);
 
+  if (abort_set(opt)) return RCM_ERR_ABORTED;
   HIP_TRY(hipMemcpyAsync(seg_off, seg_off_host, sizeof(int32_t) * (g.nseg + 1),
                          hipMemcpyHostToDevice, s));
   g.seg_off = seg_off;
@@ -354,6 +384,8 @@ rcm_status run(const Graph& gin, const int32_t* seg_off_host, const Opts& opt, c
   P.seg_off = g.seg_off;
   P.nseg = g.nseg;
   P.dkey = reinterpret_cast<unsigned long long*>(ws + L.dkey);
+  P.abort_flag = opt.abort_dev;
+  P.shuffle = opt.shuffle;
   // distance words of the asynchronous passes start below every pass tag
   if (opt.async_search) HIP_TRY(hipMemsetAsync(P.dkey, 0, 8 * static_cast<size_t>(g.n), s));
   P.teams = teams;
@@ -430,6 +462,7 @@ rcm_status run(const Graph& gin, const int32_t* seg_off_host, const Opts& opt, c
       g_used[4] = opt.search_round;
     }
     g_used[5] = opt.small_cutoff;
+    if (abort_set(opt)) return RCM_ERR_ABORTED;
     timer.kmark(kslot, true);
     HIP_TRY(launch_order(P, blocks, threads, s));
     timer.kmark(kslot, false);
@@ -607,14 +640,19 @@ rcm_status check_common(int32_t n, const rcm_options* opts, Opts* o) {
 extern "C" {
 
 const char* rcm_status_string(rcm_status s) {
-  switch (s) {
+  // a C caller may pass any int; reading it as the enum type would be
+  // undefined for values outside the enumerators' range
+  static_assert(sizeof(rcm_status) == sizeof(int32_t), "rcm_status is a 32-bit int");
+  int32_t v = 0;
+  std::memcpy(&v, &s, sizeof(v));
+  switch (v) {
     case RCM_OK: return "ok";
     case RCM_ERR_INVALID_ARGUMENT: return "invalid argument";
     case RCM_ERR_BAD_CSR: return "malformed CSR pattern";
     case RCM_ERR_NOT_SYMMETRIC: return "pattern is not symmetric";
     case RCM_ERR_WORKSPACE_TOO_SMALL: return "workspace too small";
     case RCM_ERR_OUT_OF_MEMORY: return "out of device memory";
-    case RCM_ERR_ABORTED: return "aborted: a device-side wait timed out";
+    case RCM_ERR_ABORTED: return "aborted: the abort flag was set or a device-side wait timed out";
     case RCM_ERR_HIP: return "HIP runtime error";
   }
   return "unknown status";
@@ -639,6 +677,37 @@ size_t rcm_batched_workspace_bytes(int32_t num_graphs, int64_t total_vertices, i
 
 void rcm_last_timings(rcm_timings* out) {
   if (out) *out = g_timings;
+}
+
+rcm_status rcm_abort_flag_create(int32_t** flag_out) {
+  if (!flag_out) return RCM_ERR_INVALID_ARGUMENT;
+  *flag_out = nullptr;
+  void* h = nullptr;
+  if (hipHostMalloc(&h, sizeof(int32_t), hipHostMallocMapped | hipHostMallocCoherent) !=
+      hipSuccess)
+    return RCM_ERR_HIP;
+  void* d = nullptr;
+  if (hipHostGetDevicePointer(&d, h, 0) != hipSuccess || d == nullptr) {
+    (void)hipHostFree(h);
+    return RCM_ERR_HIP;
+  }
+  int32_t* f = static_cast<int32_t*>(h);
+  __atomic_store_n(f, 0, __ATOMIC_RELEASE);
+  {
+    std::lock_guard<std::mutex> lk(g_flag_mutex);
+    g_flags[f] = static_cast<const int32_t*>(d);
+  }
+  *flag_out = f;
+  return RCM_OK;
+}
+
+void rcm_abort_flag_destroy(int32_t* flag) {
+  if (!flag) return;
+  {
+    std::lock_guard<std::mutex> lk(g_flag_mutex);
+    if (g_flags.erase(flag) == 0) return;
+  }
+  (void)hipHostFree(flag);
 }
 
 }  // extern "C"
@@ -692,7 +761,16 @@ bool order_small(int32_t n, const int32_t* rowptr, const int32_t* colidx, int32_
   }
   Timer timer(s, timing);
   SmallJob job{n, -1, rowptr, colidx, perm_out, iperm_out, 0, 0, res};
-  SmallOpts so{o.pp_variant, o.reverse_mode, o.check_full, static_cast<int32_t>(limit)};
+  SmallOpts so{o.pp_variant, o.reverse_mode, o.check_full, static_cast<int32_t>(limit),
+               o.shuffle, o.abort_dev};
+  if (abort_set(o)) {
+    *out = RCM_ERR_ABORTED;
+    if (owned) {
+      (void)hipFreeAsync(res, s);
+      (void)hipStreamSynchronize(s);
+    }
+    return true;
+  }
   SmallResult h{};
   timer.mark(0);
   timer.kmark(0, true);
@@ -727,6 +805,11 @@ bool order_small(int32_t n, const int32_t* rowptr, const int32_t* colidx, int32_
 }
 
 }  // namespace
+
+rcm_status check_call(int32_t n, const rcm_options* opts) {
+  Opts o;
+  return check_common(n, opts, &o);
+}
 
 rcm_status order_single(int32_t n, const int32_t* rowptr, const int32_t* colidx,
                         int32_t* perm_out, int32_t* iperm_out, rcm_stats* stats,

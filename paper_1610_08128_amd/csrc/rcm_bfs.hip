@@ -73,6 +73,9 @@ struct Team {
   long long pm;             // level orders: degrees of the vertices this thread
                             // reached in the current pass
   unsigned long long woke;  // narrow episodes seen (thread 0 only)
+  const int32_t* abort_flag;  // the caller's abort flag, or null
+  uint32_t shuffle;         // 0, or the seed of the shuffle mode
+  uint32_t polls;           // single-work-group barriers passed (abort polling)
   bool aborted;
 };
 
@@ -133,6 +136,7 @@ struct Shared {
   int32_t lown_base;               // wide labelled level: the label range of the
   int32_t lown_len;                // children this work-group placed (its list
   int32_t lown_ok;                 // in srec), valid when it holds them all
+  int32_t stop;                    // abort polls: the flag or an error was seen
   int32_t state[8];
 };
 
@@ -149,6 +153,23 @@ __device__ __forceinline__ void flag_error(GlobalCtl* g, int code, int site = 0,
     const int32_t d[7] = {site, comp, pass, level, cur_b, cur_e, end};
     for (int i = 0; i < 7; ++i) st_relaxed(&g->diag[i], d[i]);
   }
+}
+
+// Abort poll by every thread of a work-group: thread 0 reads the launch's
+// error word and the caller's abort flag (flagging RCM_ERR_ABORTED for the
+// latter); t.aborted when either is set.
+__device__ __forceinline__ void poll_stop(Team& t, Shared& S) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int32_t stop = ld_relaxed(&t.g->error) != 0 ? 1 : 0;
+    if (!stop && abort_requested(t.abort_flag)) {
+      flag_error(t.g, RCM_ERR_ABORTED, 21, t.comp);
+      stop = 1;
+    }
+    S.stop = stop;
+  }
+  __syncthreads();
+  t.aborted = S.stop != 0;
 }
 
 // Wait (thread 0) until *ctr >= target, giving up after the wall-clock limit
@@ -200,6 +221,7 @@ __device__ __forceinline__ void drain_memory_ops() {
 // read-only data (rows, vertex records) must come back from memory.  The
 // compiler barrier keeps the loads after the wait.
 __device__ __forceinline__ void slot_exchange(Team& t, Shared& S, uint32_t payload, bool drain) {
+  shuffle_delay(t.shuffle, static_cast<uint32_t>(t.wid), t.seq);
   if (drain) drain_memory_ops();
   __syncthreads();
   t.seq += 1;
@@ -242,6 +264,13 @@ __device__ __forceinline__ void slot_exchange(Team& t, Shared& S, uint32_t paylo
           }
         }
       }
+    }
+    // every 64th barrier the team's first work-group polls the caller's
+    // abort flag; the others stop when it no longer arrives (their waits
+    // check the error word)
+    if (lane == 0 && t.wid == 0 && (seq & 63) == 0 && abort_requested(t.abort_flag)) {
+      flag_error(t.g, RCM_ERR_ABORTED, 20, t.comp);
+      ok = false;
     }
     int32_t below = 0, all = 0, mx = 0, fl = 0;
 #pragma unroll
@@ -293,7 +322,11 @@ __device__ __forceinline__ void local_counts(Shared& S, int32_t c) {
 // Team barrier; `solo` = only this work-group is active (narrow mode or W=1).
 __device__ __forceinline__ void team_barrier(Team& t, Shared& S, bool solo) {
   if (solo || t.W == 1) {
-    __syncthreads();
+    // a work-group alone polls for an abort every 64th barrier
+    if (t.abort_flag != nullptr && ((++t.polls) & 63u) == 0)
+      poll_stop(t, S);
+    else
+      __syncthreads();
     return;
   }
   slot_exchange(t, S, 0u, true);
@@ -586,11 +619,25 @@ __device__ __forceinline__ bool lds_bfs_levels(const BfsParams& P, Team& t, Shar
     const long long q2 = wall_clock64();
     mykey = wave_min_u64(mykey);
     if ((threadIdx.x & 63) == 0 && mykey != kMaxKey) atomicMin(&N.kmin[nx], mykey);
+    // every 64th level: abort poll
+    const bool poll = t.abort_flag != nullptr && (nlev & 63) == 63;
+    if (poll && threadIdx.x == 0) {
+      S.stop = ld_relaxed(&t.g->error) != 0 ? 1 : 0;
+      if (!S.stop && abort_requested(t.abort_flag)) {
+        flag_error(t.g, RCM_ERR_ABORTED, 22, t.comp, epoch, level);
+        S.stop = 1;
+      }
+    }
     __syncthreads();
     const long long q3 = wall_clock64();
     const int32_t cnt = N.cnt[nx];
     const int32_t rows = N.rows[nx];
     ++nlev;
+    if (poll && S.stop) {
+      t.aborted = true;
+      done = true;
+      break;
+    }
     e_clear += q1 - q0;
     e_expand += q2 - q1;
     e_reduce += q3 - q2;
@@ -1545,7 +1592,22 @@ __device__ __forceinline__ bool lds_label_levels(const BfsParams& P, Team& t, Sh
         atomicAdd(&N.rows[mx], inf[j].y - inf[j].x);
       }
     }
+    // every 64th level: abort poll
+    const bool poll = t.abort_flag != nullptr && (nlev & 63) == 63;
+    if (poll && threadIdx.x == 0) {
+      S.stop = ld_relaxed(&t.g->error) != 0 ? 1 : 0;
+      if (!S.stop && abort_requested(t.abort_flag)) {
+        flag_error(t.g, RCM_ERR_ABORTED, 23, t.comp, 0, levels);
+        S.stop = 1;
+      }
+    }
     __syncthreads();
+    if (poll && S.stop) {
+      t.aborted = true;
+      done = true;
+      ++nlev;
+      break;
+    }
     ++nlev;
     cur_b = cur_e;
     cur_e += total;
@@ -2035,20 +2097,39 @@ __device__ __forceinline__ void order_main(const BfsParams& P) {
   t.woke = 0;
   if (threadIdx.x == 0) S.lown_ok = 0;
   t.aborted = false;
+  t.abort_flag = P.abort_flag;
+  t.shuffle = P.shuffle;
+  t.polls = 0;
+  t.comp = 0;
   if (static_cast<int32_t>(blockIdx.x) < P.big_blocks) {
+    // shuffle mode: which work-group plays which team member
+    const int32_t b = shuffle_index(static_cast<int32_t>(blockIdx.x), P.big_blocks, P.shuffle);
     t.W = P.team_size;
-    t.wid = blockIdx.x % P.team_size;
-    t.ctl = P.teams + blockIdx.x / P.team_size;
-    t.slots = P.slots + blockIdx.x / P.team_size;
-    t.sub_slots = P.sub_slots + blockIdx.x / P.team_size;
+    t.wid = b % P.team_size;
+    t.ctl = P.teams + b / P.team_size;
+    t.slots = P.slots + b / P.team_size;
+    t.sub_slots = P.sub_slots + b / P.team_size;
     while (true) {
-      if (t.wid == 0 && threadIdx.x == 0)
-        st_relaxed(&t.ctl->task, atomicAdd(&P.queues[0], 1));
+      if (t.wid == 0 && threadIdx.x == 0) {
+        int32_t ti = atomicAdd(&P.queues[0], 1);
+        // stop at a task boundary once the launch has an error or the
+        // caller asks for an abort
+        if (t.abort_flag != nullptr) {
+          if (ld_relaxed(&t.g->error) != 0) {
+            ti = -1;
+          } else if (abort_requested(t.abort_flag)) {
+            flag_error(t.g, RCM_ERR_ABORTED, 24);
+            ti = -1;
+          }
+        }
+        st_relaxed(&t.ctl->task, ti);
+      }
       team_barrier(t, S, false);
       if (t.aborted) return;
       const int32_t ti = ld_relaxed(&t.ctl->task);
+      if (ti < 0) return;
       if (ti >= P.n_big) break;
-      const CompTask task = P.big_tasks[ti];
+      const CompTask task = P.big_tasks[shuffle_index(ti, P.n_big, P.shuffle)];
       t.comp = task.index;
       order_component(P, t, S, task);
       if (t.aborted) return;
@@ -2061,16 +2142,33 @@ __device__ __forceinline__ void order_main(const BfsParams& P) {
   t.woke = 0;
   // the small list first, then whatever the teams have not taken yet of
   // the large one
+  uint32_t fetched = 0;
   for (int q = 1; q >= 0; --q) {
     const CompTask* list = q == 1 ? P.tasks : P.big_tasks;
     const int32_t count = q == 1 ? P.ntasks : P.n_big;
     while (true) {
-      if (threadIdx.x == 0) S.task = atomicAdd(&P.queues[q], 1);
+      shuffle_delay(P.shuffle, blockIdx.x, fetched);
+      if (threadIdx.x == 0) {
+        int32_t ti = atomicAdd(&P.queues[q], 1);
+        // abort polls: the error word at every task, the caller's flag at
+        // every 16th
+        if (t.abort_flag != nullptr) {
+          if (ld_relaxed(&t.g->error) != 0) {
+            ti = -1;
+          } else if ((fetched & 15u) == 0 && abort_requested(t.abort_flag)) {
+            flag_error(t.g, RCM_ERR_ABORTED, 25);
+            ti = -1;
+          }
+        }
+        S.task = ti;
+      }
+      ++fetched;
       __syncthreads();
       const int32_t ti = S.task;
       __syncthreads();
+      if (ti < 0) return;
       if (ti >= count) break;
-      const CompTask task = list[ti];
+      const CompTask task = list[shuffle_index(ti, count, q == 1 ? mix32(P.shuffle) : P.shuffle)];
       t.comp = task.index;
       order_component(P, t, S, task);
       if (t.aborted) return;

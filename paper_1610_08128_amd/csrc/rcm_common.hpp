@@ -103,6 +103,50 @@ struct SegStats {
 // ---------------------------------------------------------------------------
 // Device helpers.
 // ---------------------------------------------------------------------------
+
+// 32-bit mixing function (the finaliser of MurmurHash3).
+__host__ __device__ __forceinline__ uint32_t mix32(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x85ebca6bu;
+  x ^= x >> 13;
+  x *= 0xc2b2ae35u;
+  x ^= x >> 16;
+  return x;
+}
+
+// A seeded bijection of [0, count) (seed 0: the identity): an affine map
+// x -> a x + c with a odd is a bijection modulo the next power of two P >=
+// count; applying it until the value falls below count (cycle walking)
+// restricts it to a bijection of [0, count), in at most P - count + 1 steps.
+__host__ __device__ __forceinline__ int32_t shuffle_index(int32_t i, int32_t count,
+                                                          uint32_t seed) {
+  if (seed == 0 || count <= 1 || i < 0 || i >= count) return i;
+  uint32_t mask = 1;
+  while (mask < static_cast<uint32_t>(count)) mask <<= 1;
+  mask -= 1;
+  const uint32_t a = mix32(seed) | 1u;
+  const uint32_t c = mix32(seed ^ 0x9e3779b9u);
+  uint32_t x = static_cast<uint32_t>(i);
+  do {
+    x = (a * x + c) & mask;
+  } while (x >= static_cast<uint32_t>(count));
+  return static_cast<int32_t>(x);
+}
+
+// The caller's abort flag, read at system scope so that the load reaches
+// the host's copy (one PCIe round trip; callers poll it sparingly).
+__device__ __forceinline__ bool abort_requested(const int32_t* flag) {
+  return flag != nullptr &&
+         __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0;
+}
+
+// Shuffle mode's perturbation: a seeded wait of 0 to 7 times ~0.4 us
+// (s_sleep 16 = 1024 clocks), the same for every thread of a work-group.
+__device__ __forceinline__ void shuffle_delay(uint32_t seed, uint32_t a, uint32_t b) {
+  if (seed == 0) return;
+  const uint32_t k = mix32(seed ^ mix32(a * 0x9e3779b9u ^ b)) & 7u;
+  for (uint32_t i = 0; i < k; ++i) __builtin_amdgcn_s_sleep(16);
+}
 __device__ __forceinline__ int32_t ld_relaxed(const int32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -310,6 +354,8 @@ struct BfsParams {
   const int32_t* seg_off;     // vertex offsets of the graphs (segments), nseg + 1
   int32_t nseg;
   unsigned long long* dkey;   // per vertex: pass tag << 32 | ~distance (asynchronous passes)
+  const int32_t* abort_flag;  // the caller's abort flag (coherent host memory), or null
+  uint32_t shuffle;           // 0, or the seed of the work-group / task shuffle
 };
 
 // The one-work-group engine for a whole small graph in LDS (rcm_small.hip).
@@ -338,6 +384,8 @@ struct SmallOpts {
   int32_t reverse_mode;
   int32_t check_full;
   int32_t lds_bytes;        // dynamic LDS of each work-group
+  uint32_t shuffle;         // 0, or the seed of the work-group -> job shuffle
+  const int32_t* abort_flag;  // the caller's abort flag (coherent host memory), or null
 };
 // LDS bytes the engine needs for a graph (0 for n <= 0), and the most one
 // work-group may have on the current device (0 if unknown).
@@ -360,6 +408,9 @@ rcm_status order_single(int32_t n, const int32_t* rowptr, const int32_t* colidx,
                         int32_t* perm_out, int32_t* iperm_out, rcm_stats* stats,
                         const rcm_options* opts, void* workspace, size_t workspace_bytes,
                         void* stream, bool timing);
+// The checks order_single makes before any HIP call: n >= 0, valid options
+// (RCM_ERR_INVALID_ARGUMENT otherwise).
+rcm_status check_call(int32_t n, const rcm_options* opts);
 
 // One launch of the ordering kernel over the task lists in p; cooperative
 // (all blocks co-resident) whenever p has multi-work-group teams.

@@ -29,6 +29,11 @@ void* g_scratch_ptr[kMaxDevices] = {};
 extern "C" rcm_status rcm_order_noalloc(int32_t n, const int32_t* rowptr, const int32_t* colidx,
                                         int32_t* perm_out, int32_t* iperm_out, rcm_stats* stats,
                                         const rcm_options* opts, void* stream) {
+  // argument and option errors, and the empty graph, need no device
+  const rcm_status st = rcm::check_call(n, opts);
+  if (st != RCM_OK || n == 0)
+    return rcm::order_single(n, rowptr, colidx, perm_out, iperm_out, stats, opts, nullptr, 0,
+                             stream, false);
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return RCM_ERR_HIP;
   std::lock_guard<std::mutex> lk(g_device_mutex[dev]);

@@ -363,6 +363,7 @@ __device__ void order_graph(const SmallJob& J, const SmallOpts& O, char* smem) {
   const int32_t nnz = J.nnz >= 0 ? J.nnz : J.rowptr[n];
   __shared__ int32_t cnt[2];
   __shared__ int32_t asym;
+  __shared__ int32_t stop;
   SmallResult* R = J.res;
   if (nnz < 0) {
     if (tid == 0) R->status = RCM_ERR_BAD_CSR;
@@ -563,7 +564,26 @@ __device__ void order_graph(const SmallJob& J, const SmallOpts& O, char* smem) {
   Acc acc;
   uint32_t pass = 0;
   int32_t o = 0, s_from = 0;
+  // abort polls: one PCIe read of the caller's flag whenever 4096 units of
+  // work have passed since the last (a level walked is one unit, a
+  // component begun 64), checked between passes
+  uint32_t since_poll = 0;
+  auto abort_poll = [&](uint32_t units) -> bool {
+    if (O.abort_flag == nullptr) return false;
+    since_poll += units;
+    if (since_poll < 4096) return false;
+    since_poll = 0;
+    if (tid == 0) stop = abort_requested(O.abort_flag) ? 1 : 0;
+    __syncthreads();
+    const bool hit = stop != 0;
+    __syncthreads();
+    return hit;
+  };
   while (o < n) {
+    if (abort_poll(64)) {
+      acc.err = RCM_ERR_ABORTED;
+      break;
+    }
     // the next unlabelled vertex: the next component's lowest id
     int32_t s = -1;
     while (s < 0 && s_from < n) {
@@ -595,8 +615,13 @@ __device__ void order_graph(const SmallJob& J, const SmallOpts& O, char* smem) {
       uint32_t root = static_cast<uint32_t>(s);
       int32_t nlvl = r.ecc - 1;
       bool labelled = false;
+      bool aborted = false;
       __syncthreads();
       while (!asym && r.ecc > nlvl) {
+        if (abort_poll(static_cast<uint32_t>(r.ecc) + 1u)) {
+          aborted = true;
+          break;
+        }
         nlvl = r.ecc;
         const uint32_t v = static_cast<uint32_t>(r.key & 0xffffffffu);
         ++nbfs;
@@ -614,6 +639,10 @@ __device__ void order_graph(const SmallJob& J, const SmallOpts& O, char* smem) {
         }
         __syncthreads();
         if (r.count != size) asym = 1;
+      }
+      if (aborted) {
+        acc.err = RCM_ERR_ABORTED;
+        break;
       }
       if (O.pp_variant == 1) root = static_cast<uint32_t>(r.key & 0xffffffffu);
       t_search += wall_clock64() - ts0;
@@ -711,7 +740,9 @@ __global__ void __launch_bounds__(kSW) k_small_order(SmallJob single, const Smal
   // accesses fault)
   extern __shared__ __align__(16) char smem[];
   for (int32_t j = blockIdx.x; j < njobs; j += gridDim.x) {
-    order_graph<uint16_t>(jobs ? jobs[j] : single, opts, smem);
+    // shuffle mode: which work-group takes which graph
+    const int32_t jj = shuffle_index(j, njobs, opts.shuffle);
+    order_graph<uint16_t>(jobs ? jobs[jj] : single, opts, smem);
     __syncthreads();
   }
 }

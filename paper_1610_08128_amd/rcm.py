@@ -39,6 +39,8 @@ EXPORTED = [
     "rcm_last_timings",
     "rcm_order_noalloc",
     "rcm_tuning_options",
+    "rcm_abort_flag_create",
+    "rcm_abort_flag_destroy",
 ]
 
 NOALLOC_SCRATCH_BYTES = 256 << 20  # RCM_NOALLOC_SCRATCH_BYTES in include/rcm.h
@@ -84,8 +86,9 @@ class Options(ctypes.Structure):
         ("label_team", ctypes.c_int32),
         ("search_round", ctypes.c_int32),
         ("mode", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("shuffle_seed", ctypes.c_int32),
         ("tuning_file", ctypes.c_char_p),
+        ("abort_flag", ctypes.c_void_p),
     ]
 
 
@@ -148,6 +151,10 @@ def lib() -> ctypes.CDLL:
         L.rcm_tuning_options.restype = ctypes.c_int
         L.rcm_last_timings.argtypes = [ctypes.POINTER(Timings)]
         L.rcm_last_timings.restype = None
+        L.rcm_abort_flag_create.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+        L.rcm_abort_flag_create.restype = ctypes.c_int
+        L.rcm_abort_flag_destroy.argtypes = [ctypes.c_void_p]
+        L.rcm_abort_flag_destroy.restype = None
         _lib = L
     return _lib
 
@@ -159,7 +166,8 @@ def status_string(status: int) -> str:
 def make_options(*, pp_variant=0, reverse_mode=0, check_full=False, team_size=0,
                  block_threads=0, small_cutoff=0, narrow_cutoff=0, small_threads=0,
                  max_teams=0, rebalance_levels=0, label_mode=0, async_search=0,
-                 label_team=0, search_round=0, mode=0, tuning_file=None) -> Options:
+                 label_team=0, search_round=0, mode=0, tuning_file=None, shuffle_seed=0,
+                 abort_flag=None) -> Options:
     o = Options()
     o.pp_variant = int(pp_variant)
     o.reverse_mode = int(reverse_mode)
@@ -177,7 +185,44 @@ def make_options(*, pp_variant=0, reverse_mode=0, check_full=False, team_size=0,
     o.search_round = int(search_round)
     o.mode = int(mode)
     o.tuning_file = tuning_file.encode() if isinstance(tuning_file, str) else tuning_file
+    o.shuffle_seed = int(shuffle_seed)
+    o.abort_flag = abort_flag.address if isinstance(abort_flag, AbortFlag) else abort_flag
     return o
+
+
+class AbortFlag:
+    """rcm_abort_flag_create's flag: pass it as ``abort_flag=`` to a call and
+    ``set()`` it, from any thread, to make that call return
+    RCM_ERR_ABORTED; ``clear()`` it before the next call."""
+
+    def __init__(self):
+        p = ctypes.c_void_p()
+        st = lib().rcm_abort_flag_create(ctypes.byref(p))
+        if st != OK:
+            raise RcmError(st, "rcm_abort_flag_create")
+        self.address = p.value
+        self._word = ctypes.c_int32.from_address(self.address)
+
+    def set(self) -> None:
+        self._word.value = 1
+
+    def clear(self) -> None:
+        self._word.value = 0
+
+    @property
+    def is_set(self) -> bool:
+        return self._word.value != 0
+
+    def close(self) -> None:
+        if self.address:
+            lib().rcm_abort_flag_destroy(self.address)
+            self.address = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 TUNING_FIELDS = ("team_size", "block_threads", "small_cutoff", "narrow_cutoff", "small_threads",
