@@ -220,18 +220,28 @@ __device__ __forceinline__ void drain_memory_ops() {
 // once (1.7 us more per barrier for 256 work-groups), and afterwards even
 // read-only data (rows, vertex records) must come back from memory.  The
 // compiler barrier keeps the loads after the wait.
-__device__ __forceinline__ void slot_exchange(Team& t, Shared& S, uint32_t payload, bool drain) {
+//
+// The barrier has two halves: slot_arrive stores this work-group's slot and
+// slot_wait collects the others'.  Between them a work-group may do work
+// that needs nothing from the other work-groups (using LDS but not the
+// fields slot_wait fills); slot_exchange is the two back to back.
+__device__ __forceinline__ void slot_arrive(Team& t, Shared& S, uint32_t payload, bool drain) {
   shuffle_delay(t.shuffle, static_cast<uint32_t>(t.wid), t.seq);
   if (drain) drain_memory_ops();
   __syncthreads();
   t.seq += 1;
   const uint32_t seq = t.seq;
+  if (threadIdx.x == 0)
+    __hip_atomic_store(&t.slots->s[seq & 1][t.wid][0],
+                       (static_cast<unsigned long long>(seq) << 32) | payload, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void slot_wait(Team& t, Shared& S) {
+  const uint32_t seq = t.seq;
   if (threadIdx.x < 64) {
     const int lane = threadIdx.x;
     unsigned long long* base = &t.slots->s[seq & 1][0][0];
-    if (lane == 0)
-      __hip_atomic_store(base + t.wid * 16, (static_cast<unsigned long long>(seq) << 32) | payload,
-                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     // lane l waits for work-groups l, l + 64, ... (kMaxTeam / 64 at most),
     // polling all of them in each round trip
     constexpr int kPer = kMaxTeam / 64;
@@ -305,6 +315,11 @@ __device__ __forceinline__ void slot_exchange(Team& t, Shared& S, uint32_t paylo
   __syncthreads();
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
   t.aborted = S.flag != 0;
+}
+
+__device__ __forceinline__ void slot_exchange(Team& t, Shared& S, uint32_t payload, bool drain) {
+  slot_arrive(t, S, payload, drain);
+  slot_wait(t, S);
 }
 
 // The same counts for a work-group alone.
@@ -1688,7 +1703,7 @@ __device__ __forceinline__ void global_label_level(const BfsParams& P, Team& t, 
           // the row this parent loaded for its claims at the previous level
           const int32_t* kr = kept_row(S.u, p - lo);
 #pragma unroll
-          for (int j = 0; j < kRB; ++j) cnb[j] = kr[j];
+          for (int j = 0; j < kRB; ++j) cnb[j] = kr[j] & 0x7fffffff;
         } else {
           load_batch(P.colidx, e.y, e.z, u, cnb);
         }
@@ -1711,6 +1726,118 @@ __device__ __forceinline__ void global_label_level(const BfsParams& P, Team& t, 
   }
   const long long tot = block_sum_i64(wg_total, S.red);
   const long long t1 = wall_clock64();
+  // A work-group whose children all sit in registers (every parent's row is
+  // one batch, one parent per thread) and fit its LDS list orders them
+  // before the barrier has completed: their order within the work-group's
+  // list, their records and the rows they claim from need nothing from the
+  // other work-groups, only their labels (the level's base plus the counts
+  // of the work-groups before) do.  So it arrives, ranks its children into
+  // the list, loads their rows into LDS while the others arrive, and then
+  // waits; afterwards it writes the records at their labels and claims.
+  const bool early = !solo && one_round && tot <= kStageCap &&
+                     __syncthreads_and(captured || c_mine == 0) != 0;
+  if (early) {
+    slot_arrive(t, S, static_cast<uint32_t>(tot), false);
+    int rtot;
+    const int c = captured ? c_mine : 0;
+    const int ex = block_excl_scan(c, S.scan, &rtot);
+    if (c > 0) {
+      uint64_t key[kRB];
+#pragma unroll
+      for (int j = 0; j < kRB; ++j)
+        key[j] = (cmask >> j & 1u) ? pack_key(cinf[j].z, cnb[j]) : kMaxKey;
+#pragma unroll
+      for (int j = 0; j < kRB; ++j) {
+        if (!(cmask >> j & 1u)) continue;
+        int rank = 0;
+#pragma unroll
+        for (int i = 0; i < kRB; ++i) rank += key[i] < key[j] ? 1 : 0;
+        reinterpret_cast<int4*>(S.u.srec)[ex + rank] = record(cnb[j], cinf[j]);
+        my_m += cinf[j].z;
+      }
+    }
+    __syncthreads();
+    // waves 1.. load the rows and read their claims while wave 0 waits for
+    // the other work-groups.  Claims below this level's first label (cur_e)
+    // are final for the children, whose labels are all at least cur_e;
+    // every other claim (unclaimed, or one a work-group that already passed
+    // this barrier has just made) may still need the child's atomic.  So the
+    // flag does not depend on the child's label; it goes into bit 31 of the
+    // kept row entry (vertex ids are below 2^31).
+    const int32_t len = static_cast<int32_t>(tot);
+    if (threadIdx.x >= 64) {
+      for (int32_t i = threadIdx.x - 64; i < len && i < kRowCap; i += B - 64) {
+        const int4 r = reinterpret_cast<const int4*>(S.u.srec)[i];
+        if (r.z - r.y > kRB) continue;
+        int32_t nb[kRB];
+        if (r.z > r.y) {
+          load_batch(P.colidx, r.y, r.z, r.x, nb);
+        } else {
+#pragma unroll
+          for (int j = 0; j < kRB; ++j) nb[j] = r.x;
+        }
+        uint32_t cl[kRB];
+#pragma unroll
+        for (int j = 0; j < kRB; ++j) cl[j] = ld_relaxed(&P.claim[nb[j]]);
+        int32_t* kr = kept_row(S.u, i);
+#pragma unroll
+        for (int j = 0; j < kRB; ++j)
+          kr[j] = nb[j] | (cl[j] >= static_cast<uint32_t>(cur_e) && nb[j] != r.x
+                               ? int32_t(0x80000000u) : 0);
+      }
+    }
+    slot_wait(t, S);
+    if (t.aborted) return;
+    const long long t2 = wall_clock64();
+    const int32_t total = S.wtot;
+    if (total == 0) {
+      done = true;
+      return;
+    }
+    // (A) every listed child gets its record at its label and claims the
+    // neighbours found unclaimed (rows past the kept ones claim from memory)
+    const int32_t list_base = cur_e + S.wpre;
+    for (int32_t i = threadIdx.x; i < len; i += B) {
+      const int4 r = reinterpret_cast<const int4*>(S.u.srec)[i];
+      const int32_t at = list_base + i;
+      if (at < end) st_rec(&P.qi[at], r);
+      if (i < kRowCap && r.z - r.y <= kRB) {
+        const int32_t* kr = kept_row(S.u, i);
+#pragma unroll
+        for (int j = 0; j < kRB; ++j)
+          if (kr[j] < 0) atomicMin(&P.claim[kr[j] & 0x7fffffff], static_cast<uint32_t>(at));
+      } else {
+        claim_row(P, r.x, make_int4(r.y, r.z, 0, 0), static_cast<uint32_t>(at));
+      }
+    }
+    const long long t3 = wall_clock64();
+    if (threadIdx.x == 0) {
+      S.lown_base = list_base;
+      S.lown_len = S.wsum[wid];
+      S.lown_ok = S.wmax <= kStageCap ? 1 : 0;
+    }
+    team_barrier(t, S, false);
+    if (t.aborted) return;
+    if (t.wid == 0 && threadIdx.x == 0) {
+      const long long t4 = wall_clock64();
+      t.ctl->clk[12] += t4 - ta;
+      t.ctl->clk[13] += 1;
+      t.ctl->clk[16] += t1 - ta;
+      t.ctl->clk[17] += t2 - t1;
+      t.ctl->clk[18] += t3 - t2;
+      t.ctl->clk[19] += t4 - t3;
+      t.ctl->clk[30] += 1;  // levels that took this path
+    }
+    cur_b = cur_e;
+    cur_e += total;
+    ++levels;
+    if (cur_e > end) {
+      if (threadIdx.x == 0)
+        flag_error(t.g, RCM_ERR_NOT_SYMMETRIC, 3, t.comp, 0, levels, cur_b, cur_e, end);
+      done = true;
+    }
+    return;
+  }
   // the counts are all this barrier hands over: the count phase only read,
   // and placement touches other labels and claims than it read
   if (solo) {
