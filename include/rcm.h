@@ -208,6 +208,19 @@ typedef struct {
                               one-work-group engine (at least every 4096
                               levels), and then end normally.  Any other
                               pointer is RCM_ERR_INVALID_ARGUMENT          */
+  int32_t relabel_levels; /* single graphs: when the first level structure of
+                             vertex 0's component has at least this many
+                             levels (a long mesh), that component is
+                             renumbered in the structure's level order and
+                             the rest of its ordering runs on the renumbered
+                             copy, whose neighbouring levels sit together in
+                             memory.  The result is the same (every tie is
+                             broken by the caller's ids).  0 = auto (4096),
+                             -1 = never.  Uses workspace that the component
+                             search needs only later, so graphs with more
+                             than 8 entries per vertex are not renumbered;
+                             needs the asynchronous search and label_mode 0 */
+  int32_t reserved;
 } rcm_options;
 
 /* Human-readable name of a status code (static string). */
@@ -292,7 +305,7 @@ rcm_status rcm_order_batched(int32_t num_graphs, const int64_t* vtx_offsets,
  *   single:n2^<floor log2 n>:d<nnz/n rounded half to even> <option>=<int> ...
  * Launch options: team_size block_threads small_cutoff narrow_cutoff
  * small_threads max_teams rebalance_levels async_search label_team
- * search_round mode. */
+ * search_round mode relabel_levels. */
 rcm_status rcm_tuning_options(const char* path, int32_t num_graphs, int64_t n, int64_t nnz,
                               rcm_options* out);
 
@@ -326,7 +339,9 @@ typedef struct {
   int32_t team_pp_levels;    /* levels expanded by the pseudo-peripheral passes */
   int32_t team_label_levels; /* levels of the labelled BFS */
   /* The settings the call used (filled whatever RCM_TIMING says): the
-     engine (1 persistent team kernel, 2 one-work-group LDS engine), the
+     engine (1 persistent team kernel, 2 one-work-group LDS engine, 3 the
+     team kernel, which renumbered the graph after its first level
+     structure: see relabel_levels), the
      team size, threads per team work-group, labelling sub-team and
      asynchronous round length of the launch with teams (0 if none ran), and
      the small-component cutoff.  Shows what a tuning table changed.      */

@@ -52,6 +52,7 @@ struct Opts {
   int label_team = 64;
   int search_round = 16;
   int mode = 0;  // 0 auto, 1 team kernel only, 2 one-work-group LDS engine only
+  int relabel_levels = 4096;  // renumber a long whole-graph component (0 = never)
   uint32_t shuffle = 0;                 // seed of the work-group / task shuffle
   const int32_t* abort_flag = nullptr;  // the caller's abort flag (host address) ...
   const int32_t* abort_dev = nullptr;   // ... and the address the kernels read
@@ -116,6 +117,7 @@ bool parse_options(const rcm_options* o, Opts* out, bool batched = false) {
     if (o->label_team < 0 || o->label_team > kMaxTeam) return false;
     if (o->search_round < 0) return false;
     if (o->mode < 0 || o->mode > 2) return false;
+    if (o->relabel_levels < -1) return false;
     if (!known_flag(o->abort_flag, &r.abort_dev)) return false;
     r.pp_variant = o->pp_variant;
     r.reverse_mode = o->reverse_mode;
@@ -133,6 +135,7 @@ bool parse_options(const rcm_options* o, Opts* out, bool batched = false) {
     if (o->search_round) r.search_round = o->search_round;
     r.mode = o->mode;
     r.shuffle = static_cast<uint32_t>(o->shuffle_seed);
+    if (o->relabel_levels) r.relabel_levels = o->relabel_levels > 0 ? o->relabel_levels : 0;
     r.abort_flag = o->abort_flag;
   }
   *out = r;
@@ -386,6 +389,10 @@ rcm_status run(const Graph& gin, const int32_t* seg_off_host, const Opts& opt, c
   P.dkey = reinterpret_cast<unsigned long long*>(ws + L.dkey);
   P.abort_flag = opt.abort_dev;
   P.shuffle = opt.shuffle;
+  P.relabel_levels = 0;
+  P.resume = 0;
+  P.relabelled = 0;
+  P.new_of_old = nullptr;
   // distance words of the asynchronous passes start below every pass tag
   if (opt.async_search) HIP_TRY(hipMemsetAsync(P.dkey, 0, 8 * static_cast<size_t>(g.n), s));
   P.teams = teams;
@@ -486,15 +493,85 @@ rcm_status run(const Graph& gin, const int32_t* seg_off_host, const Opts& opt, c
     HIP_TRY(hipMemcpyAsync(t_big, &ht, sizeof(ht), hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(results, &hr, sizeof(hr), hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemsetAsync(seeds, 0, sizeof(int32_t), s));
+    // a long component stops after its first level structure (asynchronous
+    // passes and labelled orders only) when its renumbered columns fit the
+    // component results' region (see below): at most 8 entries per vertex
+    const size_t ci_room = L.t_single - L.results - 256;
+    P.relabel_levels = opt.label_mode == 0 && opt.async_search &&
+                               4 * static_cast<size_t>(g.nnz) <= ci_room
+                           ? opt.relabel_levels
+                           : 0;
     st = launch(t_big, 1, nullptr, 0, 1, true);
+    P.relabel_levels = 0;
     if (st != RCM_OK) return st;
     int32_t hres[8];
     HIP_TRY(hipMemcpyAsync(hres, results, sizeof(CompResult), hipMemcpyDeviceToHost, s));
-    st = read_ints(h, &gctl->error, 1, s);
+    // error, diag[8], p1_stop, p1_ecc, p1_tag, p1_size
+    int32_t gc[13];
+    st = read_ints(gc, &gctl->error, 13, s);
     if (st != RCM_OK) return st;
-    if (h[0]) report_device_error(gctl, s);
-    if (h[0] == RCM_ERR_NOT_SYMMETRIC) return RCM_ERR_NOT_SYMMETRIC;
-    if (h[0]) return RCM_ERR_ABORTED;
+    if (gc[0]) report_device_error(gctl, s);
+    if (gc[0] == RCM_ERR_NOT_SYMMETRIC) return RCM_ERR_NOT_SYMMETRIC;
+    if (gc[0]) return RCM_ERR_ABORTED;
+    if (gc[9]) {
+      // Renumber the component in that structure's level order and order it
+      // from there in a second launch.  Until that launch ends, only the
+      // regions of the component search (which runs afterwards, on the
+      // caller's numbering) and of the other components' tasks and results
+      // are free: they hold the maps, the new rows and the new records.  The
+      // second launch gets a visited array of its own, so that the stamps
+      // of the first structure, which the component search reads, stay.
+      const int32_t ecc1 = gc[10];
+      const uint32_t tag1 = static_cast<uint32_t>(gc[11]);
+      const int32_t size1 = gc[12];
+      if (ecc1 < 0 || ecc1 >= size1 || size1 < 1 || size1 > g.n) return RCM_ERR_HIP;
+      int32_t* err = misc + 12;
+      int32_t* counted = misc + 13;
+      int32_t* rowptr_new = pos;
+      int32_t* colidx_new = reinterpret_cast<int32_t*>(ws + L.results + 256);
+      int4* vinfo_new = reinterpret_cast<int4*>(ws + L.t_single);
+      static_assert(sizeof(CompTask) >= sizeof(int4), "a task list holds the records");
+      HIP_TRY(hipMemsetAsync(err, 0, 2 * sizeof(int32_t), s));
+      HIP_TRY(launch_relabel(g, vinfo, P.dkey, tag1, ecc1, size1, csize, flags, parent, scan_blk,
+                             sizes, offs, rowptr_new, colidx_new,
+                             static_cast<int64_t>(ci_room / 4), vinfo_new, err, counted, s));
+      st = read_ints(h, err, 2, s);
+      if (st != RCM_OK) return st;
+      if (h[0] || h[1] != size1) {
+        if (std::getenv("RCM_DEBUG"))
+          std::fprintf(stderr, "rcm: the first level structure counts %d of %d vertices\n",
+                       h[1], size1);
+        return RCM_ERR_NOT_SYMMETRIC;
+      }
+      long long clk_first[32];
+      std::memcpy(clk_first, timer.clk, sizeof(clk_first));
+      const CompTask rt{0, size1, 0, 0, ht.anchor};
+      HIP_TRY(hipMemcpyAsync(t_big, &rt, sizeof(rt), hipMemcpyHostToDevice, s));
+      int32_t* visit2 = csize;  // free again once the renumbering is built
+      HIP_TRY(hipMemsetAsync(visit2, 0, 4 * N, s));
+      const BfsParams saved = P;
+      P.colidx = colidx_new;
+      P.rowptr = rowptr_new;
+      P.vinfo = vinfo_new;
+      P.visit = visit2;
+      P.new_of_old = sizes;
+      P.relabelled = 1;
+      P.resume = 1;
+      st = launch(t_big, 1, nullptr, 0, 1, true);
+      P = saved;
+      if (st != RCM_OK) return st;
+      if (timer.on)
+        for (int i = 0; i < 32; ++i) timer.clk[i] += clk_first[i];
+      HIP_TRY(hipMemcpyAsync(hres, results, sizeof(CompResult), hipMemcpyDeviceToHost, s));
+      st = read_ints(gc, &gctl->error, 1, s);
+      if (st != RCM_OK) return st;
+      if (gc[0]) report_device_error(gctl, s);
+      if (gc[0] == RCM_ERR_NOT_SYMMETRIC) return RCM_ERR_NOT_SYMMETRIC;
+      if (gc[0]) return RCM_ERR_ABORTED;
+      // the other components claim in the caller's numbering from scratch
+      if (size1 < g.n) HIP_TRY(hipMemsetAsync(claim, 0xFF, 4 * N, s));
+      g_used[0] = 3;  // the team kernel on the renumbered component
+    }
     head_size = hres[4];
     if (head_size < 1 || head_size > g.n) return RCM_ERR_HIP;
   }

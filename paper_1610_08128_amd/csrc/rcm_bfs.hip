@@ -492,7 +492,7 @@ __device__ __forceinline__ void bfs_expand(const BfsParams& P, Team& t, Shared& 
 #pragma unroll
       for (int j = 0; j < kRB; ++j) {
         if (mask >> j & 1u) {
-          const uint64_t kv = pack_key(inf[j].z, nb[j]);
+          const uint64_t kv = pack_key(inf[j].z, inf[j].w);
           mykey = kv < mykey ? kv : mykey;
         }
       }
@@ -557,6 +557,10 @@ __device__ __forceinline__ void lds_put(NarrowLds& N, int buf, int i, int4 r) {
 // atomics).  Runs from the frontier qi[cur_b, cur_e) at `level` until the
 // pass ends, the next level no longer fits (more than kNarrowCap vertices or
 // more than kHash / 2 row entries), or it reaches stop_width vertices.
+// (Telling visited neighbours from LDS tables of the previous two levels
+// instead of the global stamps measured slower: 5.5 against 3.4 us per level
+// on a 32-wide strip, the table probes being dependent LDS round trips per
+// lane where the stamp loads of a row batch are in flight together.)
 // Returns false, having done nothing, when the current frontier does not fit.
 // On return the global key / tail slots are as the team levels expect them.
 __device__ __forceinline__ bool lds_bfs_levels(const BfsParams& P, Team& t, Shared& S, int32_t end, int32_t epoch,
@@ -626,7 +630,7 @@ __device__ __forceinline__ bool lds_bfs_levels(const BfsParams& P, Team& t, Shar
           if (cur_e + idx < end) P.qi[cur_e + idx] = r;
           if (idx < kNarrowCap) lds_put(N, (level + 1) & 1, idx, r);
           P.visit[nb[j]] = epoch;
-          const uint64_t kv = pack_key(inf[j].z, nb[j]);
+          const uint64_t kv = pack_key(inf[j].z, inf[j].w);
           mykey = kv < mykey ? kv : mykey;
         }
       }
@@ -844,7 +848,7 @@ __device__ __forceinline__ void own_bfs_levels(const BfsParams& P, Team& t, Shar
 #pragma unroll
         for (int j = 0; j < kRB; ++j) {
           if (!(mask >> j & 1u)) continue;
-          const uint64_t kv = pack_key(inf[j].z, nb[j]);
+          const uint64_t kv = pack_key(inf[j].z, inf[j].w);
           mykey = kv < mykey ? kv : mykey;
           if (idx < kOwnCap) {
             S.u.own[cb ^ 1][idx][0] = nb[j];
@@ -971,7 +975,7 @@ __device__ __forceinline__ void bfs_pass(const BfsParams& P, Team& t, Shared& S,
     __hip_atomic_store(&P.visit[root], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __hip_atomic_store(&t.ctl->pass_m[parity], 0ll, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     for (int i = 0; i < 3; ++i) st_relaxed(tail + i, 0);
-    __hip_atomic_store(minkey + 0, pack_key(ri.z, root), __ATOMIC_RELAXED,
+    __hip_atomic_store(minkey + 0, pack_key(ri.z, ri.w), __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_AGENT);
     __hip_atomic_store(minkey + 1, kMaxKey, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __hip_atomic_store(minkey + 2, kMaxKey, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1279,7 +1283,8 @@ __device__ __forceinline__ bool async_bfs_pass(const BfsParams& P, Team& t, Shar
                          __HIP_MEMORY_SCOPE_AGENT);
     }
     if (d >= my_max) {
-      const uint64_t kk = pack_key(P.vinfo[v].z, v);
+      const int4 vi = P.vinfo[v];
+      const uint64_t kk = pack_key(vi.z, vi.w);
       if (d > my_max) {
         my_max = d;
         my_key = kk;
@@ -1393,40 +1398,46 @@ __device__ __forceinline__ void place_long_row(const BfsParams& P, Shared& S, in
                                                int32_t list_base, long long& my_m) {
   const uint32_t pl = static_cast<uint32_t>(p);
   constexpr int kKids = 4;  // children ranked in registers
-  uint64_t ck[kKids];
+  uint64_t ck[kKids];  // their (degree, caller id) keys ...
+  int32_t cv[kKids];   // ... and vertex numbers
 #pragma unroll
-  for (int i = 0; i < kKids; ++i) ck[i] = kMaxKey;
+  for (int i = 0; i < kKids; ++i) {
+    ck[i] = kMaxKey;
+    cv[i] = u;
+  }
   int nc = 0;
   for (int32_t k0 = a; k0 < b; k0 += kRB) {
     int32_t nb[kRB];
     load_batch(P.colidx, k0, b, u, nb);
     uint32_t cl[kRB];
-    int32_t dg[kRB];
+    int2 dw[kRB];  // (degree, caller id)
 #pragma unroll
     for (int j = 0; j < kRB; ++j) cl[j] = ld_relaxed(&P.claim[nb[j]]);
 #pragma unroll
-    for (int j = 0; j < kRB; ++j) dg[j] = P.vinfo[nb[j]].z;
+    for (int j = 0; j < kRB; ++j) dw[j] = reinterpret_cast<const int2*>(P.vinfo + nb[j])[1];
 #pragma unroll
     for (int j = 0; j < kRB; ++j) {
       const bool child = nb[j] != u && cl[j] == pl;
-      const uint64_t kv = pack_key(dg[j], nb[j]);
+      const uint64_t kv = pack_key(dw[j].x, dw[j].y);
 #pragma unroll
-      for (int i = 0; i < kKids; ++i) ck[i] = (child && i == nc) ? kv : ck[i];
+      for (int i = 0; i < kKids; ++i) {
+        ck[i] = (child && i == nc) ? kv : ck[i];
+        cv[i] = (child && i == nc) ? nb[j] : cv[i];
+      }
       nc += child ? 1 : 0;
     }
   }
   if (nc <= kKids) {
     int4 inf[kKids];
 #pragma unroll
-    for (int i = 0; i < kKids; ++i)
-      inf[i] = P.vinfo[i < nc ? static_cast<int32_t>(ck[i] & 0xffffffffu) : u];
+    for (int i = 0; i < kKids; ++i) inf[i] = P.vinfo[cv[i]];
 #pragma unroll
     for (int i = 0; i < kKids; ++i) {
       if (i >= nc) continue;
       int rank = 0;
 #pragma unroll
       for (int x = 0; x < kKids; ++x) rank += ck[x] < ck[i] ? 1 : 0;
-      const int32_t v = static_cast<int32_t>(ck[i] & 0xffffffffu);
+      const int32_t v = cv[i];
       const int32_t at = base + rank;
       if (at < end) st_rec(&P.qi[at], record(v, inf[i]));
       my_m += inf[i].z;
@@ -1444,20 +1455,20 @@ __device__ __forceinline__ void place_long_row(const BfsParams& P, Shared& S, in
     for (int j = 0; j < kRB; ++j) {
       if (!(nb[j] != u && cl[j] == pl)) continue;
       const int4 inf = P.vinfo[nb[j]];
-      const uint64_t kv = pack_key(inf.z, nb[j]);
+      const uint64_t kv = pack_key(inf.z, inf.w);
       int rank = 0;
       for (int32_t k1 = a; k1 < b; k1 += kRB) {
         int32_t w[kRB];
         load_batch(P.colidx, k1, b, u, w);
         uint32_t cw[kRB];
-        int32_t dw[kRB];
+        int2 dw[kRB];
 #pragma unroll
         for (int i = 0; i < kRB; ++i) cw[i] = ld_relaxed(&P.claim[w[i]]);
 #pragma unroll
-        for (int i = 0; i < kRB; ++i) dw[i] = P.vinfo[w[i]].z;
+        for (int i = 0; i < kRB; ++i) dw[i] = reinterpret_cast<const int2*>(P.vinfo + w[i])[1];
 #pragma unroll
         for (int i = 0; i < kRB; ++i)
-          rank += (w[i] != u && cw[i] == pl && pack_key(dw[i], w[i]) < kv) ? 1 : 0;
+          rank += (w[i] != u && cw[i] == pl && pack_key(dw[i].x, dw[i].y) < kv) ? 1 : 0;
       }
       const int32_t at = base + rank;
       if (at < end) st_rec(&P.qi[at], record(nb[j], inf));
@@ -1589,7 +1600,7 @@ __device__ __forceinline__ bool lds_label_levels(const BfsParams& P, Team& t, Sh
     if (c > 0) {
       uint64_t key[kRB];
 #pragma unroll
-      for (int j = 0; j < kRB; ++j) key[j] = (ch >> j & 1u) ? pack_key(inf[j].z, nb[j]) : kMaxKey;
+      for (int j = 0; j < kRB; ++j) key[j] = (ch >> j & 1u) ? pack_key(inf[j].z, inf[j].w) : kMaxKey;
       const int32_t base = cur_e + ex;
 #pragma unroll
       for (int j = 0; j < kRB; ++j) {
@@ -1745,7 +1756,7 @@ __device__ __forceinline__ void global_label_level(const BfsParams& P, Team& t, 
       uint64_t key[kRB];
 #pragma unroll
       for (int j = 0; j < kRB; ++j)
-        key[j] = (cmask >> j & 1u) ? pack_key(cinf[j].z, cnb[j]) : kMaxKey;
+        key[j] = (cmask >> j & 1u) ? pack_key(cinf[j].z, cinf[j].w) : kMaxKey;
 #pragma unroll
       for (int j = 0; j < kRB; ++j) {
         if (!(cmask >> j & 1u)) continue;
@@ -1870,7 +1881,7 @@ __device__ __forceinline__ void global_label_level(const BfsParams& P, Team& t, 
         uint64_t key[kRB];
 #pragma unroll
         for (int j = 0; j < kRB; ++j)
-          key[j] = (cmask >> j & 1u) ? pack_key(cinf[j].z, cnb[j]) : kMaxKey;
+          key[j] = (cmask >> j & 1u) ? pack_key(cinf[j].z, cinf[j].w) : kMaxKey;
         int32_t at[kRB];
 #pragma unroll
         for (int j = 0; j < kRB; ++j) {
@@ -2024,7 +2035,7 @@ __device__ __forceinline__ int32_t label_pass(const BfsParams& P, Team& t, Share
     uint64_t k = kMaxKey;
     for (int32_t p = lo + threadIdx.x; p < hi; p += B) {
       const int4 r = ld_rec(P, p);
-      const uint64_t kv = pack_key(r.w, r.x);
+      const uint64_t kv = pack_key(r.w, P.relabelled ? P.vinfo[r.x].w : r.x);
       k = kv < k ? kv : k;
     }
     k = wave_min_u64(k);
@@ -2120,23 +2131,55 @@ __device__ __forceinline__ void order_component(const BfsParams& P, Team& t, Sha
   const bool try_async =
       P.async_search != 0 && t.W > 1 && task.index < (1 << 25) &&
       (size < 0 || static_cast<long long>(size) * 8 >= static_cast<long long>(seg_e - seg_b));
+  bool last_async = false;  // the last search pass ran asynchronously
   auto search_pass = [&](int32_t from, int32_t epoch, int parity, int32_t& e, uint64_t& lk,
                          bool find_end) {
+    last_async = false;
     if (try_async && epoch < 64) {
       const uint32_t tag =
           (static_cast<uint32_t>(task.index + 1) << 6) | static_cast<uint32_t>(epoch);
       if (async_bfs_pass(P, t, S, o, end, from, tag, parity, seg_b, seg_e, e, lk, find_end,
-                         found))
+                         found)) {
+        last_async = true;
         return;
+      }
       if (t.aborted) return;
     }
     bfs_pass(P, t, S, o, end, from, epoch, parity, e, lk, find_end, found);
   };
-  search_pass(task.seed, 1, 0, ecc, lastkey, size < 0);
-  if (t.aborted) return;
-  if (size < 0) {
-    size = found - o;
-    end = found;
+  // the vertex of a (degree, id) key: its caller id, renumbered when the
+  // launch runs on a renumbered graph
+  auto key_vertex = [&](uint64_t k) {
+    const int32_t id = static_cast<int32_t>(k & 0xffffffffu);
+    return P.new_of_old != nullptr ? P.new_of_old[id] : id;
+  };
+  if (P.resume && task.size >= 0 && task.index == 0) {
+    // the first level structure ran in an earlier launch (see below)
+    ecc = ld_relaxed(&P.gctl->p1_ecc);
+    lastkey = ld_relaxed(&P.gctl->p1_lastkey);
+  } else {
+    search_pass(task.seed, 1, 0, ecc, lastkey, size < 0);
+    if (t.aborted) return;
+    if (size < 0) {
+      size = found - o;
+      end = found;
+    }
+    // a long component: stop here, so that the library renumbers it in
+    // this structure's level order (its vertices then sit near their
+    // neighbours in memory) and resumes on that copy
+    if (P.relabel_levels > 0 && task.size < 0 && task.index == 0 && P.nseg == 1 &&
+        P.label_mode == 0 && last_async && ecc + 1 >= P.relabel_levels) {
+      if (t.wid == 0 && threadIdx.x == 0) {
+        st_relaxed(&P.gctl->p1_ecc, ecc);
+        st_relaxed(&P.gctl->p1_size, size);
+        __hip_atomic_store(&P.gctl->p1_tag, (static_cast<uint32_t>(task.index + 1) << 6) | 1u,
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&P.gctl->p1_lastkey, static_cast<unsigned long long>(lastkey),
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        st_relaxed(&P.gctl->p1_stop, 1);
+      }
+      return;
+    }
   }
   t.anchor = task.anchor >= 0 ? task.anchor : o + size - 1;
   int32_t r = task.seed;
@@ -2146,7 +2189,7 @@ __device__ __forceinline__ void order_component(const BfsParams& P, Team& t, Sha
   bool labelled = false;
   while (ecc > nlvl) {
     nlvl = ecc;
-    const int32_t v = static_cast<int32_t>(lastkey & 0xffffffffu);  // min degree, last level
+    const int32_t v = key_vertex(lastkey);  // min degree, last level
     ++nbfs;
     r = v;
     if (P.pp_variant == 0 && nbfs >= 3 && P.label_mode == 0) {
@@ -2171,7 +2214,7 @@ __device__ __forceinline__ void order_component(const BfsParams& P, Team& t, Sha
       if (t.aborted) return;
     }
   }
-  const int32_t root = P.pp_variant == 1 ? static_cast<int32_t>(lastkey & 0xffffffffu) : r;
+  const int32_t root = P.pp_variant == 1 ? key_vertex(lastkey) : r;
   // reversal: Cuthill-McKee label t of this component goes to anchor - t
   const int32_t anchor = task.anchor >= 0 ? task.anchor : o + size - 1;
   if (P.label_mode != 0) {
@@ -2192,7 +2235,7 @@ __device__ __forceinline__ void order_component(const BfsParams& P, Team& t, Sha
   }
   if (t.wid == 0 && threadIdx.x == 0) {
     CompResult* res = P.results + task.index;
-    res->root = root;
+    res->root = P.relabelled ? P.vinfo[root].w : root;
     res->nbfs = nbfs;
     res->levels = levels;
     res->size = size;
@@ -2201,7 +2244,8 @@ __device__ __forceinline__ void order_component(const BfsParams& P, Team& t, Sha
   if (P.label_mode != 0) return;  // perm is written by the sort
   const int32_t nthreads = t.W * blockDim.x;
   for (int32_t i = t.wid * blockDim.x + threadIdx.x; i < size; i += nthreads) {
-    const int32_t v = ld_rec(P, o + i).x;
+    const int32_t x = ld_rec(P, o + i).x;
+    const int32_t v = P.relabelled && x >= 0 && x < P.n ? P.vinfo[x].w : x;
     const int32_t pos = anchor - i;
     P.perm[pos] = v;
     if (v >= 0 && v < P.n) P.iperm[v] = pos;

@@ -84,8 +84,18 @@ struct alignas(128) GlobalCtl {
   int32_t error;                 // first error of the launch (rcm_status)
   int32_t diag[8];               // where it was detected: site, component index,
                                  // pass (0 = labelled), level, cur_b, cur_e, end
-  int32_t pad[22];
+  // a launch that stopped after the first level structure of vertex 0's
+  // component so that the library can renumber the graph (BfsParams::
+  // relabel_levels): the structure's eccentricity, its pass tag, and the
+  // minimum (degree, id) key of its last level
+  int32_t p1_stop;
+  int32_t p1_ecc;
+  uint32_t p1_tag;
+  int32_t p1_size;
+  unsigned long long p1_lastkey;
+  int32_t pad[14];
 };
+static_assert(sizeof(GlobalCtl) == 128, "one line");
 
 // Per-segment (per-graph) accumulators filled by the device.
 struct SegStats {
@@ -318,10 +328,29 @@ hipError_t launch_level_order(int32_t n, int32_t max_degree_bits, bool by_degree
 hipError_t launch_exclusive_scan(const int32_t* in, int32_t* out, int32_t count, int32_t* tmp,
                                  int32_t* total_out, hipStream_t s);
 
+// Locality renumbering (rcm_relabel.hip) of the component whose `size`
+// vertices carry the pass tag `tag` and their distance in dkey (an
+// asynchronous level structure with eccentricity ecc): its vertices are
+// renumbered 0 .. size - 1 level by level (in any order within a level),
+// and the component is rebuilt in the new numbering -- rowptr_new
+// (size + 1), colidx_new (its entries), vinfo_new (row begin, row end,
+// degree, caller id) -- with new_of_old (for its vertices; 0 for the
+// others) and old_of_new the two maps; colidx_new holds cap entries.  Scratch: hist and first (ecc + 1
+// int32 each), scan_tmp (n / 4096 + 2 int32); cursor holds n int32.  err is
+// set for a distance outside [0, ecc]; *counted receives the number of
+// tagged vertices (which must equal size).
+hipError_t launch_relabel(const Graph& g, const int4* vinfo, const unsigned long long* dkey,
+                          uint32_t tag, int32_t ecc, int32_t size, int32_t* hist, int32_t* first,
+                          int32_t* cursor, int32_t* scan_tmp, int32_t* new_of_old,
+                          int32_t* old_of_new, int32_t* rowptr_new, int32_t* colidx_new,
+                          int64_t cap, int4* vinfo_new, int32_t* err, int32_t* counted,
+                          hipStream_t s);
+
 struct BfsParams {
   const int32_t* rowptr;
   const int32_t* colidx;
-  const int4* vinfo;  // per vertex: row begin, row end, degree, 0
+  const int4* vinfo;  // per vertex: row begin, row end, degree, the vertex's id in
+                      // the caller's graph (its own number unless relabelled)
   int32_t* visit;
   uint32_t* claim;
   int4* qi;           // per position: vertex, row begin, row end, degree
@@ -356,6 +385,17 @@ struct BfsParams {
   unsigned long long* dkey;   // per vertex: pass tag << 32 | ~distance (asynchronous passes)
   const int32_t* abort_flag;  // the caller's abort flag (coherent host memory), or null
   uint32_t shuffle;           // 0, or the seed of the work-group / task shuffle
+  // Locality renumbering of long components (single graphs): with
+  // relabel_levels > 0, the task of vertex 0's component stops after its
+  // first level structure when that has at least relabel_levels levels and
+  // was asynchronous, leaving its results in GlobalCtl (p1_*).  resume = 1 continues that task from there, and a
+  // relabelled launch runs on the graph renumbered in the structure's order:
+  // new_of_old maps a caller id to its number, vinfo.w back; every
+  // (degree, id) key and every output uses the caller's ids.
+  int32_t relabel_levels;
+  int32_t resume;
+  int32_t relabelled;
+  const int32_t* new_of_old;  // null unless relabelled
 };
 
 // The one-work-group engine for a whole small graph in LDS (rcm_small.hip).

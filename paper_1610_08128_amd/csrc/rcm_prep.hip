@@ -29,8 +29,10 @@ inline int grid_for(int64_t work, int threads, int max_blocks = 8192) {
 // ---------------------------------------------------------------------------
 // Row checks + degree + beta of the input order.
 // ---------------------------------------------------------------------------
-// vinfo[i] = (row begin, row end, degree, 0): one 16-byte record per vertex,
-// read by the traversal in a single load.
+// vinfo[i] = (row begin, row end, degree, i): one 16-byte record per vertex,
+// read by the traversal in a single load (the last field is the vertex's id
+// in the caller's graph, which the (degree, id) keys use; it differs from
+// the vertex's number only in a renumbered graph).
 //
 // A pattern is a set of positions, so a column repeated within a row is a
 // malformed input (rows may come in any order).  Rows of up to kDupRegs
@@ -48,7 +50,7 @@ __global__ void k_validate_scan(int32_t n, int32_t nnz, const int32_t* __restric
     const int32_t a = rowptr[i];
     const int32_t b = rowptr[i + 1];
     if (a < 0 || b < a || b > nnz) {
-      vinfo[i] = make_int4(0, 0, 0, 0);
+      vinfo[i] = make_int4(0, 0, 0, i);
       beta[i] = 0;
       atomicOr(err, 1);
       continue;
@@ -96,7 +98,7 @@ __global__ void k_validate_scan(int32_t n, int32_t nnz, const int32_t* __restric
       }
     }
     if (bad) atomicOr(err, 1);
-    vinfo[i] = make_int4(a, b, d, 0);
+    vinfo[i] = make_int4(a, b, d, i);
     beta[i] = i - mn;
   }
 }

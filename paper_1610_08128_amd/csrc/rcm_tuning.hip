@@ -55,6 +55,7 @@ const Field kFields[] = {
     {"label_team", &rcm_options::label_team},
     {"search_round", &rcm_options::search_round},
     {"mode", &rcm_options::mode},
+    {"relabel_levels", &rcm_options::relabel_levels},
 };
 
 bool parse_class(const char* s, Entry* e) {

@@ -89,6 +89,8 @@ class Options(ctypes.Structure):
         ("shuffle_seed", ctypes.c_int32),
         ("tuning_file", ctypes.c_char_p),
         ("abort_flag", ctypes.c_void_p),
+        ("relabel_levels", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -167,7 +169,7 @@ def make_options(*, pp_variant=0, reverse_mode=0, check_full=False, team_size=0,
                  block_threads=0, small_cutoff=0, narrow_cutoff=0, small_threads=0,
                  max_teams=0, rebalance_levels=0, label_mode=0, async_search=0,
                  label_team=0, search_round=0, mode=0, tuning_file=None, shuffle_seed=0,
-                 abort_flag=None) -> Options:
+                 abort_flag=None, relabel_levels=0) -> Options:
     o = Options()
     o.pp_variant = int(pp_variant)
     o.reverse_mode = int(reverse_mode)
@@ -186,6 +188,7 @@ def make_options(*, pp_variant=0, reverse_mode=0, check_full=False, team_size=0,
     o.mode = int(mode)
     o.tuning_file = tuning_file.encode() if isinstance(tuning_file, str) else tuning_file
     o.shuffle_seed = int(shuffle_seed)
+    o.relabel_levels = int(relabel_levels)
     o.abort_flag = abort_flag.address if isinstance(abort_flag, AbortFlag) else abort_flag
     return o
 
@@ -227,7 +230,7 @@ class AbortFlag:
 
 TUNING_FIELDS = ("team_size", "block_threads", "small_cutoff", "narrow_cutoff", "small_threads",
                  "max_teams", "rebalance_levels", "async_search", "label_team", "search_round",
-                 "mode")
+                 "mode", "relabel_levels")
 
 
 def tuning_options(path: str, n: int, nnz: int, num_graphs: int = 1) -> Dict[str, int]:

@@ -642,3 +642,46 @@ def test_engine_equals_team_kernel(seed):
     b = gpu_order(g, mode=1)
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and a[2] == b[2]
     check(g, mode=2)
+
+
+# Long graphs whose vertex-0 component is renumbered after its first level
+# structure (relabel_levels; forced here with a threshold of 2 levels): the
+# ordering must not change.  On a connected graph the renumbered path must
+# have run; with several components it runs when vertex 0's is large enough
+# for the asynchronous search, and the other components are then ordered in
+# the caller's numbering.
+def _relabel_graphs():
+    return [
+        I.grid2d(16, 4000, seed=1),
+        I.path(30000, seed=2),
+        I.strip_drop(8, 12000, 0.01, seed=3),
+        I.shuffle_rows(I.drop_diagonal(I.grid2d(12, 5000, seed=4)), 5),
+        I.grid3d(10, 10, 600, seed=6),
+        I.add_random_self_loops(I.grid2d(20, 3000, seed=7), 0.3, 7),
+        I.disjoint_union([I.grid2d(10, 3000, seed=8), I.path(500), I.star(6)], seed=9),
+        # vertex 0 in the long component, other components beside it
+        I.disjoint_union([I.grid2d(10, 3000, seed=10), I.path(700, seed=11), I.star(6),
+                          I.path(1), I.grid2d(7, 9, seed=12)]),
+        I.strip_drop(4, 20000, 0.02, seed=13),
+    ]
+
+
+@pytest.mark.parametrize("case", range(9))
+def test_relabelled_long_graphs(case):
+    from paper_1610_08128_amd import rcm
+
+    g = _relabel_graphs()[case]
+    g.name = g.name or f"long{case}"
+    variants = [dict(), dict(pp_variant=1, reverse_mode=1), dict(team_size=16, narrow_cutoff=64),
+                dict(team_size=256, label_team=32, search_round=4)]
+    for v in variants:
+        st = check(g, mode=1, relabel_levels=2, **v)
+        used = rcm.last_timings()["used_mode"]
+        assert used == 3 if st["num_components"] == 1 else used in (1, 3), (g.name, v, used)
+    check(g, mode=1, relabel_levels=-1)
+    assert rcm.last_timings()["used_mode"] == 1
+    # the default threshold (4096 levels) and a level-synchronous first
+    # search, which never renumbers
+    check(g, mode=1)
+    check(g, mode=1, relabel_levels=2, async_search=-1)
+    assert rcm.last_timings()["used_mode"] == 1
