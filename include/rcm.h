@@ -223,23 +223,33 @@ typedef struct {
   int32_t reserved;
 } rcm_options;
 
-/* Human-readable name of a status code (static string). */
+/* Human-readable name of a status code (static string; any int32 value is
+ * accepted).  Library infrastructure: no passage of the paper. */
 const char* rcm_status_string(rcm_status s);
 
-/* Fill *opts with the defaults. */
+/* Fill *opts with the defaults (all zero).  Infrastructure. */
 void rcm_default_options(rcm_options* opts);
 
 /* Device workspace needed by rcm_order_ex for a graph with n vertices and
- * nnz entries (bytes, 256-byte aligned start expected).  Pure host
- * arithmetic; never fails (returns 0 for n <= 0). */
+ * nnz entries (bytes, 256-byte aligned start expected; the same for any
+ * nnz).  Pure host arithmetic; never fails (returns 0 for n <= 0).  Sizing
+ * of this library's state (the per-vertex arrays of the level structures,
+ * claims and the Cuthill-McKee order of Algorithms 2 and 3). */
 size_t rcm_workspace_bytes(int32_t n, int64_t nnz, const rcm_options* opts);
 
 /* Order one graph with default options; internal workspace; no iperm.
+ * The operation of Section I (a permutation P so that P A P^T has a small
+ * bandwidth), computed per Algorithm 2 (pseudo-peripheral vertex),
+ * Algorithm 3 (labelled level-synchronous BFS with SortPerm) and the
+ * reversal of Algorithm 1, one component after another (Section III-B);
+ * the statistics are Section II-A's bandwidth and envelope.
  * perm_out: device int32[n].  stats: host, nullable. */
 rcm_status rcm_order(int32_t n, const int32_t* rowptr, const int32_t* colidx,
                      int32_t* perm_out, rcm_stats* stats, void* stream);
 
-/* Order one graph.  opts may be NULL (defaults).  workspace: device memory of
+/* Order one graph: rcm_order's operation (Section I; Algorithms 1-3) with
+ * the options above (Algorithm 4's pick, the Section VI variants, launch
+ * settings).  opts may be NULL (defaults).  workspace: device memory of
  * at least rcm_workspace_bytes(n, nnz, opts) bytes, or NULL to let the
  * library allocate (stream-ordered) and free it within the call. */
 rcm_status rcm_order_ex(int32_t n, const int32_t* rowptr, const int32_t* colidx,
@@ -267,12 +277,15 @@ rcm_status rcm_order_noalloc(int32_t n, const int32_t* rowptr, const int32_t* co
                              int32_t* perm_out, int32_t* iperm_out, rcm_stats* stats,
                              const rcm_options* opts, void* stream);
 
-/* Device workspace needed by rcm_order_batched (bytes). */
+/* Device workspace needed by rcm_order_batched (bytes): rcm_workspace_bytes
+ * of the graphs' disjoint union plus its globalised CSR.  Infrastructure. */
 size_t rcm_batched_workspace_bytes(int32_t num_graphs, int64_t total_vertices,
                                    int64_t total_nnz, const rcm_options* opts);
 
 /* Order many independent graphs in one call (each exactly as rcm_order_ex
- * would, per graph).
+ * would, per graph): the graphs are ordered as the components of their
+ * disjoint union, which Section III-B's one-RCM-per-component rule makes
+ * equivalent.
  *   vtx_offsets, nnz_offsets: HOST int64[G+1], prefix sums of the graphs'
  *     vertex counts and entry counts (offsets[0] = 0).
  *   rowptr_cat: device int32, graph g's local rowptr (starting at 0, n_g+1
@@ -373,6 +386,8 @@ typedef struct {
                                 reversal and the result statistics; [26, 27]
                                 spare                                          */
 } rcm_timings;
+/* Copy the calling thread's last timings into *out (NULL is ignored).
+ * Diagnostics of this library: no passage of the paper. */
 void rcm_last_timings(rcm_timings* out);
 
 #ifdef __cplusplus
