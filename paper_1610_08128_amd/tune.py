@@ -57,7 +57,11 @@ SMALL_CANDIDATES: List[Dict[str, int]] = (
     [dict(mode=1, team_size=w, block_threads=256, narrow_cutoff=nc, label_team=w)
      for w in (16, 64) for nc in (64, 256)])
 
-BATCH_CANDIDATES: List[Dict[str, int]] = [
+# The first candidate is the library's automatic batch layout (no options:
+# a batch of many large components, none of them very large, gets teams of
+# 4 over every resident work-group); setting team_size or max_teams turns
+# that rule off.
+BATCH_CANDIDATES: List[Dict[str, int]] = [dict()] + [
     dict(small_cutoff=sc, small_threads=st, team_size=w, max_teams=mt)
     for sc in (1 << 15, 1 << 16, 1 << 17)
     for st in (256, 512)
@@ -131,17 +135,19 @@ class TuningTable:
 
 
 def _time_calls(call, reps: int) -> float:
+    """Median wall time of `reps` calls after one warm-up call (the median,
+    not the best: a batched call's time can be bimodal)."""
     import torch
 
     call()
     torch.cuda.synchronize()
-    best = float("inf")
+    times = []
     for _ in range(reps):
         t0 = time.perf_counter()
         call()
         torch.cuda.synchronize()
-        best = min(best, time.perf_counter() - t0)
-    return best
+        times.append(time.perf_counter() - t0)
+    return float(np.median(times))
 
 
 def autotune_single(graphs: Iterable, candidates: Optional[Sequence[Dict[str, int]]] = None,
@@ -184,7 +190,7 @@ def autotune_single(graphs: Iterable, candidates: Optional[Sequence[Dict[str, in
 
 
 def autotune_batched(batches: Iterable, candidates: Optional[Sequence[Dict[str, int]]] = None,
-                     reps: int = 2, table: Optional[TuningTable] = None) -> TuningTable:
+                     reps: int = 5, table: Optional[TuningTable] = None) -> TuningTable:
     """Like autotune_single for batched calls; each batch is a list of
     graphs ordered in one rcm_order_batched call."""
     import torch

@@ -32,7 +32,7 @@ def main(out: str = TABLE) -> str:
     table = tune.autotune_single([inputs.config(0)], candidates=tune.SMALL_CANDIDATES, reps=5,
                                  table=table)
     print(f"2D grid done ({time.time() - t0:.1f} s)", flush=True)
-    table = tune.autotune_batched([inputs.batch_graphs(512, seed=4)], reps=2, table=table)
+    table = tune.autotune_batched([inputs.batch_graphs(512, seed=4)], reps=7, table=table)
     print(f"batch done ({time.time() - t0:.1f} s)", flush=True)
     table.save(out, header="MI355X (gfx950), one GPU; workloads: 128^3 3D grid, 64x64 2D grid, "
                            "512-graph batch\nregenerate: python -m "
