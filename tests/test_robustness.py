@@ -177,6 +177,23 @@ def test_shuffle_seed_keeps_the_ordering(mode):
             assert st == want.stats, (g.name, seed)
 
 
+def test_shuffle_seed_keeps_renumbered_orderings():
+    """The renumbering of long components (forced with a two-level
+    threshold) under shuffled work-group roles and barrier delays."""
+    from paper_1610_08128_amd import rcm
+
+    for g in (I.grid2d(12, 3000, seed=21),
+              I.disjoint_union([I.strip_drop(6, 4000, 0.01, seed=22), I.path(40), I.star(5)])):
+        want = oracle.rcm(g.n, g.rowptr, g.colidx)
+        rp, ci = _dev(g)
+        for seed in (0,) + SEEDS:
+            _say(f"case shuffle renumbered {g.name} n={g.n} seed={seed}")
+            perm, st = rcm.order(rp, ci, mode=1, relabel_levels=2, team_size=32, shuffle_seed=seed)
+            assert rcm.last_timings()["used_mode"] == 3
+            assert np.array_equal(perm.cpu().numpy(), want.perm), (g.name, seed)
+            assert st == want.stats, (g.name, seed)
+
+
 def test_shuffle_seed_keeps_batched_orderings():
     import torch
     from paper_1610_08128_amd import rcm
