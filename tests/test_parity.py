@@ -685,3 +685,26 @@ def test_relabelled_long_graphs(case):
     check(g, mode=1)
     check(g, mode=1, relabel_levels=2, async_search=-1)
     assert rcm.last_timings()["used_mode"] == 1
+
+
+def test_relabelled_tiny_graphs():
+    """The renumbering at its smallest: vertex-0 components of two to a few
+    vertices (eccentricity 1 and up), alone or beside other components.
+    Every case must give the oracle's ordering; the smallest may not
+    renumber at all (their first search's ring is so small that it can fall
+    back to the level-synchronous pass), but most do."""
+    from paper_1610_08128_amd import rcm
+
+    gs = [I.path(2), I.path(3), I.star(5), I.complete(4), I.cycle(5, seed=1),
+          I.disjoint_union([I.path(2), I.path(1), I.star(4)]),
+          I.disjoint_union([I.cycle(7), I.grid2d(3, 4, seed=2)]),
+          I.drop_diagonal(I.grid2d(2, 9, seed=3)), I.path(40, seed=4), I.grid2d(5, 7, seed=5)]
+    renumbered = 0
+    for idx, g in enumerate(gs):
+        g.name = g.name or f"tinyrl{idx}"
+        for v in (dict(), dict(pp_variant=1, reverse_mode=1)):
+            check(g, mode=1, relabel_levels=2, team_size=4, **v)
+            used = rcm.last_timings()["used_mode"]
+            assert used in (1, 3), used
+            renumbered += used == 3
+    assert renumbered >= 6, renumbered
