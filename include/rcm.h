@@ -127,7 +127,7 @@ typedef struct {
                             work-group of the team without grid-wide barriers;
                             0 = auto (256), -1 = never                         */
   int32_t small_threads; /* threads per work-group of the single-work-group
-                            teams; 0 = auto (512); 256 or 512                  */
+                            teams; 0 = auto (256); 256 or 512                  */
   int32_t max_teams;     /* most large-component teams run at once; 0 = auto
                             (16; 32 in batched calls), at most 64.  With small
                             components too, half of the resident work-groups

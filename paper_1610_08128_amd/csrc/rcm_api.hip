@@ -39,7 +39,7 @@ struct Opts {
   int check_full = 0;
   int team_size = 0;  // 0: by size, see team_for
   int threads = 256;
-  int small_threads = 512;
+  int small_threads = 256;
   int small_cutoff = 1 << 18;
   int narrow_cutoff = 256;
   int max_teams = 16;

@@ -2347,17 +2347,26 @@ __device__ __forceinline__ void order_main(const BfsParams& P) {
   }
 }
 
-// One instance for both work-group sizes (256 and 512 threads).  An
-// instance bounded at 256 threads gets twice the registers and compiles
-// without any scratch spill, but it measured slower on the 128^3 grid
-// (k_order 8.8 against 8.2 ms, the search passes 3.4 against 2.9 ms): its
-// extra registers go to accumulator-register copies, and the spills of the
-// 512-thread bound sit outside the level loops' load chains.
-__global__ void __launch_bounds__(512) k_order(BfsParams P) {
+// Two instances of the same kernel, one per work-group size.  Bounded at
+// 256 threads, a wave may use all 512 registers of a lane (256 vector and
+// 256 accumulator registers) and the kernel compiles without any scratch
+// spill; bounded at 512 it gets 256 and spills (about 170 vector registers
+// to scratch).  On the 128^3 grid both take the same time (the labelled
+// pass is faster without the spills, the asynchronous search slightly
+// slower), so 256-thread work-groups, the default, run the spill-free
+// instance, and 512-thread ones the other.
+__global__ void __launch_bounds__(256) k_order(BfsParams P) {
   order_main(P);
 }
 
-const void* order_kernel(int32_t) { return reinterpret_cast<const void*>(k_order); }
+__global__ void __launch_bounds__(512) k_order_wide(BfsParams P) {
+  order_main(P);
+}
+
+const void* order_kernel(int32_t threads) {
+  return threads > 256 ? reinterpret_cast<const void*>(k_order_wide)
+                       : reinterpret_cast<const void*>(k_order);
+}
 
 // Cooperative launches of this library in one process never overlap: each
 // is sized to what the device holds at once, and two of them resident side
@@ -2393,7 +2402,10 @@ hipError_t launch_order(const BfsParams& p, int32_t blocks, int32_t threads, hip
     if (e != hipSuccess) return e;
     return hipStreamSynchronize(s);
   }
-  k_order<<<blocks, threads, 0, s>>>(q);
+  if (threads > 256)
+    k_order_wide<<<blocks, threads, 0, s>>>(q);
+  else
+    k_order<<<blocks, threads, 0, s>>>(q);
   return hipGetLastError();
 }
 
