@@ -57,6 +57,10 @@ MEASURED_TRAFFIC = {
 KERNEL_SOURCES = ("paper_1610_08128_amd/csrc/rcm_bfs.hip",
                   "paper_1610_08128_amd/csrc/rcm_common.hpp")
 
+# The serving sweep (--mode serve) faulted the GPU once at the current
+# kernel sources and the cause is not known, so it refuses to run.
+SERVE_SWEEP_ENABLED = False
+
 
 def kernel_sources_hash() -> str:
     import hashlib
@@ -319,6 +323,12 @@ def run_serve(args):
     from paper_1610_08128_amd import inputs, rcm
     from paper_1610_08128_amd.serve import Server
 
+    if not SERVE_SWEEP_ENABLED:
+        raise SystemExit(
+            "--mode serve is switched off: with the current kernel sources one sweep faulted "
+            "the GPU at about 184 requests/s (two executors, batches growing past 8 requests), "
+            "after the rates up to 97/s had completed, and the cause has not been found; the "
+            "sweep stays off until it is")
     desc = inputs.request_stream(args.serve_pool, 1.0)
     t0 = time.perf_counter()
     pool = [inputs.request_graph(kind, n_t, seed) for (_, kind, n_t, seed) in desc]
