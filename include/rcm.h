@@ -355,7 +355,9 @@ typedef struct {
      engine (1 persistent team kernel, 2 one-work-group LDS engine, 3 the
      team kernel, which renumbered the graph after its first level
      structure: see relabel_levels), the
-     team size, threads per team work-group, labelling sub-team and
+     team size, threads per team work-group (with engine 2: 512 for its
+     bounded-row variant, whose rows hold at most 8 off-diagonal entries,
+     64 for the general one), labelling sub-team and
      asynchronous round length of the launch with teams (0 if none ran), and
      the small-component cutoff.  Shows what a tuning table changed.      */
   int32_t used_mode;

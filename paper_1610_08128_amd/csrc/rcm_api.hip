@@ -203,15 +203,33 @@ Layout make_layout(int64_t n, int64_t nnz, int64_t nseg, bool batched, int teams
 constexpr int kSmallTeams = 1024;
 constexpr int kWideBatchTeam = 4;  // team size of a batch's many-teams layout
 
+// The calling thread's timing events on the current device, created on its
+// first timed call there and kept (creating ten events costs more than a
+// small graph's whole ordering).
+bool thread_events(hipEvent_t** out) {
+  thread_local std::map<int, std::vector<hipEvent_t>> pool;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return false;
+  auto it = pool.find(dev);
+  if (it == pool.end()) {
+    std::vector<hipEvent_t> ev(10);
+    for (auto& x : ev)
+      if (hipEventCreate(&x) != hipSuccess) return false;
+    it = pool.emplace(dev, std::move(ev)).first;
+  }
+  *out = it->second.data();
+  return true;
+}
+
 // Phase timing with HIP events on the call's stream (RCM_TIMING=1).
 // Event slots: 0 start, 1 checks done, 2/3 around the component search,
 // 4 ordering done, 5 statistics done; kernel slots around the launches.
 struct Timer {
   bool on;
   hipStream_t s;
-  hipEvent_t ev[6];
+  hipEvent_t* ev = nullptr;   // 6 phase events, then kev
+  hipEvent_t* kev = nullptr;  // 4 kernel events
   bool used[6] = {false, false, false, false, false, false};
-  hipEvent_t kev[4];
   bool kused[2] = {false, false};
   long long clk[32] = {};
   // allow = false: never (the allocation-free entry point creates no events)
@@ -219,8 +237,8 @@ struct Timer {
     const char* e = std::getenv("RCM_TIMING");
     on = allow && e && e[0] == '1';
     if (on) {
-      for (auto& x : ev) (void)hipEventCreate(&x);
-      for (auto& x : kev) (void)hipEventCreate(&x);
+      on = thread_events(&ev);
+      kev = on ? ev + 6 : nullptr;
     }
   }
   void mark(int slot) {
@@ -260,12 +278,6 @@ struct Timer {
       for (int i = 0; i < 28; ++i) t.phase_ticks[i] = clk[4 + i];
     }
     g_timings = t;
-  }
-  ~Timer() {
-    if (on) {
-      for (auto& x : ev) (void)hipEventDestroy(x);
-      for (auto& x : kev) (void)hipEventDestroy(x);
-    }
   }
 };
 
@@ -798,9 +810,43 @@ namespace {
 // not fit, then one readback of its result.  Returns false when the engine
 // does not apply (level orders, too many vertices, or it declined), having
 // written no output; else true with the call's status in *out.
+// The calling thread's pinned, device-mapped result record: the engine's
+// kernel writes it where the host reads it, so a call needs no copy back.
+// Returns the host view (and the device view in *dev), null if it cannot be
+// allocated.
+SmallResult* thread_result(SmallResult** dev) {
+  thread_local SmallResult* host_view = nullptr;
+  thread_local SmallResult* dev_view = nullptr;
+  if (host_view == nullptr) {
+    void* h = nullptr;
+    if (hipHostMalloc(&h, sizeof(SmallResult),
+                      hipHostMallocMapped | hipHostMallocCoherent | hipHostMallocPortable) !=
+        hipSuccess)
+      return nullptr;
+    void* d = nullptr;
+    if (hipHostGetDevicePointer(&d, h, 0) != hipSuccess || d == nullptr) {
+      (void)hipHostFree(h);
+      return nullptr;
+    }
+    host_view = static_cast<SmallResult*>(h);
+    dev_view = static_cast<SmallResult*>(d);
+  }
+  *dev = dev_view;
+  return host_view;
+}
+
+// RCM_SMALL_ELL=0 keeps the bounded-row engine out (every small graph then
+// takes the general one), for tests of the general engine on meshes.
+bool small_ell_enabled() {
+  const char* e = std::getenv("RCM_SMALL_ELL");
+  return !(e && e[0] == '0');
+}
+
 bool order_small(int32_t n, const int32_t* rowptr, const int32_t* colidx, int32_t* perm_out,
                  int32_t* iperm_out, rcm_stats* stats, const Opts& o, void* workspace,
-                 size_t workspace_bytes, hipStream_t s, bool timing, rcm_status* out) {
+                 size_t workspace_bytes, hipStream_t s, bool timing, rcm_status* out,
+                 int32_t* nnz_seen) {
+  *nnz_seen = -1;
   if (o.label_mode != 0) return false;
   const size_t limit = small_lds_limit();
   if (limit == 0 || small_lds_bytes(n, 0) > limit) return false;
@@ -821,20 +867,25 @@ bool order_small(int32_t n, const int32_t* rowptr, const int32_t* colidx, int32_
   }
   // the single-graph workspace does not depend on the entry count
   const size_t need = make_layout(n, 0, 1, false, kSmallTeams).total;
+  // The result record: the thread's pinned one for a regular call; for the
+  // allocation-free entry point (timing == false) the workspace's first bytes
   SmallResult* res = nullptr;
+  SmallResult* host = timing ? thread_result(&res) : nullptr;
   bool owned = false;
-  if (workspace) {
-    if (workspace_bytes < need) {
-      *out = RCM_ERR_WORKSPACE_TOO_SMALL;
-      return true;
+  if (host == nullptr) {
+    if (workspace) {
+      if (workspace_bytes < need) {
+        *out = RCM_ERR_WORKSPACE_TOO_SMALL;
+        return true;
+      }
+      res = static_cast<SmallResult*>(workspace);
+    } else {
+      if (hipMallocAsync(reinterpret_cast<void**>(&res), sizeof(SmallResult), s) != hipSuccess) {
+        *out = RCM_ERR_OUT_OF_MEMORY;
+        return true;
+      }
+      owned = true;
     }
-    res = static_cast<SmallResult*>(workspace);
-  } else {
-    if (hipMallocAsync(reinterpret_cast<void**>(&res), sizeof(SmallResult), s) != hipSuccess) {
-      *out = RCM_ERR_OUT_OF_MEMORY;
-      return true;
-    }
-    owned = true;
   }
   Timer timer(s, timing);
   SmallJob job{n, -1, rowptr, colidx, perm_out, iperm_out, 0, 0, res};
@@ -849,12 +900,32 @@ bool order_small(int32_t n, const int32_t* rowptr, const int32_t* colidx, int32_
     return true;
   }
   SmallResult h{};
+  auto run_kernel = [&](bool ell) -> bool {
+    const hipError_t e =
+        ell ? launch_small_ell(job, so, s) : launch_small_order(job, nullptr, 1, so, s);
+    if (e != hipSuccess) return false;
+    if (host == nullptr && hipMemcpyAsync(&h, res, sizeof(h), hipMemcpyDeviceToHost, s) !=
+                               hipSuccess)
+      return false;
+    if (hipStreamSynchronize(s) != hipSuccess) return false;
+    if (host != nullptr) std::memcpy(&h, host, sizeof(h));
+    return true;
+  };
   timer.mark(0);
   timer.kmark(0, true);
-  if (launch_small_order(job, nullptr, 1, so, s) != hipSuccess ||
-      hipMemcpyAsync(&h, res, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess ||
-      hipStreamSynchronize(s) != hipSuccess)
-    *out = RCM_ERR_HIP;
+  // the bounded-row engine first where the graph can fit it; it declines
+  // graphs with longer rows, which the general engine then takes
+  const bool try_ell = small_ell_enabled() && small_ell_lds_bytes(n) <= limit;
+  bool ok = true;
+  if (try_ell) {
+    ok = run_kernel(true);
+    g_used[2] = 512;
+  }
+  if (ok && (!try_ell || h.status == kSmallDeclined)) {
+    ok = run_kernel(false);
+    g_used[2] = 64;
+  }
+  if (!ok) *out = RCM_ERR_HIP;
   timer.kmark(0, false);
   timer.mark(5);
   if (owned) {
@@ -865,6 +936,7 @@ bool order_small(int32_t n, const int32_t* rowptr, const int32_t* colidx, int32_
   if (timer.on)
     for (int i = 0; i < 6; ++i) g_timings.phase_ticks[20 + i] = h.ticks[i];
   if (*out != RCM_OK) return true;
+  *nnz_seen = h.nnz;
   if (h.status == kSmallDeclined) return false;
   *out = static_cast<rcm_status>(h.status);
   if (*out == RCM_OK && stats) {
@@ -900,29 +972,42 @@ rcm_status order_single(int32_t n, const int32_t* rowptr, const int32_t* colidx,
   if (n == 0) return RCM_OK;
   if (!rowptr || !perm_out) return RCM_ERR_INVALID_ARGUMENT;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (const char* tf = tuning_path(opts)) {
-    // a tuning table: its entry for this graph's size class supplies every
-    // launch option left at 0 (the entry count needs one readback first)
-    int32_t nnz = 0;
-    HIP_TRY(hipMemcpyAsync(&nnz, rowptr + n, 4, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    rcm_options eff{};
-    if (opts) eff = *opts;
-    if (!tuning_apply(tf, n, nnz < 0 ? 0 : nnz, 1, &eff)) return RCM_ERR_INVALID_ARGUMENT;
-    if (!parse_options(&eff, &o)) return RCM_ERR_INVALID_ARGUMENT;
+  // A tuning table: its entry for this graph's size class supplies every
+  // launch option left at 0.  The class needs the entry count, which the
+  // engine reads itself and the team path reads back anyway, so the table
+  // is applied once that count is known; only the engine choice (an exact
+  // class's mode 1) can undo an engine result.
+  const char* tf = tuning_path(opts);
+  auto tuned = [&](int32_t nnz, rcm_options* eff) -> bool {
+    *eff = opts ? *opts : rcm_options{};
+    return tuning_apply(tf, n, nnz < 0 ? 0 : nnz, 1, eff);
+  };
+  if (tf) {
+    rcm_options probe{};
+    if (!tuned(0, &probe)) return RCM_ERR_INVALID_ARGUMENT;  // unreadable or malformed
   }
   if (o.mode != 1) {
     g_used[0] = 2;
+    int32_t seen = -1;
     if (order_small(n, rowptr, colidx, perm_out, iperm_out, stats, o, workspace,
-                    workspace_bytes, s, timing, &st))
-      return st;
-    if (o.mode == 2) return RCM_ERR_INVALID_ARGUMENT;
+                    workspace_bytes, s, timing, &st, &seen)) {
+      rcm_options eff{};
+      const bool team = tf && o.mode == 0 && st == RCM_OK && seen >= 0 && tuned(seen, &eff) &&
+                        eff.mode == 1;
+      if (!team) return st;
+    } else if (o.mode == 2) {
+      return RCM_ERR_INVALID_ARGUMENT;
+    }
   }
   g_used[0] = 1;
   int32_t ends[2];
   HIP_TRY(hipMemcpyAsync(&ends[0], rowptr, 4, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipMemcpyAsync(&ends[1], rowptr + n, 4, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
+  if (tf) {
+    rcm_options eff{};
+    if (!tuned(ends[1], &eff) || !parse_options(&eff, &o)) return RCM_ERR_INVALID_ARGUMENT;
+  }
   if (ends[0] != 0 || ends[1] < 0) return RCM_ERR_BAD_CSR;
   if (ends[1] > 0 && !colidx) return RCM_ERR_INVALID_ARGUMENT;
   const Layout L = make_layout(n, ends[1], 1, false, kSmallTeams);

@@ -402,7 +402,8 @@ struct BfsParams {
 struct SmallResult {
   int32_t status;  // rcm_status, or kSmallDeclined
   int32_t ncomp, diameter, nbfs, nlevels;
-  int32_t pad[3];
+  int32_t nnz;     // the entry count the kernel read (-1 before it did)
+  int32_t pad[2];
   unsigned long long bw_before, prof_before, bw_after, prof_after, edges;
   long long ticks[6];  // 100 MHz clock: load, row checks, searches, labelled
                        // BFS, reversal, result statistics (diagnostics)
@@ -434,6 +435,11 @@ size_t small_lds_limit();
 // jobs_dev == nullptr: one job, `single`.
 hipError_t launch_small_order(const SmallJob& single, const SmallJob* jobs_dev, int32_t njobs,
                               const SmallOpts& opts, hipStream_t s);
+// The bounded-row variant (rcm_small_ell.hip) for one graph: LDS bytes it
+// needs (0 for n <= 0, SIZE_MAX past its 16-bit ids) and its launch; it
+// declines graphs with a row of more than 8 off-diagonal entries.
+size_t small_ell_lds_bytes(int64_t n);
+hipError_t launch_small_ell(const SmallJob& job, const SmallOpts& opts, hipStream_t s);
 
 // Tuning tables (rcm_tuning.hip): the file named by opts->tuning_file, else
 // by RCM_TUNING_FILE, else none (nullptr).  tuning_apply sets every launch

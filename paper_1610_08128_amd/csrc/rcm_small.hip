@@ -365,6 +365,7 @@ __device__ void order_graph(const SmallJob& J, const SmallOpts& O, char* smem) {
   __shared__ int32_t asym;
   __shared__ int32_t stop;
   SmallResult* R = J.res;
+  if (tid == 0) R->nnz = nnz;
   if (nnz < 0) {
     if (tid == 0) R->status = RCM_ERR_BAD_CSR;
     return;

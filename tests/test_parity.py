@@ -633,6 +633,65 @@ def test_engine_status_codes():
         rcm.ERR_NOT_SYMMETRIC
 
 
+def _max_offdiag(g):
+    rows = np.diff(g.rowptr)
+    if g.n == 0:
+        return 0
+    r = np.repeat(np.arange(g.n), rows)
+    off = np.bincount(r[g.colidx != r], minlength=g.n) if g.colidx.size else np.zeros(g.n)
+    return int(off.max()) if off.size else 0
+
+
+def _bounded_row_graphs():
+    """Graphs whose rows hold at most 8 off-diagonal entries: the bounded-row
+    variant of the engine takes them.  Levels of one vertex (paths) up to
+    several wave-wide chunks (the 66 x 90 grid, the 3D grid), many
+    components, isolated vertices, self loops, shuffled rows, no diagonal."""
+    gs = [g for g in _tiny_graphs() if _max_offdiag(g) <= 8]
+    gs += [I.config(0),
+           I.grid2d(66, 90, seed=11),
+           I.grid3d(18, 18, 18, seed=42),
+           I.shuffle_rows(I.drop_diagonal(I.grid2d(30, 41, seed=3)), 5),
+           I.add_random_self_loops(I.grid3d(9, 10, 11, seed=4), 0.3, 4),
+           I.disjoint_union([I.grid2d(10, 12), I.path(50), I.path(1), I.cycle(30),
+                             I.grid3d(5, 6, 7), I.path(2)], seed=7),
+           I.path(5000, seed=12),
+           I.strip_drop(4, 1200, 0.02, seed=13),
+           I.rgg_patches(3000, 14)]
+    return [g for g in gs if _max_offdiag(g) <= 8]
+
+
+@pytest.mark.parametrize("idx", range(len(_bounded_row_graphs())))
+def test_engine_bounded_rows_both_variants(idx, monkeypatch):
+    """The bounded-row variant (8 waves, rows as sorted 16-byte records,
+    token claims) and the general engine (RCM_SMALL_ELL=0) both give the
+    oracle's ordering and statistics, and each call ran the variant asked
+    for."""
+    from paper_1610_08128_amd import rcm
+
+    g = _bounded_row_graphs()[idx]
+    assert _max_offdiag(g) <= 8
+    for variant, threads in (("1", 512), ("0", 64)):
+        monkeypatch.setenv("RCM_SMALL_ELL", variant)
+        for pp, rev in ((0, 0), (1, 1), (0, 1)):
+            check(g, pp_variant=pp, reverse_mode=rev, mode=2)
+            tm = rcm.last_timings()
+            assert tm["used_mode"] == 2 and tm["used_block_threads"] == threads, (variant, tm)
+        check(I.shuffle_rows(g, idx + 1), mode=2, check_full=True)
+
+
+def test_engine_bounded_rows_declines_long_rows():
+    """A graph with one row of 9 off-diagonal entries goes to the general
+    engine; a row of 8 stays in the bounded-row variant."""
+    from paper_1610_08128_amd import rcm
+
+    for k, threads in ((8, 512), (9, 64)):
+        g = I.disjoint_union([I.star(k + 1), I.grid2d(12, 13, seed=k)], seed=k)
+        assert _max_offdiag(g) == k
+        check(g, mode=2)
+        assert rcm.last_timings()["used_block_threads"] == threads
+
+
 @pytest.mark.parametrize("seed", range(6))
 def test_engine_equals_team_kernel(seed):
     """The two engines agree with each other on the same input (and with the
