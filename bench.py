@@ -747,7 +747,8 @@ def main():
 
     roofline = None
     asynchronous = args.async_search >= 0
-    if k_pp is not None:
+    engine = phases.get("used_mode") == 2
+    if k_pp is not None and not engine:
         kbytes = method_kernel_bytes(g.n, m, k_pp)
         ibytes = order_kernel_bytes(g.n, m, k_pp, asynchronous)
         kavg_s = float(np.mean(kern_ms)) / 1000.0
@@ -797,9 +798,13 @@ def main():
             "pseudo_diameter": st["pseudo_diameter"],
             "bfs_passes": passes_run if passes_run is not None else st["num_bfs"] + 1,
             "method_bfs_passes": st["num_bfs"] + 1,
-            "team_size": args.team_size or (256 if g.n >= (1 << 18) else 64),
-            "block_threads": args.block_threads or 256,
-            "search_passes": "asynchronous" if asynchronous else "level-synchronous",
+            **({"engine": "one-work-group LDS engine, %s (%d threads)" % (
+                    "bounded-row variant" if phases.get("used_block_threads") == 512
+                    else "general variant", phases.get("used_block_threads", 0))}
+               if engine else {
+                "team_size": args.team_size or (256 if g.n >= (1 << 18) else 64),
+                "block_threads": args.block_threads or 256,
+                "search_passes": "asynchronous" if asynchronous else "level-synchronous"}),
         },
         "teps": round(teps, 1),
         "teps_method": round(teps_method, 1),
@@ -814,6 +819,19 @@ def main():
         "cpu_baseline": cpu,
         "matches_oracle": check,
     }
+    if engine:
+        # one work-group with the graph in LDS: the bound is the chain of
+        # dependent LDS round trips of each BFS level, not a device roofline
+        kavg_ms = float(np.mean(kern_ms))
+        levels = st["num_bfs"] * (st["pseudo_diameter"] + 1) if st["num_components"] == 1 else None
+        out["engine_kernel"] = {
+            "avg_launch_ms": round(kavg_ms, 4),
+            "bfs_levels_walked": levels,
+            "us_per_level": round(kavg_ms * 1000.0 / levels, 3) if levels else None,
+            "phase_us_last_step": [round(t / 100.0, 1) for t in phases["phase_ticks"][20:26]],
+            "phase_names": ["load and checks", "row sort", "searches", "labelled BFS",
+                            "reversal", "statistics"],
+        }
     print(json.dumps(out), flush=True)
 
 

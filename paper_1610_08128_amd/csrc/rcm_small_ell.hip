@@ -13,12 +13,14 @@
 //   children in Algorithm 3 are then already in SortPerm's order along its
 //   row: a child's rank among its siblings is the number of children before
 //   it in the row, a popcount.
-// - In a search, a vertex is claimed by writing a (pass, lane, slot) token
-//   into its word and reading it back after the wave's writes; exactly one
-//   writer finds its own token.  This replaces exchange-with-return atomics,
-//   which cost a full LDS round trip each.  The labelled BFS keeps the
-//   minimum claim (Algorithm 3's smallest parent label) with LDS atomic
-//   minimums, read back once.
+// - Every pass claims vertices with LDS atomic minimums that return
+//   nothing, and reads the words back once: in a search the claim is a
+//   (level, lane, slot) token and the lane that finds its own token back
+//   found the vertex; in the labelled BFS it is the parent's label + 1, and
+//   the minimum is Algorithm 3's smallest parent label.  A level is then
+//   three dependent LDS round trips (its queue entries, their rows, the
+//   claims read back) and no exchange-with-return atomics, which cost a
+//   full round trip each.
 // - The bulk phases (loading with the checks, the row sort, the statistics
 //   of the result) run on eight waves; the level loops, whose levels are a
 //   wave wide on such graphs, run on the first wave alone while the others
@@ -40,10 +42,20 @@ constexpr int kEThreads = 512;              // eight waves for the bulk phases
 constexpr int kEWaves = kEThreads / 64;
 constexpr int kSlots = 8;                   // columns per row record
 constexpr uint32_t kNone16 = 0xFFFFu;       // "no label" (16-bit)
-constexpr uint32_t kFreeW = 0xFFFFFFFFu;    // claim word: unclaimed, unstamped
-constexpr uint32_t kStampBit = 0x80000000u; // search stamps: kStampBit | pass << 9 | token
-constexpr uint32_t kDoneW = 0x7FFFFFFFu;    // a vertex of an already ordered component
+// Claim words (every pass claims with atomic minimums): kFreeW unclaimed,
+// kDoneW a vertex of an ordered component, label + 1 in a labelled pass
+// (at most 65,535), and in a search the token
+//   (kPassTop - pass) << 25 | (level + 1) << 9 | lane << 3 | slot.
+// A later search's tokens are smaller than an earlier one's, so a new
+// search finds the component unclaimed without resetting it, and every
+// token is larger than every label claim, so neither does the labelled
+// pass after the searches.  The pass number wraps after kPassTop - 1
+// searches (the claim words are reset then).
+constexpr uint32_t kFreeW = 0xFFFFFFFFu;
+constexpr uint32_t kDoneW = 0u;
 constexpr int kTokBits = 9;                 // token: lane (6 bits) and slot (3 bits)
+constexpr int kPassShift = 25;              // above 16 bits of level + 1
+constexpr uint32_t kPassTop = 127;
 constexpr uint32_t kNoKey = 0xFFFFFFFFu;    // (degree << 16 | id) of no vertex
 
 inline __host__ __device__ size_t al16(size_t x) { return (x + 15) & ~static_cast<size_t>(15); }
@@ -113,7 +125,7 @@ __device__ __forceinline__ int ell_wave_prefix(uint32_t c, int bits, int* total)
 // The first W columns of u's record.
 template <int W>
 __device__ __forceinline__ void load_row(const ELds& L, uint32_t u, uint32_t* nb) {
-  if (W == 8) {
+  if constexpr (W == 8) {
     const uint4 r = L.row[u];
     const uint32_t w[4] = {r.x, r.y, r.z, r.w};
 #pragma unroll
@@ -127,6 +139,27 @@ __device__ __forceinline__ void load_row(const ELds& L, uint32_t u, uint32_t* nb
     nb[1] = r.x >> 16;
     nb[2] = r.y & 0xFFFFu;
     nb[3] = r.y >> 16;
+  }
+}
+
+// Columns [S * sub, S * sub + S) of u's record (S = 1, 2, 4 or 8).
+template <int S>
+__device__ __forceinline__ void load_part(const ELds& L, uint32_t u, uint32_t sub, uint32_t* nb) {
+  if constexpr (S == 8) {
+    load_row<8>(L, u, nb);
+  } else if constexpr (S == 4) {
+    const uint2 r = reinterpret_cast<const uint2*>(L.row)[2 * u + sub];
+    nb[0] = r.x & 0xFFFFu;
+    nb[1] = r.x >> 16;
+    nb[2] = r.y & 0xFFFFu;
+    nb[3] = r.y >> 16;
+  } else if constexpr (S == 2) {
+    const uint32_t r = reinterpret_cast<const uint32_t*>(L.row)[4 * u + sub];
+    nb[0] = r & 0xFFFFu;
+    nb[1] = r >> 16;
+  } else {
+    static_assert(S == 1, "1, 2, 4 or 8 columns");
+    nb[0] = reinterpret_cast<const uint16_t*>(L.row)[8 * u + sub];
   }
 }
 
@@ -144,72 +177,109 @@ __device__ __forceinline__ uint32_t ell_level_key(const ELds& L, int32_t b, int3
   return wave_min_u32(k);
 }
 
+// One level of a search: the vertices ord[fb, fe) claim their neighbours
+// and the vertices they find go to ord[fe + next, ...); returns how many.
+// LPV lanes share a vertex, each taking S of its W columns (a narrow level
+// keeps more lanes busy and each lane's work short); the lanes of a vertex
+// are adjacent, so lane order is the (vertex, column) order.  A vertex is
+// claimed with an LDS atomic minimum of a token (level + 1, lane, slot) and
+// is found by the lane that reads its own token back: a vertex of an
+// earlier level keeps its smaller token, an ordered component's kDoneW (0)
+// stays, and of the lanes reaching a new vertex exactly one holds the
+// minimum.  A level wider than one pass of the wave is taken in chunks; a
+// later chunk's tokens are not larger than an earlier chunk's of the same
+// level, so there each lane first reads the words and claims only unclaimed
+// ones.  With kCheck a neighbour in an ordered component sets badm.
+template <int S, int LPV, bool kCheck>
+__device__ __forceinline__ int32_t ell_search_level(const ELds& L, int32_t n, int32_t fb,
+                                                    int32_t fe, uint32_t lvl,
+                                                    unsigned long long& badm) {
+  constexpr int32_t kPer = 64 / LPV;  // vertices per chunk
+  const uint32_t lane = threadIdx.x;
+  uint32_t* const mine = &L.sink[lane];
+  uint16_t* const mine16 = reinterpret_cast<uint16_t*>(mine);
+  const bool one = fe - fb <= kPer;
+  int32_t next = 0;
+  for (int32_t q = fb; q < fe; q += kPer) {
+    const int32_t i = q + static_cast<int32_t>(lane) / LPV;
+    const bool act = i < fe;
+    const uint32_t u = act ? static_cast<uint32_t>(L.ord[i]) : 0u;
+    uint32_t nb[S];
+    load_part<S>(L, u, lane % LPV, nb);
+    unsigned nbr = 0;  // (bitwise operators throughout: no branches per slot)
+#pragma unroll
+    for (int j = 0; j < S; ++j) nbr |= static_cast<unsigned>(act & (nb[j] != u)) << j;
+    unsigned cand = nbr;
+    if (!one) {
+      // unclaimed in this search: kFreeW or an earlier search's token, all
+      // of them at least the next larger search field
+      const uint32_t unclaimed = ((lvl >> kPassShift) + 1u) << kPassShift;
+      cand = 0;
+#pragma unroll
+      for (int j = 0; j < S; ++j)
+        cand |= (nbr >> j & 1u & static_cast<unsigned>(lds_ld(&L.clm[nb[j]]) >= unclaimed)) << j;
+    }
+#pragma unroll
+    for (int j = 0; j < S; ++j)
+      atomicMin((cand >> j & 1u) ? &L.clm[nb[j]] : mine,
+                lvl | (lane << 3) | static_cast<uint32_t>(j));
+    lds_fence();
+    unsigned win = 0;
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+      const uint32_t back = lds_ld(&L.clm[nb[j]]);
+      win |= (cand >> j & 1u &
+              static_cast<unsigned>(back == (lvl | (lane << 3) | static_cast<uint32_t>(j))))
+             << j;
+      if (kCheck) badm |= __ballot((nbr >> j & 1u) & (back == kDoneW));
+    }
+    int total;
+    const int pre = ell_wave_prefix(static_cast<uint32_t>(__popc(win)), S >= 4 ? (S == 8 ? 4 : 3)
+                                                                            : (S == 2 ? 2 : 1),
+                                    &total);
+    const int32_t base = fe + next + pre;
+    // each vertex is found once per pass, so the positions stay below n;
+    // clamped to the spare entry all the same (the caller's level-end check
+    // reports a count past n)
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+      const int32_t at = base + __popc(win & ((1u << j) - 1u));
+      *((win >> j & 1u) ? &L.ord[at < n ? at : n] : mine16) = static_cast<uint16_t>(nb[j]);
+    }
+    next += total;
+  }
+  lds_fence();
+  return next;
+}
+
 // Unlabelled level structure from root (Algorithm 2's BFS), queue in
-// ord[o, ...), pass number `pass` (1 .. 2^22 - 2).  First wave only.
-template <int W>
+// ord[o, ...), search number pass (1 .. kPassTop - 1).  The component's claim
+// words must be kFreeW or tokens of earlier searches on entry.  With
+// kCheck, a neighbour in an ordered component sets bad; the first search of
+// a component checks, since every later pass must reach the same vertices
+// and read the same rows (a different count sets bad).  First wave only.
+template <int W, bool kCheck>
 __device__ EPass ell_search(const ELds& L, int32_t n, int32_t o, uint32_t root, uint32_t pass,
                             bool& bad) {
-  const uint32_t lane = threadIdx.x;
-  const uint32_t stampw = kStampBit | (pass << kTokBits);
-  if (lane == 0) {
+  const uint32_t passw = (kPassTop - pass) << kPassShift;
+  if (threadIdx.x == 0) {
     L.ord[o] = static_cast<uint16_t>(root);
-    lds_st(&L.clm[root], stampw | ((1u << kTokBits) - 1));
+    lds_st(&L.clm[root], passw | (1u << kTokBits) | ((1u << kTokBits) - 1));
   }
   lds_fence();
   int32_t fb = o, fe = o + 1, ecc = 0;
   unsigned long long badm = 0;
   while (true) {
-    int32_t next = 0;
-    for (int32_t q = fb; q < fe; q += 64) {
-      const int32_t i = q + static_cast<int32_t>(lane);
-      const bool act = i < fe;
-      const uint32_t u = act ? static_cast<uint32_t>(L.ord[i]) : 0u;
-      uint32_t nb[W];
-      load_row<W>(L, u, nb);
-      uint32_t cl[W];
-#pragma unroll
-      for (int j = 0; j < W; ++j) cl[j] = lds_ld(&L.clm[nb[j]]);
-      unsigned cand = 0;
-#pragma unroll
-      for (int j = 0; j < W; ++j) {
-        // (bitwise operators throughout: no short-circuit branches per slot)
-        const bool v = act & (nb[j] != u);
-        const bool done = cl[j] == kDoneW;
-        // a vertex of an ordered component: only an asymmetric pattern
-        // leads there
-        badm |= __ballot(v & done);
-        const bool seen = (cl[j] >> kTokBits) == (stampw >> kTokBits);
-        cand |= static_cast<unsigned>(v & !done & !seen) << j;
-      }
-      uint32_t* const mine = &L.sink[lane];
-#pragma unroll
-      for (int j = 0; j < W; ++j)
-        lds_st((cand >> j & 1u) ? &L.clm[nb[j]] : mine,
-               stampw | (lane << 3) | static_cast<uint32_t>(j));
-      lds_fence();
-      unsigned win = 0;
-#pragma unroll
-      for (int j = 0; j < W; ++j) {
-        const uint32_t back = lds_ld(&L.clm[nb[j]]);
-        win |= (cand >> j & 1u & static_cast<unsigned>(
-                    back == (stampw | (lane << 3) | static_cast<uint32_t>(j))))
-               << j;
-      }
-      int total;
-      const int pre = ell_wave_prefix(static_cast<uint32_t>(__popc(win)), W == 8 ? 4 : 3, &total);
-      const int32_t base = fe + next + pre;
-      // each vertex is found once per pass, so the positions stay below
-      // n; clamped to the spare entry all the same (the level-end check
-      // reports a count past n)
-      uint16_t* const mine16 = reinterpret_cast<uint16_t*>(mine);
-#pragma unroll
-      for (int j = 0; j < W; ++j) {
-        const int32_t at = base + __popc(win & ((1u << j) - 1u));
-        *((win >> j & 1u) ? &L.ord[at < n ? at : n] : mine16) = static_cast<uint16_t>(nb[j]);
-      }
-      next += total;
-    }
-    lds_fence();
+    // tokens of the level being found: (its level + 1) above lane and slot
+    const uint32_t lvl = passw | static_cast<uint32_t>(ecc + 2) << kTokBits;
+    const int32_t width = fe - fb;
+    int32_t next;
+    if (width <= 16)
+      next = ell_search_level<W / 4, 4, kCheck>(L, n, fb, fe, lvl, badm);
+    else if (width <= 32)
+      next = ell_search_level<W / 2, 2, kCheck>(L, n, fb, fe, lvl, badm);
+    else
+      next = ell_search_level<W, 1, kCheck>(L, n, fb, fe, lvl, badm);
     if (next == 0) break;
     fb = fe;
     fe += next;
@@ -228,90 +298,101 @@ __device__ EPass ell_search(const ELds& L, int32_t n, int32_t o, uint32_t root, 
   return r;
 }
 
-// Algorithm 3 from root: labels are the positions ord[o, ...).  Per level
-// every parent claims its neighbours with an LDS atomic minimum of its
-// label; a neighbour whose claim then equals the parent's label is its
-// child, and the children, already in (degree, id) order along the sorted
-// row, go to the parent's first child label plus their rank.  The claim
+// One level of Algorithm 3: the parents ord[b, e) (labels b ..) claim their
+// neighbours with an LDS atomic minimum of their label + 1; a neighbour
+// whose claim then equals a parent's is that parent's child (a vertex
+// labelled earlier keeps its smaller claim, an ordered component's kDoneW
+// (0) stays, and the component's first search has checked that none is a
+// neighbour).  The children, already in (degree, id) order along the sorted
+// row, take the parent's first child label plus their rank, the number of
+// children before them in the row.  Lanes as in ell_search_level (LPV lanes
+// per parent, S columns each: lane order is row order).  Returns the number
+// of children placed at ord[e, ...).
+template <int S, int LPV>
+__device__ __forceinline__ int32_t ell_label_level(const ELds& L, int32_t n, int32_t b,
+                                                   int32_t e) {
+  constexpr int32_t kPer = 64 / LPV;
+  const uint32_t lane = threadIdx.x;
+  uint32_t* const mine = &L.sink[lane];
+  uint16_t* const mine16 = reinterpret_cast<uint16_t*>(mine);
+  // claims of every parent of the level; a one-chunk level keeps its rows
+  // in registers for the count
+  const bool one = e - b <= kPer;
+  uint32_t u1 = 0, nb1[S];
+#pragma unroll
+  for (int j = 0; j < S; ++j) nb1[j] = 0;
+  for (int32_t q = b; q < e; q += kPer) {
+    const int32_t p = q + static_cast<int32_t>(lane) / LPV;
+    const bool act = p < e;
+    const uint32_t u = act ? static_cast<uint32_t>(L.ord[p]) : 0u;
+    uint32_t nb[S];
+    load_part<S>(L, u, lane % LPV, nb);
+#pragma unroll
+    for (int j = 0; j < S; ++j)
+      atomicMin((act & (nb[j] != u)) ? &L.clm[nb[j]] : mine, static_cast<uint32_t>(p) + 1u);
+    if (one) {
+      u1 = u;
+#pragma unroll
+      for (int j = 0; j < S; ++j) nb1[j] = nb[j];
+    }
+  }
+  lds_fence();
+  int32_t placed = 0;
+  for (int32_t q = b; q < e; q += kPer) {
+    const int32_t p = q + static_cast<int32_t>(lane) / LPV;
+    const bool act = p < e;
+    uint32_t u, nb[S];
+    if (one) {
+      u = u1;
+#pragma unroll
+      for (int j = 0; j < S; ++j) nb[j] = nb1[j];
+    } else {
+      u = act ? static_cast<uint32_t>(L.ord[p]) : 0u;
+      load_part<S>(L, u, lane % LPV, nb);
+    }
+    unsigned child = 0;
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+      const uint32_t c2 = lds_ld(&L.clm[nb[j]]);
+      child |= static_cast<unsigned>(act & (nb[j] != u) & (c2 == static_cast<uint32_t>(p) + 1u))
+               << j;
+    }
+    int total;
+    const int pre = ell_wave_prefix(static_cast<uint32_t>(__popc(child)),
+                                    S >= 4 ? (S == 8 ? 4 : 3) : (S == 2 ? 2 : 1), &total);
+    const int32_t base = e + placed + pre;
+    // (a vertex is placed once per pass: positions below n, clamped to the
+    // spare entry all the same)
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+      const int32_t at = base + __popc(child & ((1u << j) - 1u));
+      *((child >> j & 1u) ? &L.ord[at < n ? at : n] : mine16) = static_cast<uint16_t>(nb[j]);
+    }
+    placed += total;
+  }
+  lds_fence();
+  return placed;
+}
+
+// Algorithm 3 from root: labels are the positions ord[o, ...).  The claim
 // words of the component must be kFreeW on entry.  First wave only.
 template <int W>
 __device__ EPass ell_label(const ELds& L, int32_t n, int32_t o, uint32_t root, bool& bad) {
-  const uint32_t lane = threadIdx.x;
-  if (lane == 0) {
+  if (threadIdx.x == 0) {
     L.ord[o] = static_cast<uint16_t>(root);
-    lds_st(&L.clm[root], static_cast<uint32_t>(o));
+    lds_st(&L.clm[root], static_cast<uint32_t>(o) + 1u);
   }
   lds_fence();
   int32_t b = o, e = o + 1, levels = 1;
-  unsigned long long badm = 0;
   while (true) {
-    // claims of every parent of the level; a one-chunk level keeps its rows
-    // in registers for the count
-    const bool one = e - b <= 64;
-    uint32_t u1 = 0, nb1[W];
-#pragma unroll
-    for (int j = 0; j < W; ++j) nb1[j] = 0;
-    for (int32_t q = b; q < e; q += 64) {
-      const int32_t p = q + static_cast<int32_t>(lane);
-      const bool act = p < e;
-      const uint32_t u = act ? static_cast<uint32_t>(L.ord[p]) : 0u;
-      uint32_t nb[W];
-      load_row<W>(L, u, nb);
-      uint32_t cl[W];
-#pragma unroll
-      for (int j = 0; j < W; ++j) cl[j] = lds_ld(&L.clm[nb[j]]);
-#pragma unroll
-      for (int j = 0; j < W; ++j) {
-        const bool v = act & (nb[j] != u);
-        const bool done = cl[j] == kDoneW;
-        badm |= __ballot(v & done);
-        const bool lower = v & !done & (cl[j] > static_cast<uint32_t>(p));
-        atomicMin(lower ? &L.clm[nb[j]] : &L.sink[lane], static_cast<uint32_t>(p));
-      }
-      if (one) {
-        u1 = u;
-#pragma unroll
-        for (int j = 0; j < W; ++j) nb1[j] = nb[j];
-      }
-    }
-    lds_fence();
-    // children: the neighbours whose claim is the parent's label
-    int32_t placed = 0;
-    for (int32_t q = b; q < e; q += 64) {
-      const int32_t p = q + static_cast<int32_t>(lane);
-      const bool act = p < e;
-      uint32_t u, nb[W];
-      if (one) {
-        u = u1;
-#pragma unroll
-        for (int j = 0; j < W; ++j) nb[j] = nb1[j];
-      } else {
-        u = act ? static_cast<uint32_t>(L.ord[p]) : 0u;
-        load_row<W>(L, u, nb);
-      }
-      uint32_t c2[W];
-#pragma unroll
-      for (int j = 0; j < W; ++j) c2[j] = lds_ld(&L.clm[nb[j]]);
-      unsigned child = 0;
-#pragma unroll
-      for (int j = 0; j < W; ++j)
-        child |= static_cast<unsigned>(act & (nb[j] != u) & (c2[j] == static_cast<uint32_t>(p)))
-                 << j;
-      int total;
-      const int pre =
-          ell_wave_prefix(static_cast<uint32_t>(__popc(child)), W == 8 ? 4 : 3, &total);
-      const int32_t base = e + placed + pre;
-      // (a vertex is placed once per pass: positions below n, clamped to
-      // the spare entry all the same)
-      uint16_t* const mine16 = reinterpret_cast<uint16_t*>(&L.sink[lane]);
-#pragma unroll
-      for (int j = 0; j < W; ++j) {
-        const int32_t at = base + __popc(child & ((1u << j) - 1u));
-        *((child >> j & 1u) ? &L.ord[at < n ? at : n] : mine16) = static_cast<uint16_t>(nb[j]);
-      }
-      placed += total;
-    }
-    lds_fence();
+    const int32_t width = e - b;
+    int32_t placed;
+    if (width <= 16)
+      placed = ell_label_level<W / 4, 4>(L, n, b, e);
+    else if (width <= 32)
+      placed = ell_label_level<W / 2, 2>(L, n, b, e);
+    else
+      placed = ell_label_level<W, 1>(L, n, b, e);
     if (placed == 0) break;
     if (e + placed > n) {
       bad = true;
@@ -321,7 +402,6 @@ __device__ EPass ell_label(const ELds& L, int32_t n, int32_t o, uint32_t root, b
     e += placed;
     ++levels;
   }
-  bad |= badm != 0;
   EPass r;
   r.ecc = levels - 1;
   r.key = ell_level_key(L, b, e);
@@ -336,12 +416,12 @@ __device__ __forceinline__ void ell_reset(const ELds& L, int32_t o, int32_t size
   lds_fence();
 }
 
-// Sum of the degrees of ord[o, o + size).  First wave only.
-__device__ __forceinline__ long long ell_degree_sum(const ELds& L, int32_t o, int32_t size) {
-  long long s = 0;
-  for (int32_t i = o + static_cast<int32_t>(threadIdx.x); i < o + size; i += 64)
-    s += L.deg[L.ord[i]];
-  return wave_sum_i64(s);
+// Every claim word back to kFreeW except an ordered component's kDoneW
+// (when the search number wraps).  First wave only.
+__device__ __forceinline__ void ell_reset_all(const ELds& L, int32_t n) {
+  for (int32_t v = static_cast<int32_t>(threadIdx.x); v < n; v += 64)
+    if (lds_ld(&L.clm[v]) != kDoneW) lds_st(&L.clm[v], kFreeW);
+  lds_fence();
 }
 
 struct EAcc {
@@ -357,8 +437,16 @@ __device__ EAcc ell_components(const ELds& L, const SmallJob& J, const SmallOpts
                                long long& t_search, long long& t_label, long long& t_rev) {
   const int lane = threadIdx.x;
   EAcc acc;
-  uint32_t pass = 0;
   int32_t o = 0, s_from = 0;
+  uint32_t pass = 0;  // searches since the claim words were last reset
+  // the next search number, resetting the claim words when it wraps
+  auto next_pass = [&]() -> uint32_t {
+    if (++pass >= kPassTop) {
+      ell_reset_all(L, n);
+      pass = 1;
+    }
+    return pass;
+  };
   uint32_t since_poll = 0;
   // one read of the caller's abort flag per 4096 units of work (a level is
   // one unit, a component 64)
@@ -396,13 +484,9 @@ __device__ EAcc ell_components(const ELds& L, const SmallJob& J, const SmallOpts
       lds_fence();
     } else {
       const long long ts0 = wall_clock64();
-      if (pass + 2 >= (1u << (31 - kTokBits))) {
-        acc.err = RCM_ERR_HIP;  // more passes than stamps (cannot happen below 2^16 vertices)
-        return acc;
-      }
-      EPass r = ell_search<W>(L, n, o, static_cast<uint32_t>(s), ++pass, bad);
+      // (the component's claim words are kFreeW: no pass has touched them)
+      EPass r = ell_search<W, true>(L, n, o, static_cast<uint32_t>(s), next_pass(), bad);
       size = r.count;
-      mc = ell_degree_sum(L, o, size);
       nbfs = 1;
       uint32_t root = static_cast<uint32_t>(s);
       int32_t nlvl = r.ecc - 1;
@@ -420,13 +504,15 @@ __device__ EAcc ell_components(const ELds& L, const SmallJob& J, const SmallOpts
         if (O.pp_variant == 0 && nbfs >= 3) {
           // Algorithm 2 returns v unless this search goes deeper, and
           // Algorithm 3 starts there: this search is the labelled BFS
+          // (after searches the claim words need no reset; after a
+          // labelled pass that went deeper they do)
           const long long tl0 = wall_clock64();
-          ell_reset(L, o, size);
+          if (labelled) ell_reset(L, o, size);
           r = ell_label<W>(L, n, o, v, bad);
           labelled = true;
           tl += wall_clock64() - tl0;
         } else {
-          r = ell_search<W>(L, n, o, v, ++pass, bad);
+          r = ell_search<W, false>(L, n, o, v, next_pass(), bad);
         }
         if (r.count != size) bad = true;
       }
@@ -435,7 +521,6 @@ __device__ EAcc ell_components(const ELds& L, const SmallJob& J, const SmallOpts
       t_label += tl;
       if (!labelled && !__any(bad)) {
         const long long tl0 = wall_clock64();
-        ell_reset(L, o, size);
         r = ell_label<W>(L, n, o, root, bad);
         if (r.count != size) bad = true;
         t_label += wall_clock64() - tl0;
@@ -457,7 +542,9 @@ __device__ EAcc ell_components(const ELds& L, const SmallJob& J, const SmallOpts
       if (J.iperm) J.iperm[x] = at + J.pos_off;
       L.lab[x] = static_cast<uint16_t>(at);
       lds_st(&L.clm[x], kDoneW);
+      mc += L.deg[x];  // the degrees every level structure sums
     }
+    mc = wave_sum_i64(mc);
     lds_fence();
     t_rev += wall_clock64() - tr0;
     acc.ncomp += 1;
@@ -529,7 +616,7 @@ __global__ void __launch_bounds__(kEThreads)
   bool longrow = false;
   long long bw = 0, prof = 0;
   int maxdeg = 0;
-  constexpr int kB = 4;
+  constexpr int kB = 8;
   for (int32_t v0 = tid; v0 < n; v0 += kEThreads * kB) {
     int32_t a[kB], b[kB];
     bool take[kB];
@@ -562,8 +649,8 @@ __global__ void __launch_bounds__(kEThreads)
         const bool me = in & (c[q][j] == v);
         bad |= in & ((c[q][j] < 0) | (c[q][j] >= n));
         self += me ? 1 : 0;
-        selfpos = me & (selfpos > kSlots) ? j : selfpos;
-        mn = in & (c[q][j] < mn) ? c[q][j] : mn;
+        selfpos = (me & (selfpos > kSlots)) ? j : selfpos;
+        mn = (in & (c[q][j] < mn)) ? c[q][j] : mn;
       }
       // a repeated diagonal entry here; repeated off-diagonal ones show up
       // next to each other once the row is sorted

@@ -646,7 +646,8 @@ def _bounded_row_graphs():
     """Graphs whose rows hold at most 8 off-diagonal entries: the bounded-row
     variant of the engine takes them.  Levels of one vertex (paths) up to
     several wave-wide chunks (the 66 x 90 grid, the 3D grid), many
-    components, isolated vertices, self loops, shuffled rows, no diagonal."""
+    components (enough for the search numbers to wrap), isolated vertices,
+    self loops, shuffled rows, no diagonal."""
     gs = [g for g in _tiny_graphs() if _max_offdiag(g) <= 8]
     gs += [I.config(0),
            I.grid2d(66, 90, seed=11),
@@ -657,6 +658,9 @@ def _bounded_row_graphs():
                              I.grid3d(5, 6, 7), I.path(2)], seed=7),
            I.path(5000, seed=12),
            I.strip_drop(4, 1200, 0.02, seed=13),
+           # 200 components of two or three searches each: the search
+           # numbers wrap (every 126 searches) several times
+           I.disjoint_union([I.path(4 + i % 9, seed=i) for i in range(200)], seed=15),
            I.rgg_patches(3000, 14)]
     return [g for g in gs if _max_offdiag(g) <= 8]
 
