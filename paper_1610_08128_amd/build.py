@@ -20,7 +20,7 @@ BUILD_DIR = os.path.join(ROOT, "_build")
 
 SOURCES = ["rcm_prep.hip", "rcm_bfs.hip", "rcm_api.hip", "rcm_server.hip", "rcm_apply.hip",
            "rcm_levelorder.hip", "rcm_noalloc.hip", "rcm_small.hip", "rcm_small_ell.hip", "rcm_tuning.hip",
-           "rcm_relabel.hip"]
+           "rcm_relabel.hip", "rcm_window.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -79,6 +79,13 @@ inline bool abort_set(const Opts& o) {
   return o.abort_flag && __atomic_load_n(o.abort_flag, __ATOMIC_ACQUIRE) != 0;
 }
 
+// RCM_WINDOW=0 keeps the window engine out (renumbered components then go
+// to the team kernel), for tests of that path.
+inline bool window_enabled() {
+  const char* e = std::getenv("RCM_WINDOW");
+  return !(e && e[0] == '0');
+}
+
 // Auto team size of a single graph: all compute units for a large graph
 // (its asynchronous search passes speed up up to one work-group per CU),
 // 64 for a smaller one, whose narrow levels only pay for more barrier slots.
@@ -518,9 +525,9 @@ rcm_status run(const Graph& gin, const int32_t* seg_off_host, const Opts& opt, c
     if (st != RCM_OK) return st;
     int32_t hres[8];
     HIP_TRY(hipMemcpyAsync(hres, results, sizeof(CompResult), hipMemcpyDeviceToHost, s));
-    // error, diag[8], p1_stop, p1_ecc, p1_tag, p1_size
-    int32_t gc[13];
-    st = read_ints(gc, &gctl->error, 13, s);
+    // error, diag[8], p1_stop, p1_ecc, p1_tag, p1_size, p1_lastkey (two words)
+    int32_t gc[15];
+    st = read_ints(gc, &gctl->error, 15, s);
     if (st != RCM_OK) return st;
     if (gc[0]) report_device_error(gctl, s);
     if (gc[0] == RCM_ERR_NOT_SYMMETRIC) return RCM_ERR_NOT_SYMMETRIC;
@@ -555,25 +562,69 @@ rcm_status run(const Graph& gin, const int32_t* seg_off_host, const Opts& opt, c
                        h[1], size1);
         return RCM_ERR_NOT_SYMMETRIC;
       }
-      long long clk_first[32];
-      std::memcpy(clk_first, timer.clk, sizeof(clk_first));
-      const CompTask rt{0, size1, 0, 0, ht.anchor};
-      HIP_TRY(hipMemcpyAsync(t_big, &rt, sizeof(rt), hipMemcpyHostToDevice, s));
-      int32_t* visit2 = csize;  // free again once the renumbering is built
-      HIP_TRY(hipMemsetAsync(visit2, 0, 4 * N, s));
-      const BfsParams saved = P;
-      P.colidx = colidx_new;
-      P.rowptr = rowptr_new;
-      P.vinfo = vinfo_new;
-      P.visit = visit2;
-      P.new_of_old = sizes;
-      P.relabelled = 1;
-      P.resume = 1;
-      st = launch(t_big, 1, nullptr, 0, 1, true);
-      P = saved;
-      if (st != RCM_OK) return st;
-      if (timer.on)
-        for (int i = 0; i < 32; ++i) timer.clk[i] += clk_first[i];
+      // First the window engine: one work-group walks the remaining
+      // passes from LDS along the renumbered ids.  It declines a component
+      // whose rows or levels do not fit it, and the team kernel then
+      // resumes the ordering on the renumbered copy.
+      bool windowed = false;
+      if (window_enabled()) {
+        unsigned long long lastkey1 = 0;
+        std::memcpy(&lastkey1, &gc[13], sizeof(lastkey1));
+        WinParams W{};
+        W.n = g.n;
+        W.size = size1;
+        W.colidx = colidx_new;
+        W.vinfo = vinfo_new;
+        W.new_of_old = sizes;
+        // (the team kernel's records, 16 bytes a vertex, are free here: the
+        // row records take 8, the order 4; the first structure's distance
+        // words, read by the renumbering, hold the claims)
+        W.ell = reinterpret_cast<uint2*>(ws + L.qi);
+        W.order = reinterpret_cast<int32_t*>(ws + L.qi + 8 * static_cast<size_t>(size1));
+        W.ell_flag = misc + 14;
+        W.claim = reinterpret_cast<uint32_t*>(P.dkey);
+        W.ecc1 = ecc1;
+        W.lastkey1 = lastkey1;
+        W.pp_variant = opt.pp_variant;
+        W.anchor = ht.anchor >= 0 ? ht.anchor : size1 - 1;
+        W.perm = perm_out;
+        W.iperm = iperm;
+        W.result = results;
+        W.status = misc + 15;
+        W.abort_flag = opt.abort_dev;
+        if (abort_set(opt)) return RCM_ERR_ABORTED;
+        HIP_TRY(launch_window_order(W, s));
+        int32_t wst = 0;
+        st = read_ints(&wst, misc + 15, 1, s);
+        if (st != RCM_OK) return st;
+        if (wst == RCM_ERR_NOT_SYMMETRIC) return RCM_ERR_NOT_SYMMETRIC;
+        if (wst == RCM_ERR_ABORTED) return RCM_ERR_ABORTED;
+        windowed = wst == 0;
+        // declined: the team kernel's distance words start below every pass
+        // tag again
+        if (!windowed) HIP_TRY(hipMemsetAsync(P.dkey, 0, 8 * static_cast<size_t>(g.n), s));
+      }
+      if (!windowed) {
+        long long clk_first[32];
+        std::memcpy(clk_first, timer.clk, sizeof(clk_first));
+        const CompTask rt{0, size1, 0, 0, ht.anchor};
+        HIP_TRY(hipMemcpyAsync(t_big, &rt, sizeof(rt), hipMemcpyHostToDevice, s));
+        int32_t* visit2 = csize;  // free again once the renumbering is built
+        HIP_TRY(hipMemsetAsync(visit2, 0, 4 * N, s));
+        const BfsParams saved = P;
+        P.colidx = colidx_new;
+        P.rowptr = rowptr_new;
+        P.vinfo = vinfo_new;
+        P.visit = visit2;
+        P.new_of_old = sizes;
+        P.relabelled = 1;
+        P.resume = 1;
+        st = launch(t_big, 1, nullptr, 0, 1, true);
+        P = saved;
+        if (st != RCM_OK) return st;
+        if (timer.on)
+          for (int i = 0; i < 32; ++i) timer.clk[i] += clk_first[i];
+      }
       HIP_TRY(hipMemcpyAsync(hres, results, sizeof(CompResult), hipMemcpyDeviceToHost, s));
       st = read_ints(gc, &gctl->error, 1, s);
       if (st != RCM_OK) return st;
@@ -582,7 +633,7 @@ rcm_status run(const Graph& gin, const int32_t* seg_off_host, const Opts& opt, c
       if (gc[0]) return RCM_ERR_ABORTED;
       // the other components claim in the caller's numbering from scratch
       if (size1 < g.n) HIP_TRY(hipMemsetAsync(claim, 0xFF, 4 * N, s));
-      g_used[0] = 3;  // the team kernel on the renumbered component
+      g_used[0] = windowed ? 4 : 3;  // the window engine / the team kernel, renumbered
     }
     head_size = hres[4];
     if (head_size < 1 || head_size > g.n) return RCM_ERR_HIP;

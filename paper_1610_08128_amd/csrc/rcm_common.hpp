@@ -435,6 +435,32 @@ size_t small_lds_limit();
 // jobs_dev == nullptr: one job, `single`.
 hipError_t launch_small_order(const SmallJob& single, const SmallJob* jobs_dev, int32_t njobs,
                               const SmallOpts& opts, hipStream_t s);
+// The window engine (rcm_window.hip): the remaining passes of a long
+// component after its renumbering, by one work-group.  ids are the
+// renumbered ones (0 .. size - 1).
+constexpr int32_t kWindowDeclined = 1;  // *status when the team kernel must take over
+struct WinParams {
+  int32_t n;                      // vertices of the caller's graph
+  int32_t size;                   // vertices of the renumbered component
+  const int32_t* colidx;          // renumbered rows (entries of vinfo[x].x .. .y)
+  const int4* vinfo;              // (row begin, row end, degree, caller id)
+  const int32_t* new_of_old;      // caller id -> renumbered id
+  uint2* ell;                     // [size] row records the launch builds (workspace)
+  int32_t* ell_flag;              // set when a row does not fit its record
+  uint32_t* claim;                // [size] claim words (workspace), the window's store
+  int32_t* order;                 // [size] the labelled order (workspace)
+  int32_t ecc1;                   // the first level structure: eccentricity ...
+  unsigned long long lastkey1;    // ... and its last level's minimum (degree, caller id)
+  int32_t pp_variant;
+  int32_t anchor;                 // Cuthill-McKee label t goes to position anchor - t
+  int32_t* perm;                  // caller-id space
+  int32_t* iperm;                 // nullable
+  CompResult* result;             // the component's result record
+  int32_t* status;                // 0, kWindowDeclined, RCM_ERR_NOT_SYMMETRIC or RCM_ERR_ABORTED
+  const int32_t* abort_flag;      // device view of the caller's abort flag, or null
+};
+hipError_t launch_window_order(const WinParams& P, hipStream_t s);
+
 // The bounded-row variant (rcm_small_ell.hip) for one graph: LDS bytes it
 // needs (0 for n <= 0, SIZE_MAX past its 16-bit ids) and its launch; it
 // declines graphs with a row of more than 8 off-diagonal entries.

@@ -2,6 +2,7 @@
 oracle's bit for bit (the ordering is integer work; every tie is broken by a
 fixed rule, so the result is unique)."""
 
+import os
 import sys
 
 import numpy as np
@@ -730,17 +731,24 @@ def _relabel_graphs():
 
 
 @pytest.mark.parametrize("case", range(9))
-def test_relabelled_long_graphs(case):
+@pytest.mark.parametrize("window", ["1", "0"])
+def test_relabelled_long_graphs(case, window, monkeypatch):
+    """With the window engine (rows of at most 4 off-diagonal entries; it
+    declines the others, and the team kernel resumes) and without it
+    (RCM_WINDOW=0: the team kernel on the renumbered copy)."""
     from paper_1610_08128_amd import rcm
 
+    monkeypatch.setenv("RCM_WINDOW", window)
     g = _relabel_graphs()[case]
     g.name = g.name or f"long{case}"
     variants = [dict(), dict(pp_variant=1, reverse_mode=1), dict(team_size=16, narrow_cutoff=64),
                 dict(team_size=256, label_team=32, search_round=4)]
+    renumbered = (3, 4) if window == "1" else (3,)
     for v in variants:
         st = check(g, mode=1, relabel_levels=2, **v)
         used = rcm.last_timings()["used_mode"]
-        assert used == 3 if st["num_components"] == 1 else used in (1, 3), (g.name, v, used)
+        assert used in renumbered if st["num_components"] == 1 else used in (1,) + renumbered, \
+            (g.name, v, used)
     check(g, mode=1, relabel_levels=-1)
     assert rcm.last_timings()["used_mode"] == 1
     # the default threshold (4096 levels) and a level-synchronous first
@@ -762,12 +770,39 @@ def test_relabelled_tiny_graphs():
           I.disjoint_union([I.path(2), I.path(1), I.star(4)]),
           I.disjoint_union([I.cycle(7), I.grid2d(3, 4, seed=2)]),
           I.drop_diagonal(I.grid2d(2, 9, seed=3)), I.path(40, seed=4), I.grid2d(5, 7, seed=5)]
-    renumbered = 0
+    renumbered = windowed = 0
     for idx, g in enumerate(gs):
         g.name = g.name or f"tinyrl{idx}"
         for v in (dict(), dict(pp_variant=1, reverse_mode=1)):
-            check(g, mode=1, relabel_levels=2, team_size=4, **v)
-            used = rcm.last_timings()["used_mode"]
-            assert used in (1, 3), used
-            renumbered += used == 3
-    assert renumbered >= 6, renumbered
+            for window in ("1", "0"):
+                os.environ["RCM_WINDOW"] = window
+                try:
+                    check(g, mode=1, relabel_levels=2, team_size=4, **v)
+                finally:
+                    os.environ.pop("RCM_WINDOW")
+                used = rcm.last_timings()["used_mode"]
+                assert used in ((1, 3, 4) if window == "1" else (1, 3)), used
+                renumbered += used in (3, 4)
+                windowed += used == 4
+    assert renumbered >= 12, renumbered
+    assert windowed >= 4, windowed
+
+
+def test_window_engine_runs_and_declines():
+    """Long components with rows of at most 4 off-diagonal entries take the
+    window engine (used_mode 4), also when it must slide its window many
+    times (the path and the strips are far longer than the window) and when
+    its levels take several passes of the wave; a
+    component with longer rows (a 3D grid) goes back to the team kernel
+    (used_mode 3); both give the oracle's ordering."""
+    from paper_1610_08128_amd import rcm
+
+    # (grid2d(100, 2000) in its natural numbering: vertex 0 at a corner, so
+    # the later searches' levels -- up to 100 wide, two passes of the wave
+    # -- each lie within one level of the renumbering)
+    for g, want in ((I.path(30000, seed=2), 4), (I.strip_drop(8, 12000, 0.01, seed=3), 4),
+                    (I.grid2d(40, 3000, seed=8), 4), (I.grid2d(100, 2000), 4),
+                    (I.grid3d(10, 10, 600, seed=6), 3)):
+        for v in (dict(), dict(pp_variant=1, reverse_mode=1)):
+            check(g, mode=1, relabel_levels=2, **v)
+            assert rcm.last_timings()["used_mode"] == want, (g.name, v)

@@ -189,7 +189,7 @@ def test_shuffle_seed_keeps_renumbered_orderings():
         for seed in (0,) + SEEDS:
             _say(f"case shuffle renumbered {g.name} n={g.n} seed={seed}")
             perm, st = rcm.order(rp, ci, mode=1, relabel_levels=2, team_size=32, shuffle_seed=seed)
-            assert rcm.last_timings()["used_mode"] == 3
+            assert rcm.last_timings()["used_mode"] in (3, 4)
             assert np.array_equal(perm.cpu().numpy(), want.perm), (g.name, seed)
             assert st == want.stats, (g.name, seed)
 
