@@ -354,7 +354,9 @@ typedef struct {
   /* The settings the call used (filled whatever RCM_TIMING says): the
      engine (1 persistent team kernel, 2 one-work-group LDS engine, 3 the
      team kernel, which renumbered the graph after its first level
-     structure: see relabel_levels), the
+     structure: see relabel_levels, 4 the same renumbering, after which one
+     work-group walked the remaining level structures from an LDS window of
+     the renumbered ids; RCM_WINDOW=0 keeps that engine out), the
      team size, threads per team work-group (with engine 2: 512 for its
      bounded-row variant, whose rows hold at most 8 off-diagonal entries,
      64 for the general one), labelling sub-team and

@@ -920,15 +920,17 @@ bool order_small(int32_t n, const int32_t* rowptr, const int32_t* colidx, int32_
   const size_t need = make_layout(n, 0, 1, false, kSmallTeams).total;
   // The result record: the thread's pinned one for a regular call; for the
   // allocation-free entry point (timing == false) the workspace's first bytes
+  // (a caller's workspace must hold what the call documents whatever part
+  // of it the call uses)
+  if (workspace && workspace_bytes < need) {
+    *out = RCM_ERR_WORKSPACE_TOO_SMALL;
+    return true;
+  }
   SmallResult* res = nullptr;
   SmallResult* host = timing ? thread_result(&res) : nullptr;
   bool owned = false;
   if (host == nullptr) {
     if (workspace) {
-      if (workspace_bytes < need) {
-        *out = RCM_ERR_WORKSPACE_TOO_SMALL;
-        return true;
-      }
       res = static_cast<SmallResult*>(workspace);
     } else {
       if (hipMallocAsync(reinterpret_cast<void**>(&res), sizeof(SmallResult), s) != hipSuccess) {
