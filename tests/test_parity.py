@@ -152,8 +152,15 @@ def test_grid_128_cubed(team, threads, narrow):
 
 
 def test_strip_32x500000():
+    """The strip at full size: renumbered after its first level structure
+    and finished by the window engine (used_mode 4), both variants."""
+    from paper_1610_08128_amd import rcm
+
     g = I.config(2)
     check(g)
+    assert rcm.last_timings()["used_mode"] == 4
+    check(g, pp_variant=1, reverse_mode=1)
+    assert rcm.last_timings()["used_mode"] == 4
 
 
 @pytest.mark.parametrize("case", range(4))
