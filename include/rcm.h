@@ -234,7 +234,8 @@ void rcm_default_options(rcm_options* opts);
  * nnz entries (bytes, 256-byte aligned start expected; the same for any
  * nnz).  Pure host arithmetic; never fails (returns 0 for n <= 0).  Sizing
  * of this library's state (the per-vertex arrays of the level structures,
- * claims and the Cuthill-McKee order of Algorithms 2 and 3). */
+ * claims and the Cuthill-McKee order of Algorithms 2 and 3, and a 32-byte
+ * copy of each row for graphs whose rows have at most 8 entries). */
 size_t rcm_workspace_bytes(int32_t n, int64_t nnz, const rcm_options* opts);
 
 /* Order one graph with default options; internal workspace; no iperm.
@@ -269,7 +270,7 @@ rcm_status rcm_order_ex(int32_t n, const int32_t* rowptr, const int32_t* colidx,
  * device allocation or free and creates no HIP events (RCM_TIMING is
  * ignored).  Arguments as for rcm_order_ex (opts nullable, iperm_out
  * nullable).  Errors: RCM_ERR_WORKSPACE_TOO_SMALL when the graph needs
- * more workspace than the array holds (about 1.4 million vertices at
+ * more workspace than the array holds (about 1.2 million vertices at
  * 7 entries per row); RCM_ERR_HIP when the array's address cannot be
  * obtained.  The calls of one process on one device share the array and
  * are serialised by the library; every call initialises what it uses. */

@@ -79,6 +79,13 @@ inline bool abort_set(const Opts& o) {
   return o.abort_flag && __atomic_load_n(o.abort_flag, __ATOMIC_ACQUIRE) != 0;
 }
 
+// RCM_ELL=0 keeps the team kernel on the CSR for graphs whose rows would
+// fit the fixed-stride copy, for tests of both paths.
+inline bool ell_enabled() {
+  const char* e = std::getenv("RCM_ELL");
+  return !(e && e[0] == '0');
+}
+
 // RCM_WINDOW=0 keeps the window engine out (renumbered components then go
 // to the team kernel), for tests of that path.
 inline bool window_enabled() {
@@ -155,6 +162,7 @@ struct Layout {
   size_t sizes, offs, results, t_single, t_small, t_big, scan_blk;
   size_t seg_off, comp_seg_off, segstats, gctl, teams, slots, sub_slots, small_ctl, misc, sched;
   size_t rowptr_g, colidx_g;
+  size_t ell;  // single graphs: the fixed-stride copy of bounded rows (0 = none)
   size_t total;
 };
 
@@ -200,8 +208,10 @@ Layout make_layout(int64_t n, int64_t nnz, int64_t nseg, bool batched, int teams
   if (batched) {
     L.rowptr_g = take(4 * (N + 1));
     L.colidx_g = take(4 * static_cast<size_t>(nnz));
+    L.ell = 0;
   } else {
     L.rowptr_g = L.colidx_g = 0;
+    L.ell = take(4 * kEllWidth * N);
   }
   L.total = off;
   return L;
@@ -358,11 +368,14 @@ rcm_status run(const Graph& gin, const int32_t* seg_off_host, const Opts& opt, c
 
   timer.mark(0);
   // 2. checks, degrees, input bandwidth/profile
-  HIP_TRY(launch_validate_scan(g, vinfo, beta, segstats, misc + 0, misc + 3, s));
-  int32_t h[4];
-  rcm_status st = read_ints(h, misc, 4, s);
+  int4* ell = L.ell != 0 && N > 0 ? reinterpret_cast<int4*>(ws + L.ell) : nullptr;
+  HIP_TRY(launch_validate_scan(g, vinfo, beta, segstats, misc + 0, misc + 3, ell, misc + 6, s));
+  int32_t h[7];
+  rcm_status st = read_ints(h, misc, 7, s);
   if (st != RCM_OK) return st;
   if (h[0]) return RCM_ERR_BAD_CSR;
+  // a row longer than the copy's width: the traversal reads the CSR
+  if (h[6] || !ell_enabled()) ell = nullptr;
   if (h[3]) {
     // rows too long for the scan's own duplicate check
     HIP_TRY(launch_dup_long(g, misc + 0, s));
@@ -412,6 +425,7 @@ rcm_status run(const Graph& gin, const int32_t* seg_off_host, const Opts& opt, c
   P.resume = 0;
   P.relabelled = 0;
   P.new_of_old = nullptr;
+  P.ell = ell;
   // distance words of the asynchronous passes start below every pass tag
   if (opt.async_search) HIP_TRY(hipMemsetAsync(P.dkey, 0, 8 * static_cast<size_t>(g.n), s));
   P.teams = teams;
@@ -619,6 +633,7 @@ rcm_status run(const Graph& gin, const int32_t* seg_off_host, const Opts& opt, c
         P.new_of_old = sizes;
         P.relabelled = 1;
         P.resume = 1;
+        P.ell = nullptr;  // the copy holds the caller's numbering
         st = launch(t_big, 1, nullptr, 0, 1, true);
         P = saved;
         if (st != RCM_OK) return st;

@@ -114,8 +114,14 @@ __device__ __forceinline__ int32_t* kept_row(SharedBuf& u, int32_t i) {
   return reinterpret_cast<int32_t*>(&u) + 4 * kStageCap + kRB * i;
 }
 
+// Asynchronous passes over a graph with a fixed-stride row copy: the rows of
+// the first kORowCap records of each own-frontier buffer, loaded by whoever
+// reached the vertex, alongside its atomic.
+constexpr int kORowCap = 1024;
+
 struct Shared {
   SharedBuf u;
+  int4 orow[2][kORowCap][2];
   int scan[17];
   long long red[16];
   int32_t cnt;
@@ -419,6 +425,21 @@ __device__ __forceinline__ void st_rec(int4* p, int4 r) {
       static_cast<uint32_t>(r.z) | (static_cast<unsigned long long>(static_cast<uint32_t>(r.w)) << 32);
   __hip_atomic_store(q, lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __hip_atomic_store(q + 1, hi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// A compiler-only barrier: loads before it are issued before it (their
+// results are still waited for only where they are used).  No instruction.
+__device__ __forceinline__ void issue_fence() { asm volatile("" ::: "memory"); }
+
+// Row v of the fixed-stride copy (the entries, then v): what load_batch
+// returns for a row of at most kRB entries, in two 16-byte loads whose
+// address needs no row pointer.
+static_assert(kEllWidth == kRB, "a copied row is one register batch");
+__device__ __forceinline__ void ell_row(const int4* __restrict__ ell, int32_t v, int32_t* nb) {
+  const int4 a = ell[2 * static_cast<size_t>(v)];
+  const int4 b = ell[2 * static_cast<size_t>(v) + 1];
+  nb[0] = a.x; nb[1] = a.y; nb[2] = a.z; nb[3] = a.w;
+  nb[4] = b.x; nb[5] = b.y; nb[6] = b.z; nb[7] = b.w;
 }
 
 // A frontier record as read back, clamped into the graph (vertex in [0, n),
@@ -1079,6 +1100,106 @@ __device__ __forceinline__ int32_t ring_pos(int32_t o, int32_t ring, int32_t v) 
   return o + static_cast<int32_t>(static_cast<uint32_t>(v) % static_cast<uint32_t>(ring));
 }
 
+// One step of an asynchronous pass over a graph with a fixed-stride row
+// copy.  A record's row is already in LDS (the first kORowCap records of the
+// own buffer) or at a known address, so the supersede test of the record,
+// the atomics on its neighbours' distance words and the loads of those
+// neighbours' rows are all one round trip; the rows of the neighbours it
+// reaches go into LDS with their records.  A record found superseded has
+// made its atomics by then.  That is harmless: a neighbour w it won at
+// distance du + 1 is adjacent to the record's vertex, whose distance is now
+// below du, so the record that lowered it reaches w with a shorter distance
+// later and expands it from there.  Only the records of a current vertex
+// expand what they reached.
+__device__ __forceinline__ void async_step_ell(const BfsParams& P, Shared& S, int32_t o,
+                                               int32_t ring, int32_t lo, int32_t n_glob,
+                                               int32_t own_n, int cb, uint32_t tag, int32_t room,
+                                               int32_t g_e, int32_t* tail, long long& d_exp,
+                                               long long& d_sup) {
+  const int B = blockDim.x;
+  for (int32_t i = threadIdx.x; i < n_glob + own_n; i += B) {
+    int32_t u, du;
+    int32_t nb[kRB];
+    if (i < n_glob) {
+      const int4 e = ld_rec(P, ring_pos(o, ring, lo + i));
+      u = e.x;
+      du = e.w;
+      ell_row(P.ell, u, nb);
+    } else {
+      const int32_t j = i - n_glob;
+      u = S.u.own[cb][j][0];
+      du = S.u.own[cb][j][3];
+      if (j < kORowCap) {
+        const int4 a = S.orow[cb][j][0];
+        const int4 b = S.orow[cb][j][1];
+        nb[0] = a.x; nb[1] = a.y; nb[2] = a.z; nb[3] = a.w;
+        nb[4] = b.x; nb[5] = b.y; nb[6] = b.z; nb[7] = b.w;
+      } else {
+        ell_row(P.ell, u, nb);
+      }
+    }
+    const unsigned long long mine = dist_key(tag, du);
+    const unsigned long long want = dist_key(tag, du + 1);
+    const unsigned long long cur =
+        __hip_atomic_load(&P.dkey[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // Branch-free, so that every load and atomic is in flight before the
+    // first result is waited for: the row's own vertex (its diagonal entry
+    // and the padding) gets its atomic, which its own word always beats,
+    // and loads vertex 0's row, one cache line for the whole wave, unused.
+    // (rows in plain int arrays, which the compiler keeps in registers;
+    // arrays of int4 it may leave in scratch memory)
+    unsigned long long old[kRB];
+    int32_t rw[kRB][kEllWidth];
+#pragma unroll
+    for (int j = 0; j < kRB; ++j) old[j] = atomicMax(&P.dkey[nb[j]], want);
+#pragma unroll
+    for (int j = 0; j < kRB; ++j) ell_row(P.ell, nb[j] != u ? nb[j] : 0, rw[j]);
+    // a compiler barrier: the row loads are only used behind the
+    // supersede test, and moved there they would start a round trip of
+    // their own
+    issue_fence();
+    if (cur != mine) {
+      ++d_sup;
+      continue;
+    }
+    ++d_exp;
+    unsigned mask = 0;
+#pragma unroll
+    for (int j = 0; j < kRB; ++j) mask |= (old[j] < want ? 1u : 0u) << j;
+    if (mask == 0) continue;
+    const int32_t base = atomicAdd(&S.cnt, __popc(mask));
+    // each reached neighbour's place from the mask alone (no count carried
+    // from one entry to the next, so the rows stay in registers)
+#pragma unroll
+    for (int j = 0; j < kRB; ++j) {
+      if (!(mask >> j & 1u)) continue;
+      const int32_t idx = base + __popc(mask & ((1u << j) - 1u));
+      if (idx < kORowCap) {
+        S.u.own[cb ^ 1][idx][0] = nb[j];
+        S.u.own[cb ^ 1][idx][1] = 0;
+        S.u.own[cb ^ 1][idx][2] = 0;
+        S.u.own[cb ^ 1][idx][3] = du + 1;
+        S.orow[cb ^ 1][idx][0] = make_int4(rw[j][0], rw[j][1], rw[j][2], rw[j][3]);
+        S.orow[cb ^ 1][idx][1] = make_int4(rw[j][4], rw[j][5], rw[j][6], rw[j][7]);
+      } else if (idx < kOwnCap) {
+        S.u.own[cb ^ 1][idx][0] = nb[j];
+        S.u.own[cb ^ 1][idx][1] = 0;
+        S.u.own[cb ^ 1][idx][2] = 0;
+        S.u.own[cb ^ 1][idx][3] = du + 1;
+      } else {
+        // straight into the next round's frontier (its row is reloaded)
+        const int32_t at = atomicAdd(tail, 1);
+        if (at < room) {
+          st_rec(&P.qi[ring_pos(o, ring, g_e + at)], make_int4(nb[j], 0, 0, du + 1));
+        } else {
+          S.ovf = 1;
+        }
+        S.spill = 1;
+      }
+    }
+  }
+}
+
 // One level structure of the component whose label block is [o, end), from
 // `root`, for a team of several work-groups.  Rounds: every work-group
 // expands its share of the frontier and then, for up to `search_round` steps,
@@ -1137,6 +1258,10 @@ __device__ __forceinline__ bool async_bfs_pass(const BfsParams& P, Team& t, Shar
       if (threadIdx.x == 0) S.cnt = 0;
       __syncthreads();
       ++d_steps;
+      if (P.ell != nullptr) {
+        async_step_ell(P, S, o, ring, lo, n_glob, own_n, cb, tag, room, g_e, tail + l3, d_exp,
+                       d_sup);
+      } else {
       for (int32_t i = threadIdx.x; i < n_glob + own_n; i += B) {
         int4 e;
         if (i < n_glob) {
@@ -1196,6 +1321,7 @@ __device__ __forceinline__ bool async_bfs_pass(const BfsParams& P, Team& t, Shar
             ++idx;
           }
         }
+      }
       }
       __syncthreads();
       const int32_t cnt = S.cnt;
@@ -2354,13 +2480,17 @@ __device__ __forceinline__ void order_main(const BfsParams& P) {
 // to scratch).  On the 128^3 grid both take the same time (the labelled
 // pass is faster without the spills, the asynchronous search slightly
 // slower), so 256-thread work-groups, the default, run the spill-free
-// instance, and 512-thread ones the other.
+// instance, and 512-thread ones the other (on the CSR only).
 __global__ void __launch_bounds__(256) k_order(BfsParams P) {
   order_main(P);
 }
 
 __global__ void __launch_bounds__(512) k_order_wide(BfsParams P) {
-  order_main(P);
+  // the fixed-stride row path holds a row per neighbour in registers, which
+  // this instance would spill
+  BfsParams Q = P;
+  Q.ell = nullptr;
+  order_main(Q);
 }
 
 const void* order_kernel(int32_t threads) {

@@ -285,8 +285,11 @@ struct Graph {
 // err: malformed rows (bounds, columns out of range, repeated columns in
 // rows of up to 64 entries); long_rows: set when a row is longer, whose
 // repeated columns launch_dup_long then checks (into err).
+// ell (may be null): the rows' copy of BfsParams::ell, written for every row
+// of at most kEllWidth entries; *wide_rows is raised by any longer row.
 hipError_t launch_validate_scan(const Graph& g, int4* vinfo, int32_t* beta, SegStats* seg,
-                                int32_t* err, int32_t* long_rows, hipStream_t s);
+                                int32_t* err, int32_t* long_rows, int4* ell,
+                                int32_t* wide_rows, hipStream_t s);
 hipError_t launch_dup_long(const Graph& g, int32_t* err, hipStream_t s);
 hipError_t launch_full_check(const Graph& g, int32_t* err_dup, int32_t* err_sym, hipStream_t s);
 // Components of the vertices with skip[v] == 0 (skip may be null: all).
@@ -396,7 +399,14 @@ struct BfsParams {
   int32_t resume;
   int32_t relabelled;
   const int32_t* new_of_old;  // null unless relabelled
+  // Null, or a copy of the rows of a graph whose rows all have at most
+  // kEllWidth entries: row v is ell[2v], ell[2v + 1], its entries in order
+  // and then v itself.  A neighbour's row is then at an address known from
+  // its number alone, so the asynchronous passes load it in the same round
+  // trip as the atomic on the neighbour's distance word.
+  const int4* ell;
 };
+constexpr int kEllWidth = 8;
 
 // The one-work-group engine for a whole small graph in LDS (rcm_small.hip).
 struct SmallResult {

@@ -39,13 +39,17 @@ inline int grid_for(int64_t work, int threads, int max_blocks = 8192) {
 // entries are loaded into registers at once and compared pairwise there;
 // rows of up to kDupShort entries are compared by re-reading the row (from
 // the cache); longer rows raise *long_rows and are checked by k_dup_long.
+// With `ell`, the rows of at most kEllWidth entries are also copied there
+// from the registers (the traversal's fixed-stride copy); a longer row
+// raises *wide_rows, and the copy is then not used.
 constexpr int kDupRegs = 16;
 constexpr int kDupShort = 64;
 
 __global__ void k_validate_scan(int32_t n, int32_t nnz, const int32_t* __restrict__ rowptr,
                                 const int32_t* __restrict__ colidx, int4* __restrict__ vinfo,
                                 int32_t* __restrict__ beta, int32_t* __restrict__ err,
-                                int32_t* __restrict__ long_rows) {
+                                int32_t* __restrict__ long_rows, int4* __restrict__ ell,
+                                int32_t* __restrict__ wide_rows) {
   for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     const int32_t a = rowptr[i];
     const int32_t b = rowptr[i + 1];
@@ -81,7 +85,21 @@ __global__ void k_validate_scan(int32_t n, int32_t nnz, const int32_t* __restric
       for (int j = 0; j < kDupRegs; ++j)
 #pragma unroll
         for (int k = j + 1; k < kDupRegs; ++k) bad |= r[j] == r[k];
+      if (ell != nullptr) {
+        if (len <= kEllWidth) {
+          // the row, then the vertex itself in the unused places
+          static_assert(kEllWidth == 8, "two 16-byte halves a row");
+          int32_t e[8];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) e[j] = j < len ? r[j] : i;
+          ell[2 * static_cast<size_t>(i)] = make_int4(e[0], e[1], e[2], e[3]);
+          ell[2 * static_cast<size_t>(i) + 1] = make_int4(e[4], e[5], e[6], e[7]);
+        } else {
+          atomicOr(wide_rows, 1);
+        }
+      }
     } else {
+      if (ell != nullptr) atomicOr(wide_rows, 1);
       for (int32_t k = a; k < b; ++k) {
         const int32_t c = colidx[k];
         if (c < 0 || c >= n) { bad = true; continue; }
@@ -746,9 +764,10 @@ hipError_t launch_exclusive_scan(const int32_t* in, int32_t* out, int32_t count,
 }
 
 hipError_t launch_validate_scan(const Graph& g, int4* vinfo, int32_t* beta, SegStats* seg,
-                                int32_t* err, int32_t* long_rows, hipStream_t s) {
-  k_validate_scan<<<grid_for(g.n, kThreads), kThreads, 0, s>>>(g.n, g.nnz, g.rowptr, g.colidx,
-                                                                vinfo, beta, err, long_rows);
+                                int32_t* err, int32_t* long_rows, int4* ell,
+                                int32_t* wide_rows, hipStream_t s) {
+  k_validate_scan<<<grid_for(g.n, kThreads), kThreads, 0, s>>>(
+      g.n, g.nnz, g.rowptr, g.colidx, vinfo, beta, err, long_rows, ell, wide_rows);
   if (g.nseg > 1)
     k_check_segments<<<grid_for((static_cast<int64_t>(g.n) + kSegTile - 1) / kSegTile, 1),
                        kThreads, 0, s>>>(g.n, g.nnz, g.rowptr, g.colidx, g.seg_off, g.nseg, err);

@@ -84,7 +84,12 @@ def test_workspace_bytes_is_host_arithmetic():
     b = rcm.workspace_bytes(2000, 10000)
     assert 0 < a < b
     assert a % 256 == 0
-    assert rcm.batched_workspace_bytes(3, 1000, 5000) > a
+    # a single graph's workspace does not depend on its entry count; a
+    # batch's holds the globalised CSR, so it grows with the entries
+    assert rcm.workspace_bytes(1000, 9000) == a
+    c = rcm.batched_workspace_bytes(3, 1000, 5000)
+    assert 0 < c < rcm.batched_workspace_bytes(3, 1000, 9000)
+    assert c % 256 == 0
 
 
 def test_invalid_arguments_need_no_gpu():

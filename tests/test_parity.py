@@ -434,6 +434,66 @@ def test_level_synchronous_grid_128_cubed(team, threads, narrow):
 
 
 # ---------------------------------------------------------------------------
+# The fixed-stride row copy of graphs whose rows have at most 8 entries: the
+# asynchronous search passes load a reached neighbour's row with its atomic
+# ---------------------------------------------------------------------------
+
+def _king_graph(k, m, *, diag, seed):
+    """k x m grid with the 8 king-move neighbours: rows of exactly 8 entries
+    inside (9 with the diagonal), so the copy's width is met exactly or
+    exceeded."""
+    idx = np.arange(k * m, dtype=np.int64).reshape(k, m)
+    us = [idx[:-1, :].ravel(), idx[:, :-1].ravel(), idx[:-1, :-1].ravel(), idx[:-1, 1:].ravel()]
+    vs = [idx[1:, :].ravel(), idx[:, 1:].ravel(), idx[1:, 1:].ravel(), idx[1:, :-1].ravel()]
+    perm = np.random.default_rng(seed).permutation(k * m)
+    return I.from_edges(k * m, np.concatenate(us), np.concatenate(vs), diag=diag, perm=perm,
+                        name=f"king_{k}x{m}_diag{int(diag)}")
+
+
+def _with_hub(g, hub, degree, seed):
+    """g plus edges from `hub` to `degree` random vertices: one row longer
+    than the copy's width, so the copy is not used."""
+    u, v, diag = I._edges_of(g)
+    rng = np.random.default_rng(seed)
+    others = rng.choice(np.setdiff1d(np.arange(g.n), [hub]), size=degree, replace=False)
+    u = np.concatenate([u, np.full(degree, hub, dtype=np.int64)])
+    v = np.concatenate([v, others.astype(np.int64)])
+    return I.from_edges(g.n, u, v, diag=diag, name=f"{g.name}_hub{degree}")
+
+
+def _row_copy_graphs():
+    return [I.grid3d(24, 20, 18, seed=61), I.grid2d(90, 70, seed=62),
+            I.drop_diagonal(I.grid3d(16, 16, 16, seed=63)), I.strip_drop(8, 3000, 0.02, 64),
+            _king_graph(60, 50, diag=False, seed=65), _king_graph(40, 45, diag=True, seed=66),
+            _with_hub(I.grid3d(20, 20, 20, seed=67), 5, 9, 68),
+            I.shuffle_rows(I.grid3d(18, 22, 16, seed=69), 70)]
+
+
+@pytest.mark.parametrize("copy", ["1", "0"])
+def test_row_copy_team_path(copy, monkeypatch):
+    """Parity on the team path with the copy on and off (RCM_ELL): bounded
+    rows (with and without the diagonal, rows of exactly 8 entries, a strip
+    with dropped edges, rows in any order), rows too long for the copy, and
+    launch shapes that make records superseded often (small teams, long
+    rounds, the work-group shuffle)."""
+    monkeypatch.setenv("RCM_ELL", copy)
+    for i, g in enumerate(_row_copy_graphs()):
+        check(g, async_search=1, small_cutoff=1, team_size=2 + i, search_round=1 + 3 * i,
+              shuffle_seed=100 + i)
+        check(g, async_search=1, small_cutoff=1, team_size=64, pp_variant=1, reverse_mode=1,
+              label_mode=i % 3)
+
+
+def test_row_copy_full_size_grid_both_ways(monkeypatch):
+    """The 128^3 grid in the benchmark's launch configuration with and
+    without the copy: the same ordering."""
+    g = I.config(1)
+    for copy in ("1", "0"):
+        monkeypatch.setenv("RCM_ELL", copy)
+        check(g, async_search=1)
+
+
+# ---------------------------------------------------------------------------
 # Rows in any order, rows without a diagonal (the interface promises both)
 # ---------------------------------------------------------------------------
 
