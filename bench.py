@@ -52,7 +52,7 @@ WORKLOADS = {
 # sources at the time of the measurement, so a changed kernel reports null.
 # Summaries with the commands: profiles/k_order_<workload>_hbm_counters.md.
 MEASURED_TRAFFIC = {
-    "grid3d_128x128x128": ("486390ad6f663853", 6150004608),
+    "grid3d_128x128x128": ("0ee195ebd5f66e7d", 5562589014),
 }
 KERNEL_SOURCES = ("paper_1610_08128_amd/csrc/rcm_bfs.hip",
                   "paper_1610_08128_amd/csrc/rcm_common.hpp")
@@ -98,7 +98,8 @@ def method_kernel_bytes(n: int, m: int, k_pp: int) -> int:
     return k_pp * (8 * m + 20 * n) + (8 * m + 48 * n) + 12 * n
 
 
-def order_kernel_bytes(n: int, m: int, k_pp: int, asynchronous: bool = True) -> int:
+def order_kernel_bytes(n: int, m: int, k_pp: int, asynchronous: bool = True,
+                       row_copy: bool = False) -> int:
     """Bytes of the passes the implementation itself runs for one launch of
     the ordering kernel (reported beside the method's figure):
       every unlabelled BFS pass, level-synchronous: 8m + 20n (rowptr 8n,
@@ -108,9 +109,16 @@ def order_kernel_bytes(n: int, m: int, k_pp: int, asynchronous: bool = True) -> 
         component): 12m + 36n (colidx 4m, distance-word atomics 8m; per
         vertex the record gather 16n and the superseded-record check 8n; the
         final sweep reads the distance words 8n and writes the stamps 4n);
+        over the fixed-stride row copy (rows of at most 8 entries): 40m + 20n
+        (per entry the distance-word atomic 8m and the neighbour's 32-byte
+        row 32m, loaded together; per vertex the superseded-record check 8n
+        and the sweep 12n);
       the labelled BFS: 8m + 48n (adds claims, degrees, labels);
       the reversal: 12n (read the order, write perm and iperm)."""
-    per_pass = (12 * m + 36 * n) if asynchronous else (8 * m + 20 * n)
+    if asynchronous and row_copy:
+        per_pass = 40 * m + 20 * n
+    else:
+        per_pass = (12 * m + 36 * n) if asynchronous else (8 * m + 20 * n)
     return unlabelled_passes(k_pp) * per_pass + (8 * m + 48 * n) + 12 * n
 
 
@@ -750,7 +758,11 @@ def main():
     engine = phases.get("used_mode") == 2
     if k_pp is not None and not engine:
         kbytes = method_kernel_bytes(g.n, m, k_pp)
-        ibytes = order_kernel_bytes(g.n, m, k_pp, asynchronous)
+        # the library copies the rows when none has more than 8 entries
+        # (RCM_ELL=0 keeps it on the CSR)
+        row_copy = (int(np.diff(g.rowptr).max(initial=0)) <= 8
+                    and os.environ.get("RCM_ELL", "1")[:1] != "0")
+        ibytes = order_kernel_bytes(g.n, m, k_pp, asynchronous, row_copy)
         kavg_s = float(np.mean(kern_ms)) / 1000.0
         achieved = kbytes / kavg_s / 1e9
         roofline = {
