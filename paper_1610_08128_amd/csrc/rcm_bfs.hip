@@ -132,6 +132,8 @@ struct Shared {
   int32_t spill;                   // own-frontier level: records went to qi
   int32_t total;                   // own-frontier level: next level size
   int32_t nspill;                  // own-frontier level: records in qi
+  int32_t appended;                // asynchronous passes: records this work-group
+                                   // put in the ring this round
 
   int32_t wsum[kMaxTeam];          // slot_exchange: every work-group's count
   int32_t wpre;                    // slot_exchange: this work-group's prefix
@@ -1189,6 +1191,7 @@ __device__ __forceinline__ void async_step_ell(const BfsParams& P, Shared& S, in
       } else {
         // straight into the next round's frontier (its row is reloaded)
         const int32_t at = atomicAdd(tail, 1);
+        atomicAdd(&S.appended, 1);
         if (at < room) {
           st_rec(&P.qi[ring_pos(o, ring, g_e + at)], make_int4(nb[j], 0, 0, du + 1));
         } else {
@@ -1252,6 +1255,7 @@ __device__ __forceinline__ bool async_bfs_pass(const BfsParams& P, Team& t, Shar
     if (threadIdx.x == 0) {
       S.spill = 0;
       S.ovf = 0;
+      S.appended = 0;
     }
     const long long r0 = wall_clock64();
     for (int step = 0; step < P.search_round; ++step) {
@@ -1310,6 +1314,7 @@ __device__ __forceinline__ bool async_bfs_pass(const BfsParams& P, Team& t, Shar
             } else {
               // straight into the next round's frontier
               const int32_t at = atomicAdd(tail + l3, 1);
+              atomicAdd(&S.appended, 1);
               if (at < room) {
                 st_rec(&P.qi[ring_pos(o, ring, g_e + at)], make_int4(nb[j], inf[j].x, inf[j].y,
                                                                      du + 1));
@@ -1336,6 +1341,7 @@ __device__ __forceinline__ bool async_bfs_pass(const BfsParams& P, Team& t, Shar
     if (threadIdx.x == 0) {
       S.base = own_n > 0 ? atomicAdd(tail + l3, own_n) : 0;
       if (own_n > 0) S.spill = 1;
+      S.appended += own_n;
     }
     __syncthreads();
     for (int32_t i = threadIdx.x; i < own_n; i += B) {
@@ -1360,20 +1366,17 @@ __device__ __forceinline__ bool async_bfs_pass(const BfsParams& P, Team& t, Shar
       st_relaxed(tail + (rounds + 1) % 3, 0);
       drain_memory_ops();
     }
-    // payload: a flag for records written, a count of 1 for an overflow
-    slot_exchange(t, S, (wrote ? 0x80000000u : 0u) | (S.ovf ? 1u : 0u), false);
+    // payload: the records this work-group added to the ring (every add,
+    // its own and its spills, went through the tail counter, so the team's
+    // sum is the next frontier's size and the counter need not be read
+    // back), and a flag for an overflow
+    slot_exchange(t, S, (S.ovf ? 0x80000000u : 0u) | static_cast<uint32_t>(S.appended), false);
     if (t.aborted) return true;
-    if (threadIdx.x == 0) {
-      S.nspill = 0;
-      if (S.wspill != 0) S.nspill = ld_relaxed(tail + l3);
-      S.total = S.wtot;
-    }
-    __syncthreads();
-    if (S.total != 0) {
+    if (S.wspill != 0) {
       overflow = true;
       break;
     }
-    const int32_t total = S.nspill;
+    const int32_t total = S.wtot;
     ++rounds;
     d_tbar += wall_clock64() - r1;
     if (total == 0) break;
