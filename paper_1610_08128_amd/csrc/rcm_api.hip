@@ -193,7 +193,9 @@ Layout make_layout(int64_t n, int64_t nnz, int64_t nseg, bool batched, int teams
   L.results = take(sizeof(CompResult) * N);
   L.t_single = take(sizeof(CompTask) * N);
   L.t_small = take(sizeof(CompTask) * N);
-  L.t_big = take(sizeof(CompTask) * N);
+  // (at least 4 KB: the level orders' sort uses the task lists as scratch,
+  // with a fixed part of about 2 KB however small the graph)
+  L.t_big = take(std::max<size_t>(sizeof(CompTask) * N, 4096));
   L.scan_blk = take(4 * (N / 4096 + 2));
   L.seg_off = take(4 * static_cast<size_t>(nseg + 1));
   L.comp_seg_off = take(4 * static_cast<size_t>(nseg + 1));

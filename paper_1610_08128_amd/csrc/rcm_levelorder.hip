@@ -14,10 +14,15 @@
 // of (level, degree, id) inside each block.  Two stable LSD radix sorts
 // produce it, least significant key first: by degree over the vertices in
 // descending id order (global sort only), then by key.
+//
+// The radix sort is this file's own: 8-bit digits; per pass a histogram of
+// every 2,048-element tile, one exclusive scan over the histograms laid out
+// digit-major (so a digit's tiles follow each other), and a stable scatter
+// in which each tile ranks its elements per digit in index order, 256 at a
+// time, from ballots of the digit's bits within a wave and per-wave counts
+// in LDS.
 
 #include <hip/hip_runtime.h>
-
-#include <rocprim/device/device_radix_sort.hpp>
 
 #include "rcm_common.hpp"
 
@@ -64,26 +69,144 @@ __global__ void k_lo_inverse(int32_t n, const int32_t* __restrict__ perm,
     iperm[perm[k]] = k;
 }
 
-hipError_t sort_pairs(void* temp, size_t temp_bytes, const uint32_t* kin, uint32_t* kout,
-                      const int32_t* vin, int32_t* vout, int32_t n, unsigned end_bit,
+// ---- stable LSD radix sort of (uint32 key, int32 value) pairs ----
+constexpr int kDigitBits = 8;
+constexpr int kDigits = 1 << kDigitBits;
+constexpr int kSortThreads = kDigits;  // one thread per digit in the per-digit steps
+constexpr int kSortRounds = 8;         // rounds of kSortThreads elements per tile
+constexpr int kSortTile = kSortThreads * kSortRounds;
+constexpr int kSortWaves = kSortThreads / 64;
+
+inline int32_t sort_tiles(int32_t n) { return (n + kSortTile - 1) / kSortTile; }
+
+// counts[d * tiles + t] = elements of tile t whose digit at `shift` is d.
+__global__ void __launch_bounds__(kSortThreads)
+k_rs_hist(const uint32_t* __restrict__ keys, int32_t n, unsigned shift, int32_t tiles,
+          int32_t* __restrict__ counts) {
+  __shared__ int32_t h[kDigits];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * kSortTile;
+  for (int r = 0; r < kSortRounds; ++r) {
+    const int64_t i = base + r * kSortThreads + threadIdx.x;
+    if (i < n) atomicAdd(&h[(keys[i] >> shift) & (kDigits - 1)], 1);
+  }
+  __syncthreads();
+  counts[static_cast<int64_t>(threadIdx.x) * tiles + blockIdx.x] = h[threadIdx.x];
+}
+
+// Stable scatter of one tile: offs is the exclusive scan of the digit-major
+// histograms, so offs[d * tiles + t] is where tile t's first element of
+// digit d goes.  Within the tile, elements go out in index order: round r
+// takes elements r * 256 .. r * 256 + 255 in thread order; an element's rank
+// is the count of its digit in the earlier waves of the round (per-wave
+// counts in LDS) plus the earlier lanes of its own wave with the same digit
+// (the lanes whose ballots of the eight digit bits all agree with its own).
+__global__ void __launch_bounds__(kSortThreads)
+k_rs_scatter(const uint32_t* __restrict__ kin, const int32_t* __restrict__ vin,
+             uint32_t* __restrict__ kout, int32_t* __restrict__ vout, int32_t n, unsigned shift,
+             int32_t tiles, const int32_t* __restrict__ offs) {
+  __shared__ int32_t base[kDigits];
+  __shared__ int32_t wc[kSortWaves][kDigits];
+  __shared__ int32_t wp[kSortWaves][kDigits];
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6;
+  const int lane = tid & 63;
+  const unsigned long long below = (1ull << lane) - 1ull;
+  base[tid] = offs[static_cast<int64_t>(tid) * tiles + blockIdx.x];
+  const int64_t tile0 = static_cast<int64_t>(blockIdx.x) * kSortTile;
+  for (int r = 0; r < kSortRounds; ++r) {
+#pragma unroll
+    for (int w = 0; w < kSortWaves; ++w) wc[w][tid] = 0;
+    __syncthreads();
+    const int64_t i = tile0 + r * kSortThreads + tid;
+    const bool valid = i < n;
+    const uint32_t k = valid ? kin[i] : 0u;
+    const int32_t v = valid ? vin[i] : 0;
+    const int d = static_cast<int>((k >> shift) & (kDigits - 1));
+    unsigned long long same = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < kDigitBits; ++b) {
+      const bool bit = (d >> b) & 1;
+      const unsigned long long on = __ballot(bit);
+      same &= bit ? on : ~on;
+    }
+    const int rank = __popcll(same & below);
+    if (valid && rank == 0) wc[wave][d] = __popcll(same);
+    __syncthreads();
+    int32_t run = 0;
+#pragma unroll
+    for (int w = 0; w < kSortWaves; ++w) {
+      wp[w][tid] = run;
+      run += wc[w][tid];
+    }
+    __syncthreads();
+    if (valid) {
+      const int32_t at = base[d] + wp[wave][d] + rank;
+      kout[at] = k;
+      vout[at] = v;
+    }
+    __syncthreads();
+    base[tid] += run;
+  }
+}
+
+// Scratch of one sort: the histograms, their scan and the scan's block sums.
+size_t sort_temp_bytes(int32_t n) {
+  const size_t c = static_cast<size_t>(kDigits) * static_cast<size_t>(sort_tiles(n));
+  return 2 * 4 * c + 4 * (c / 1024 + 64);
+}
+
+// Sorts (ka, va) by the key bits [0, end_bit), stably, with (kb, vb) as the
+// other buffers; the sorted values end in vfinal (any of the value buffers
+// or another array), the keys in whichever key buffer the last pass wrote.
+// The last pass writes the values to vfinal directly unless vfinal is that
+// pass's own source, in which case they are copied there after it.
+hipError_t sort_pairs(void* temp, size_t temp_bytes, uint32_t* ka, int32_t* va, uint32_t* kb,
+                      int32_t* vb, int32_t* vfinal, int32_t n, unsigned end_bit,
                       hipStream_t s) {
-  size_t bytes = temp_bytes;
-  return rocprim::radix_sort_pairs(temp, bytes, kin, kout, vin, vout, static_cast<unsigned>(n),
-                                   0u, end_bit, s);
+  if (n <= 0) return hipSuccess;
+  if (temp_bytes < sort_temp_bytes(n)) return hipErrorInvalidValue;
+  const int32_t tiles = sort_tiles(n);
+  const int32_t c = kDigits * tiles;
+  int32_t* counts = static_cast<int32_t*>(temp);
+  int32_t* offs = counts + c;
+  int32_t* blk = offs + c;
+  const unsigned passes = end_bit == 0 ? 1u : (end_bit + kDigitBits - 1) / kDigitBits;
+  uint32_t* kin = ka;
+  int32_t* vin = va;
+  uint32_t* kout = kb;
+  int32_t* vout = vb;
+  for (unsigned p = 0; p < passes; ++p) {
+    const unsigned shift = p * kDigitBits;
+    if (p + 1 == passes && vfinal != vin) vout = vfinal;
+    k_rs_hist<<<tiles, kSortThreads, 0, s>>>(kin, n, shift, tiles, counts);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = launch_exclusive_scan(counts, offs, c, blk, nullptr, s);
+    if (e != hipSuccess) return e;
+    k_rs_scatter<<<tiles, kSortThreads, 0, s>>>(kin, vin, kout, vout, n, shift, tiles, offs);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // the next pass reads what this one wrote
+    uint32_t* kt = kin;
+    int32_t* vt = vin;
+    kin = kout;
+    vin = vout;
+    kout = kt;
+    vout = vt;
+  }
+  if (vin != vfinal)
+    return hipMemcpyAsync(vfinal, vin, sizeof(int32_t) * static_cast<size_t>(n),
+                          hipMemcpyDeviceToDevice, s);
+  return hipSuccess;
 }
 
 }  // namespace
 
 size_t level_order_temp_bytes(int32_t n) {
   if (n <= 0) return 0;
-  size_t bytes = 0;
-  if (rocprim::radix_sort_pairs(nullptr, bytes, static_cast<const uint32_t*>(nullptr),
-                                static_cast<uint32_t*>(nullptr),
-                                static_cast<const int32_t*>(nullptr),
-                                static_cast<int32_t*>(nullptr), static_cast<unsigned>(n), 0u,
-                                32u) != hipSuccess)
-    return 0;
-  return bytes;
+  return sort_temp_bytes(n);
 }
 
 hipError_t launch_level_order(int32_t n, int32_t max_degree_bits, bool by_degree,
@@ -105,14 +228,15 @@ hipError_t launch_level_order(int32_t n, int32_t max_degree_bits, bool by_degree
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (by_degree) {
-    e = sort_pairs(temp, temp_bytes, ka, kb, va, vb, n, deg_bits, s);
+    // by degree into vb, then the keys gathered again in that order
+    e = sort_pairs(temp, temp_bytes, ka, va, kb, vb, vb, n, deg_bits, s);
     if (e != hipSuccess) return e;
     k_lo_gather<<<g, kThreads, 0, s>>>(n, vb, key, ka);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    e = sort_pairs(temp, temp_bytes, ka, kb, vb, perm, n, key_bits, s);
+    e = sort_pairs(temp, temp_bytes, ka, vb, kb, va, perm, n, key_bits, s);
   } else {
-    e = sort_pairs(temp, temp_bytes, ka, kb, va, perm, n, key_bits, s);
+    e = sort_pairs(temp, temp_bytes, ka, va, kb, vb, perm, n, key_bits, s);
   }
   if (e != hipSuccess) return e;
   k_lo_inverse<<<g, kThreads, 0, s>>>(n, perm, iperm);
