@@ -3,16 +3,16 @@
 //
 // Permutation: new row degrees are gathered and scanned into B's row
 // pointer; every row of A is copied to its new place with its columns
-// renamed by iperm; each row is then sorted by a segmented radix sort
-// (rocPRIM) over only as many key bits as n needs.
+// renamed by iperm and sorted: a short row in registers by its thread, a
+// long one afterwards by a work-group of its own (a bitonic sort of
+// (column, position) pairs, in LDS or, for very long rows, in a scratch
+// array).
 // Product: a group of eight lanes per row (rows of meshes hold 5 to 13
 // entries), each lane striding the row, then a reduction across the group.
 
 #include "rcm_apply.h"
 
 #include <hip/hip_runtime.h>
-
-#include <rocprim/device/device_segmented_radix_sort.hpp>
 
 #include "rcm_common.hpp"
 
@@ -30,16 +30,9 @@ inline int grid_for(int64_t work, int threads, int max_blocks = 8192) {
   return static_cast<int>(b);
 }
 
-inline unsigned key_bits(int32_t n) {
-  unsigned b = 1;
-  while (b < 31 && (1ll << b) < n) ++b;
-  return b;
-}
-
 // Workspace regions of rcm_permute.
 struct ApplyLayout {
   size_t deg, blk, keys, vals, sort, total;
-  size_t sort_bytes;
 };
 
 ApplyLayout apply_layout(int32_t n, int64_t nnz, bool with_values) {
@@ -55,22 +48,7 @@ ApplyLayout apply_layout(int32_t n, int64_t nnz, bool with_values) {
   L.blk = take(4 * (N / 4096 + 2));
   L.keys = take(4 * M);
   L.vals = with_values ? take(8 * M) : 0;
-  size_t sort_bytes = 0;
-  const int32_t* off_dummy = nullptr;
-  if (with_values) {
-    (void)rocprim::segmented_radix_sort_pairs(
-        nullptr, sort_bytes, static_cast<const int32_t*>(nullptr), static_cast<int32_t*>(nullptr),
-        static_cast<const double*>(nullptr), static_cast<double*>(nullptr),
-        static_cast<unsigned>(M), static_cast<unsigned>(N), off_dummy, off_dummy, 0,
-        key_bits(n));
-  } else {
-    (void)rocprim::segmented_radix_sort_keys(
-        nullptr, sort_bytes, static_cast<const int32_t*>(nullptr), static_cast<int32_t*>(nullptr),
-        static_cast<unsigned>(M), static_cast<unsigned>(N), off_dummy, off_dummy, 0,
-        key_bits(n));
-  }
-  L.sort_bytes = sort_bytes;
-  L.sort = take(sort_bytes);
+  L.sort = take(8 * M);  // (column, position) pairs of rows too long for LDS
   L.total = off;
   return L;
 }
@@ -87,13 +65,13 @@ __global__ void k_new_degrees(int32_t n, const int32_t* __restrict__ rowptr,
 // at most kSortReg entries is sorted in registers by one thread, with a fixed
 // network of compare-and-swaps of neighbours on strictly greater keys (the
 // insertion order, so equal keys keep their input order).  A longer row goes
-// to keys / vals_tmp for the segmented sort, and end[k] marks it: end[k] = its
-// end, while a short row gets an empty segment.
+// to keys / vals_tmp in input order, and k to the list of long rows, which
+// k_sort_long_rows sorts.
 //
 // A block takes kMoveRows consecutive rows of B, whose entries are one
 // contiguous range of the output.  If that range fits kStage entries, the
 // sorted rows are staged in LDS and the range is written out coalesced (the
-// slots of long rows carry nothing; the segmented sort, later on the same
+// slots of long rows carry nothing; k_sort_long_rows, later on the same
 // stream, writes them); otherwise each thread writes its row itself.
 constexpr int kSortReg = 16;
 constexpr int kMoveRows = 256;
@@ -105,7 +83,7 @@ k_move_rows(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __rest
             const int32_t* __restrict__ iperm, const int32_t* __restrict__ rowptr_out,
             int32_t* __restrict__ keys, double* __restrict__ vals_tmp,
             int32_t* __restrict__ colidx_out, double* __restrict__ vals_out,
-            int32_t* __restrict__ end) {
+            int32_t* __restrict__ long_rows, int32_t* __restrict__ long_count) {
   __shared__ int32_t sc[kStage];
   __shared__ double sx[kStage];
   for (int64_t t = blockIdx.x; t * kMoveRows < n; t += gridDim.x) {
@@ -123,9 +101,8 @@ k_move_rows(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __rest
           keys[o + e] = iperm[colidx[a + e]];
           if (vals) vals_tmp[o + e] = vals[a + e];
         }
-        end[k] = o + len;
+        long_rows[atomicAdd(long_count, 1)] = k;
       } else {
-        end[k] = o;
         int32_t c[kSortReg];
         double x[kSortReg];
 #pragma unroll
@@ -169,6 +146,65 @@ k_move_rows(int32_t n, const int32_t* __restrict__ rowptr, const int32_t* __rest
       }
       __syncthreads();
     }
+  }
+}
+
+// The long rows: one work-group per row (a grid-stride loop over the list
+// k_move_rows made).  The row's entries become (column << 32 | position)
+// pairs, distinct even if a column repeats, so the sort puts equal columns
+// in input order as the short rows do, and the values follow their
+// positions.  They are sorted by a bitonic network whose comparators all
+// put the smaller pair first (each merge starts by comparing mirrored
+// positions), so positions past the row can stand for pairs above every
+// other without being stored: a comparator that would reach one is a no-op.
+// Rows of up to kLongLds entries sort in LDS, longer ones in place in the
+// scratch array, with a barrier of the work-group between the steps.
+constexpr int kLongThreads = 256;
+constexpr int kLongLds = 8192;
+
+__device__ __forceinline__ void bitonic_pairs(unsigned long long* a, int32_t len, int32_t pow2) {
+  for (int32_t k = 2; k <= pow2; k <<= 1) {
+    for (int32_t j = k >> 1; j > 0; j >>= 1) {
+      for (int32_t i = threadIdx.x; i < pow2; i += kLongThreads) {
+        const int32_t p = j == (k >> 1) ? (i ^ (k - 1)) : (i ^ j);
+        if (p > i && p < len) {
+          const unsigned long long x = a[i], y = a[p];
+          if (y < x) {
+            a[i] = y;
+            a[p] = x;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kLongThreads)
+k_sort_long_rows(const int32_t* __restrict__ rowptr_out, const int32_t* __restrict__ long_rows,
+                 const int32_t* __restrict__ long_count, const int32_t* __restrict__ keys,
+                 const double* __restrict__ vals_tmp, unsigned long long* __restrict__ pairs,
+                 int32_t* __restrict__ colidx_out, double* __restrict__ vals_out) {
+  __shared__ unsigned long long sp[kLongLds];
+  const int32_t count = *long_count;
+  for (int32_t r = blockIdx.x; r < count; r += gridDim.x) {
+    const int32_t k = long_rows[r];
+    const int32_t o = rowptr_out[k];
+    const int32_t len = rowptr_out[k + 1] - o;
+    int32_t pow2 = 1;
+    while (pow2 < len) pow2 <<= 1;
+    unsigned long long* a = len <= kLongLds ? sp : pairs + o;
+    for (int32_t i = threadIdx.x; i < len; i += kLongThreads)
+      a[i] = (static_cast<unsigned long long>(static_cast<uint32_t>(keys[o + i])) << 32) |
+             static_cast<uint32_t>(i);
+    __syncthreads();
+    bitonic_pairs(a, len, pow2);
+    for (int32_t i = threadIdx.x; i < len; i += kLongThreads) {
+      const unsigned long long x = a[i];
+      colidx_out[o + i] = static_cast<int32_t>(x >> 32);
+      if (vals_out) vals_out[o + i] = vals_tmp[o + static_cast<uint32_t>(x)];
+    }
+    __syncthreads();
   }
 }
 
@@ -224,30 +260,24 @@ rcm_status rcm_permute(int32_t n, int64_t nnz, const int32_t* rowptr, const int3
   int32_t* blk = reinterpret_cast<int32_t*>(ws + L.blk);
   int32_t* keys = reinterpret_cast<int32_t*>(ws + L.keys);
   double* vtmp = vals ? reinterpret_cast<double*>(ws + L.vals) : nullptr;
-  void* sort_tmp = ws + L.sort;
+  unsigned long long* pairs = reinterpret_cast<unsigned long long*>(ws + L.sort);
   k_new_degrees<<<grid_for(n, kThreads), kThreads, 0, s>>>(n, rowptr, perm, deg);
   if (hipGetLastError() != hipSuccess) return RCM_ERR_HIP;
   if (launch_exclusive_scan(deg, rowptr_out, n, blk, rowptr_out + n, s) != hipSuccess)
     return RCM_ERR_HIP;
   if (nnz == 0) return RCM_OK;
-  // the degrees are scanned by now: deg holds the long rows' segment ends
-  int32_t* seg_end = deg;
+  // the degrees are scanned by now: deg takes the list of long rows, and
+  // the scan's block sums (free again) its length
+  int32_t* long_rows = deg;
+  int32_t* long_count = blk;
+  if (hipMemsetAsync(long_count, 0, sizeof(int32_t), s) != hipSuccess) return RCM_ERR_HIP;
   k_move_rows<<<grid_for(n, kMoveRows), kMoveRows, 0, s>>>(n, rowptr, colidx, vals, perm, iperm,
                                                           rowptr_out, keys, vtmp, colidx_out,
-                                                          vals_out, seg_end);
+                                                          vals_out, long_rows, long_count);
   if (hipGetLastError() != hipSuccess) return RCM_ERR_HIP;
-  size_t sort_bytes = L.sort_bytes;
-  hipError_t e;
-  if (vals) {
-    e = rocprim::segmented_radix_sort_pairs(sort_tmp, sort_bytes, keys, colidx_out, vtmp, vals_out,
-                                            static_cast<unsigned>(nnz), static_cast<unsigned>(n),
-                                            rowptr_out, seg_end, 0, key_bits(n), s);
-  } else {
-    e = rocprim::segmented_radix_sort_keys(sort_tmp, sort_bytes, keys, colidx_out,
-                                           static_cast<unsigned>(nnz), static_cast<unsigned>(n),
-                                           rowptr_out, seg_end, 0, key_bits(n), s);
-  }
-  return e == hipSuccess ? RCM_OK : RCM_ERR_HIP;
+  k_sort_long_rows<<<1024, kLongThreads, 0, s>>>(rowptr_out, long_rows, long_count, keys, vtmp,
+                                                 pairs, colidx_out, vals_out);
+  return hipGetLastError() == hipSuccess ? RCM_OK : RCM_ERR_HIP;
 }
 
 rcm_status rcm_spmv(int32_t n, const int32_t* rowptr, const int32_t* colidx, const double* vals,

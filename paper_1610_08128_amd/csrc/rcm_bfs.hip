@@ -119,9 +119,23 @@ __device__ __forceinline__ int32_t* kept_row(SharedBuf& u, int32_t i) {
 // reached the vertex, alongside its atomic.
 constexpr int kORowCap = 1024;
 
+// Labelled levels: a parent on a row longer than a register batch ranks up
+// to kLongKids children in registers itself; one with many more on a long
+// row is placed by the whole work-group (kHeavyCap: such parents per chunk
+// of the level, at most one per thread).
+constexpr int kLongKids = 4;
+constexpr int kHeavyCap = 512;
+// A parent's own ranking of c > kLongKids children scans its row once per
+// child: c * (row batches) dependent round trips.  Past this many, the
+// work-group places them instead (one parent at a time, so not for the
+// many parents of moderate rows that rank well in parallel).
+constexpr int64_t kHeavyWork = 512;
+
+typedef int4 OwnRowStore[2][kORowCap][2];
+
 struct Shared {
   SharedBuf u;
-  int4 orow[2][kORowCap][2];
+  OwnRowStore orow;
   int scan[17];
   long long red[16];
   int32_t cnt;
@@ -144,6 +158,9 @@ struct Shared {
   int32_t lown_base;               // wide labelled level: the label range of the
   int32_t lown_len;                // children this work-group placed (its list
   int32_t lown_ok;                 // in srec), valid when it holds them all
+  int4 heavy[kHeavyCap];           // labelled levels: parents whose many children on a
+  int32_t nheavy;                  // long row the whole work-group places (label, first
+  int32_t mcnt;                    // label, children); children found so far
   int32_t stop;                    // abort polls: the flag or an error was seen
   int32_t state[8];
 };
@@ -1521,12 +1538,13 @@ __device__ __forceinline__ void defer_claims(const BfsParams& P, Shared& S, int3
 // collects the keys of up to four children in registers (placed by
 // predicated selects, no indexed register access); they are ranked there and
 // their records fetched together.  A parent with more children ranks each
-// one against the whole row.
+// one against the whole row (place_many_children takes the parents for which
+// that would be long).
 __device__ __forceinline__ void place_long_row(const BfsParams& P, Shared& S, int32_t p, int32_t u,
                                                int32_t a, int32_t b, int32_t base, int32_t end,
                                                int32_t list_base, long long& my_m) {
   const uint32_t pl = static_cast<uint32_t>(p);
-  constexpr int kKids = 4;  // children ranked in registers
+  constexpr int kKids = kLongKids;  // children ranked in registers
   uint64_t ck[kKids];  // their (degree, caller id) keys ...
   int32_t cv[kKids];   // ... and vertex numbers
 #pragma unroll
@@ -1604,6 +1622,89 @@ __device__ __forceinline__ void place_long_row(const BfsParams& P, Shared& S, in
       my_m += inf.z;
       defer_claims(P, S, nb[j], inf, at, list_base);
     }
+  }
+}
+
+// The children of parent p (label p, first child label `base`, c children)
+// when there are more than kLongKids of them, placed by the whole
+// work-group: the row is scanned in parallel for the neighbours that p
+// claimed, their (degree, caller id) keys (distinct: the id is) are sorted
+// ascending, and child i gets label base + i (SortPerm's order among
+// siblings, Table I).  The keys sort in LDS (the asynchronous passes' row
+// store, unused while labelling) up to kManyLds of them; more sort in place
+// in the children's own record slots qi[base, base + c), 16 bytes each, of
+// which the keys take the first half.  A bitonic network whose comparators
+// all put the smaller key first (each merge starts with mirrored pairs)
+// lets positions past c stand for keys above every other without storage.
+// All threads of the work-group call it with the same arguments.
+constexpr int kManyLds = static_cast<int>(sizeof(OwnRowStore) / sizeof(unsigned long long));
+
+__device__ __forceinline__ void sort_keys_ascending(unsigned long long* a, int32_t len) {
+  const int B = blockDim.x;
+  int32_t pow2 = 1;
+  while (pow2 < len) pow2 <<= 1;
+  for (int32_t k = 2; k <= pow2; k <<= 1) {
+    for (int32_t j = k >> 1; j > 0; j >>= 1) {
+      for (int32_t i = threadIdx.x; i < pow2; i += B) {
+        const int32_t q = j == (k >> 1) ? (i ^ (k - 1)) : (i ^ j);
+        if (q > i && q < len) {
+          const unsigned long long x = a[i], y = a[q];
+          if (y < x) {
+            a[i] = y;
+            a[q] = x;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+__device__ __forceinline__ void place_many_children(const BfsParams& P, Shared& S, int32_t p,
+                                                    int32_t base, int32_t c, int32_t end,
+                                                    int32_t list_base, long long& my_m) {
+  const int B = blockDim.x;
+  const int4 e = ld_rec(P, p);
+  const int32_t u = e.x;
+  const uint32_t pl = static_cast<uint32_t>(p);
+  const bool in_lds = c <= kManyLds;
+  // (the record slots are 16-byte aligned; the keys use their first 8c bytes)
+  unsigned long long* keys = in_lds ? reinterpret_cast<unsigned long long*>(&S.orow)
+                                    : reinterpret_cast<unsigned long long*>(P.qi + base);
+  if (threadIdx.x == 0) S.mcnt = 0;
+  __syncthreads();
+  for (int32_t k = e.y + threadIdx.x; k < e.z; k += B) {
+    const int32_t w = P.colidx[k];
+    if (w == u || ld_relaxed(&P.claim[w]) != pl) continue;
+    const int4 inf = P.vinfo[w];
+    const int32_t at = atomicAdd(&S.mcnt, 1);
+    if (at < c) keys[at] = pack_key(inf.z, inf.w);
+  }
+  __syncthreads();
+  // the count phase found c children, and their claims have not changed
+  // since (this level's claims are issued after placement)
+  const int32_t n = S.mcnt < c ? S.mcnt : c;
+  sort_keys_ascending(keys, n);
+  // child i's record goes to slot base + i.  In the scratch case that slot
+  // holds keys 2i and 2i + 1, so the children go out from the last chunk
+  // down, each chunk read before any of its slots is written: every key a
+  // record covers then belongs to a chunk already read.
+  const int32_t chunks = (n + B - 1) / B;
+  for (int32_t ch = chunks - 1; ch >= 0; --ch) {
+    const int32_t i = ch * B + threadIdx.x;
+    unsigned long long kv = 0;
+    if (i < n) kv = keys[i];
+    __syncthreads();
+    if (i < n) {
+      const int32_t id = static_cast<int32_t>(kv & 0xffffffffu);
+      const int32_t v = P.new_of_old != nullptr ? P.new_of_old[id] : id;
+      const int4 inf = P.vinfo[v];
+      const int32_t at = base + i;
+      if (at < end) st_rec(&P.qi[at], record(v, inf));
+      my_m += inf.z;
+      defer_claims(P, S, v, inf, at, list_base);
+    }
+    __syncthreads();
   }
 }
 
@@ -1999,6 +2100,7 @@ __device__ __forceinline__ void global_label_level(const BfsParams& P, Team& t, 
   // placement, one child per thread
   const int32_t list_base = run;
   const int32_t list_len = S.wsum[wid] < kStageCap ? S.wsum[wid] : kStageCap;
+  if (threadIdx.x == 0) S.nheavy = 0;
   for (int32_t r0 = lo; r0 < hi; r0 += B) {
     const int32_t p = r0 + threadIdx.x;
     const int c = p < hi ? (one_round ? c_mine : P.tmp[p]) : 0;
@@ -2030,9 +2132,24 @@ __device__ __forceinline__ void global_label_level(const BfsParams& P, Team& t, 
           if (cmask >> j & 1u) defer_claims(P, S, cnb[j], cinf[j], at[j], list_base);
       } else {
         const int4 e = ld_rec(P, p);
-        place_long_row(P, S, p, e.x, e.y, e.z, base, end, list_base, my_m);
+        const int64_t batches = (static_cast<int64_t>(e.z - e.y) + kRB - 1) / kRB;
+        if (c > kLongKids && c * batches > kHeavyWork) {
+          // many children on a long row: placed by the whole work-group below
+          const int h = atomicAdd(&S.nheavy, 1);
+          S.heavy[h] = make_int4(p, base, c, 0);
+        } else {
+          place_long_row(P, S, p, e.x, e.y, e.z, base, end, list_base, my_m);
+        }
       }
     }
+    __syncthreads();
+    const int nh = S.nheavy;
+    for (int h = 0; h < nh; ++h) {
+      const int4 hv = S.heavy[h];
+      place_many_children(P, S, hv.x, hv.y, hv.z, end, list_base, my_m);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) S.nheavy = 0;
     run += rtot;
   }
   // (A) for the next level: every listed child claims its neighbours

@@ -146,3 +146,16 @@ def test_gpu_permute_many_tiles():
     g = I.grid2d(1500, 1500, seed=12)
     assert g.n > 8192 * 256
     _check_gpu_permute(g, 2)
+
+
+@pytest.mark.gpu
+def test_gpu_permute_long_rows():
+    """Rows longer than a register sort: rows of 17 to 300 entries, and hub
+    rows of exactly the LDS sort's 8,192 entries, one more, and 20,001 (the
+    last two sort in the scratch array), with rows in random order."""
+    g = I.shuffle_rows(I.disjoint_union([I.star(20001), I.star(8192), I.star(8193),
+                                         I.erdos_renyi(900, 0.15, 13), I.star(18), I.star(300)],
+                                        seed=14), 3)
+    lens = np.diff(g.rowptr)
+    assert {8192, 8193, 20001} <= set(lens.tolist())
+    _check_gpu_permute(g, 4)
