@@ -469,6 +469,32 @@ def _row_copy_graphs():
             I.shuffle_rows(I.grid3d(18, 22, 16, seed=69), 70)]
 
 
+def _hub_graphs():
+    """Hubs whose children outnumber what one thread ranks: a star of 20,001
+    (its children sort outside LDS), 8,193 and 700, a wheel-like hub over a
+    cycle, and a hub joined to a grid, each relabelled."""
+    hub = np.zeros(3000, np.int64)
+    rim = np.arange(1, 3001, dtype=np.int64)
+    wheel = I.from_edges(3001, np.concatenate([hub, rim[:-1]]), np.concatenate([rim, rim[1:]]),
+                         perm=np.random.default_rng(81).permutation(3001), name="wheel_3001")
+    return [I.relabel(I.star(20001), 82)[0], I.relabel(I.star(8193), 83)[0],
+            I.relabel(I.star(700), 84)[0], wheel,
+            _with_hub(I.grid2d(60, 70, seed=85), 7, 2500, 86)]
+
+
+@pytest.mark.parametrize("team", [1, 4, 64])
+def test_hub_children_placed_by_the_work_group(team):
+    """Parity where one parent has thousands of children on a long row, on
+    a work-group alone and on teams, in both search variants."""
+    for i, g in enumerate(_hub_graphs()):
+        check(g, small_cutoff=1 if team > 1 else 1 << 30, team_size=team, pp_variant=i % 2)
+
+
+def test_batched_hub_rows():
+    _check_batch([I.star(9000), I.grid2d(40, 50, seed=87), I.relabel(I.star(3000), 88)[0],
+                  I.path(9)], small_cutoff=100)
+
+
 @pytest.mark.parametrize("copy", ["1", "0"])
 def test_row_copy_team_path(copy, monkeypatch):
     """Parity on the team path with the copy on and off (RCM_ELL): bounded
