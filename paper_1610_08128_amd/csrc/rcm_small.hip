@@ -184,27 +184,68 @@ __device__ Pass search_pass(const Lds<T>& L, int32_t n, int32_t o, uint32_t root
   return r;
 }
 
-// Children of parent p (vertex u, row [a, b)) placed at base + their rank by
-// (degree, id), for a parent with more children than the register ranking
-// holds: each child is ranked against the whole row.
+// Children of parent p (vertex u, row [a, b), c children, first label base)
+// for a parent with more children than the register ranking holds, placed
+// by the whole wave: the lanes take the row 64 entries at a time and write
+// the children, in row order, into their label range ord[base, base + c);
+// then that range is sorted by (degree, id) in place, which is their rank
+// among the siblings.  The sort is a bitonic network whose comparators all
+// put the smaller key first (each merge starts with mirrored pairs), so
+// positions past c stand for keys above every other without storage.  One
+// wave's LDS operations are performed in issue order; the wavefront fence
+// keeps the compiler to that order between the steps.  Every lane calls it
+// with the same arguments.
 template <typename T>
-__device__ __forceinline__ void place_children(const Lds<T>& L, uint32_t p, uint32_t u,
-                                               uint32_t a, uint32_t b, int32_t base, int32_t n,
-                                               int c, bool* bad) {
-  (void)c;
-  for (uint32_t k = a; k < b; ++k) {
-    const uint32_t x = L.ci[k];
-    if (x == u || L.lab[x] != L.none || L.clm[x] != p) continue;
-    const uint64_t kx = pack_key(static_cast<int32_t>(L.deg[x]), static_cast<int32_t>(x));
-    int rank = 0;
-    for (uint32_t k2 = a; k2 < b; ++k2) {
-      const uint32_t y = L.ci[k2];
-      if (y == u || L.lab[y] != L.none || L.clm[y] != p) continue;
-      rank += pack_key(static_cast<int32_t>(L.deg[y]), static_cast<int32_t>(y)) < kx ? 1 : 0;
+__device__ __forceinline__ uint64_t child_key(const Lds<T>& L, uint32_t x) {
+  return pack_key(static_cast<int32_t>(L.deg[x]), static_cast<int32_t>(x));
+}
+
+template <typename T>
+__device__ __forceinline__ void wave_place_children(const Lds<T>& L, uint32_t p, uint32_t u,
+                                                    uint32_t a, uint32_t b, int32_t base,
+                                                    int32_t n, int c, bool* bad) {
+  const uint32_t lane = threadIdx.x;
+  int32_t got = 0;
+  for (uint32_t k0 = a; k0 < b; k0 += kSW) {
+    const uint32_t k = k0 + lane;
+    uint32_t x = 0;
+    bool child = false;
+    if (k < b) {
+      x = L.ci[k];
+      child = x != u && L.lab[x] == L.none && L.clm[x] == p;
     }
-    const int32_t at = base + rank;
-    if (at < n) L.ord[at] = static_cast<T>(x);
-    else *bad = true;
+    const unsigned long long m = __ballot(child);
+    const int below = __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(m >> 32),
+                                                __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(m), 0));
+    if (child) {
+      const int32_t at = base + got + below;
+      if (got + below < c && at < n) L.ord[at] = static_cast<T>(x);
+      else *bad = true;
+    }
+    got += __popcll(m);
+  }
+  if (got != c) *bad = true;
+  int32_t len = got < c ? got : c;
+  if (base + len > n) len = n - base;
+  if (len <= 1) return;
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  T* seg = L.ord + base;
+  int32_t pow2 = 1;
+  while (pow2 < len) pow2 <<= 1;
+  for (int32_t k = 2; k <= pow2; k <<= 1) {
+    for (int32_t j = k >> 1; j > 0; j >>= 1) {
+      for (int32_t i = static_cast<int32_t>(lane); i < pow2; i += kSW) {
+        const int32_t q = j == (k >> 1) ? (i ^ (k - 1)) : (i ^ j);
+        if (q > i && q < len) {
+          const uint32_t xi = seg[i], xq = seg[q];
+          if (child_key(L, xq) < child_key(L, xi)) {
+            seg[i] = static_cast<T>(xq);
+            seg[q] = static_cast<T>(xi);
+          }
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    }
   }
 }
 
@@ -307,8 +348,16 @@ __device__ Pass label_pass(const Lds<T>& L, int32_t n, int32_t o, uint32_t root,
           if (at < n) L.ord[at] = static_cast<T>(ck[i] & 0xffffffffu);
           else bad = true;
         }
-      } else if (c > kBatch) {
-        place_children(L, static_cast<uint32_t>(p), u, a, bb, base, n, c, &bad);
+      }
+      // the parents with more children: the wave places them one by one
+      unsigned long long heavy = __ballot(c > kBatch);
+      while (heavy != 0) {
+        const int l = __ffsll(static_cast<long long>(heavy)) - 1;
+        heavy &= heavy - 1;
+        wave_place_children(L, static_cast<uint32_t>(__shfl(p, l)), static_cast<uint32_t>(__shfl(static_cast<int>(u), l)),
+                            static_cast<uint32_t>(__shfl(static_cast<int>(a), l)),
+                            static_cast<uint32_t>(__shfl(static_cast<int>(bb), l)), __shfl(base, l),
+                            n, __shfl(c, l), &bad);
       }
       placed += total;
     }

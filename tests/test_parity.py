@@ -490,6 +490,16 @@ def test_hub_children_placed_by_the_work_group(team):
         check(g, small_cutoff=1 if team > 1 else 1 << 30, team_size=team, pp_variant=i % 2)
 
 
+def test_engine_hub_rows():
+    """The one-work-group engine on graphs where one parent has thousands of
+    children (the wave collects and sorts them in their label range): stars
+    up to the engine's LDS limit, a wheel, a hub on a grid."""
+    gs = [I.relabel(I.star(2000), 91)[0], I.relabel(I.star(8000), 92)[0]] + _hub_graphs()[2:]
+    for g in gs:
+        check(g, mode=2)
+        check(g, mode=2, pp_variant=1, reverse_mode=1)
+
+
 def test_batched_hub_rows():
     _check_batch([I.star(9000), I.grid2d(40, 50, seed=87), I.relabel(I.star(3000), 88)[0],
                   I.path(9)], small_cutoff=100)
