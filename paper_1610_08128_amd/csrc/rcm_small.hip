@@ -565,8 +565,11 @@ __device__ void order_graph(const SmallJob& J, const SmallOpts& O, char* smem) {
     bw = beta > bw ? beta : bw;
     prof += beta;
   }
-  // rows longer than 64 entries: the whole wave compares each entry with
-  // the ones after it
+  // rows longer than 64 entries, one at a time by the whole wave: each
+  // entry swaps the row's number into its column's claim word (all free
+  // here), and finding that number there already means the column repeats.
+  // The words go back to free afterwards.  (The columns are in range: the
+  // load checked them.)
   if (__any(longrows)) {
     for (int32_t i0 = 0; i0 < n; i0 += kSW) {
       const int32_t i = i0 + tid;
@@ -575,13 +578,14 @@ __device__ void order_graph(const SmallJob& J, const SmallOpts& O, char* smem) {
       while (m) {
         const int w = __builtin_ctzll(m);
         m &= m - 1;
-        const uint32_t a = L.rp[i0 + w], b = L.rp[i0 + w + 1];
-        for (uint32_t k = a + tid; k < b; k += kSW) {
-          const uint32_t c = L.ci[k];
-          for (uint32_t k2 = k + 1; k2 < b; ++k2) dup |= static_cast<uint32_t>(L.ci[k2]) == c;
-        }
+        const uint32_t row = static_cast<uint32_t>(i0 + w);
+        const uint32_t a = L.rp[row], b = L.rp[row + 1];
+        for (uint32_t k = a + tid; k < b; k += kSW)
+          dup |= atomicExch(&L.clm[static_cast<uint32_t>(L.ci[k])], row) == row;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
       }
     }
+    for (int32_t i = tid; i < n; i += kSW) L.clm[i] = kFree;
   }
   if (__any(dup)) {
     if (tid == 0) R->status = RCM_ERR_BAD_CSR;
