@@ -121,27 +121,79 @@ __global__ void k_validate_scan(int32_t n, int32_t nnz, const int32_t* __restric
   }
 }
 
-// Duplicates in the rows longer than kDupShort: one work-group per row, each
-// thread comparing its entries with the ones after them.  Only launched when
-// k_validate_scan saw such a row; rows with invalid bounds were reported
-// there and are skipped.
-__global__ void k_dup_long(int32_t n, int32_t nnz, const int32_t* __restrict__ rowptr,
-                           const int32_t* __restrict__ colidx, int32_t* __restrict__ err) {
-  __shared__ int found;
+// Duplicates in the rows longer than kDupShort: one work-group per row,
+// which inserts the row's columns into a hash set in LDS (open addressing,
+// atomic compare-and-swap); finding a column already there is a repeat.  A
+// row of L entries takes ceil(L / kDupChunk) passes, pass q over the columns
+// c with c mod passes == q, so that each pass holds about kDupChunk keys in
+// kDupSlots slots.  A pass whose keys fill the table (columns crowded into
+// one residue) ends that row's check with the pairwise comparison.  A row
+// with more entries than there are columns repeats one by counting.  Only
+// launched when k_validate_scan saw such a row; rows with invalid bounds
+// were reported there and are skipped.
+constexpr int kDupSlotBits = 14;
+constexpr int kDupSlots = 1 << kDupSlotBits;  // 64 KB of LDS
+constexpr int kDupChunk = kDupSlots / 2;
+constexpr uint32_t kDupEmpty = 0xFFFFFFFFu;  // no column (columns are below 2^31)
+
+__global__ void __launch_bounds__(kThreads)
+k_dup_long(int32_t n, int32_t nnz, const int32_t* __restrict__ rowptr,
+           const int32_t* __restrict__ colidx, int32_t* __restrict__ err) {
+  __shared__ uint32_t table[kDupSlots];
+  __shared__ int found, full;
   for (int32_t i = blockIdx.x; i < n; i += gridDim.x) {
     const int32_t a = rowptr[i];
     const int32_t b = rowptr[i + 1];
     if (a < 0 || b < a || b > nnz || b - a <= kDupShort) continue;
-    if (threadIdx.x == 0) found = 0;
-    __syncthreads();
-    for (int32_t k = a + threadIdx.x; k < b; k += blockDim.x) {
-      const int32_t c = colidx[k];
-      bool dup = false;
-      for (int32_t k2 = k + 1; k2 < b && !dup; ++k2) dup = colidx[k2] == c;
-      if (dup) found = 1;
+    const int32_t len = b - a;
+    if (len > n) {
+      if (threadIdx.x == 0) atomicOr(err, 1);
+      continue;
     }
-    __syncthreads();
+    const uint32_t passes = static_cast<uint32_t>((len + kDupChunk - 1) / kDupChunk);
+    if (threadIdx.x == 0) {
+      found = 0;
+      full = 0;
+    }
+    for (uint32_t q = 0; q < passes; ++q) {
+      for (int t = threadIdx.x; t < kDupSlots; t += blockDim.x) table[t] = kDupEmpty;
+      __syncthreads();
+      if (full == 0 && found == 0) {
+        for (int32_t k = a + threadIdx.x; k < b; k += blockDim.x) {
+          const uint32_t c = static_cast<uint32_t>(colidx[k]);
+          if (c % passes != q) continue;
+          uint32_t h = (c * 2654435761u) >> (32 - kDupSlotBits);
+          bool placed = false;
+          for (int probe = 0; probe < kDupSlots; ++probe) {
+            const uint32_t old = atomicCAS(&table[h], kDupEmpty, c);
+            if (old == kDupEmpty) {
+              placed = true;
+              break;
+            }
+            if (old == c) {
+              found = 1;
+              placed = true;
+              break;
+            }
+            h = (h + 1) & (kDupSlots - 1);
+          }
+          if (!placed) full = 1;
+        }
+      }
+      __syncthreads();
+    }
+    if (full != 0 && found == 0) {
+      // the pairwise comparison for this row
+      for (int32_t k = a + threadIdx.x; k < b; k += blockDim.x) {
+        const int32_t c = colidx[k];
+        bool dup = false;
+        for (int32_t k2 = k + 1; k2 < b && !dup; ++k2) dup = colidx[k2] == c;
+        if (dup) found = 1;
+      }
+      __syncthreads();
+    }
     if (threadIdx.x == 0 && found) atomicOr(err, 1);
+    __syncthreads();
   }
 }
 

@@ -618,7 +618,7 @@ def test_rcm_order_entry_point(which):
 # Repeated columns are malformed on every path, rows of any length
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("row_len", [2, 7, 16, 17, 64, 65, 300, 2000])
+@pytest.mark.parametrize("row_len", [2, 7, 16, 17, 64, 65, 300, 2000, 40000])
 def test_duplicates_rejected_without_full_check(row_len):
     """A column repeated within a row gives RCM_ERR_BAD_CSR whatever the row
     length (register check up to 16 entries, re-read up to 64, a work-group
