@@ -130,6 +130,10 @@ constexpr int kHeavyCap = 512;
 // work-group places them instead (one parent at a time, so not for the
 // many parents of moderate rows that rank well in parallel).
 constexpr int64_t kHeavyWork = 512;
+// Asynchronous passes on the CSR: a record whose row is longer than this is
+// expanded by its whole work-group, a batch per thread, instead of by one
+// thread batch after batch.
+constexpr int32_t kHeavyRow = 2048;
 
 typedef int4 OwnRowStore[2][kORowCap][2];
 
@@ -1119,6 +1123,56 @@ __device__ __forceinline__ int32_t ring_pos(int32_t o, int32_t ring, int32_t v) 
   return o + static_cast<int32_t>(static_cast<uint32_t>(v) % static_cast<uint32_t>(ring));
 }
 
+// One batch of entries [k0, min(k0 + kRB, kend)) of the row of a current
+// record (vertex u at distance du) in an asynchronous pass on the CSR: the
+// neighbours' records are gathered alongside the atomics on their distance
+// words, and the neighbours this record reached are appended to the next
+// own frontier (or, past its capacity, straight into the next round's ring).
+// Reading the words first to spare the atomics of edges into vertices
+// already as close adds a dependent round trip per step, which measured
+// slower (3.5 -> 5.6 us per step on the 128^3 grid).
+__device__ __forceinline__ void async_expand_batch(const BfsParams& P, Shared& S, int32_t u,
+                                                   int32_t du, int32_t k0, int32_t kend,
+                                                   unsigned long long want, int cb, int32_t o,
+                                                   int32_t ring, int32_t room, int32_t g_e,
+                                                   int32_t* tail) {
+  int32_t nb[kRB];
+  load_batch(P.colidx, k0, kend, u, nb);
+  int4 inf[kRB];
+  unsigned long long old[kRB];
+#pragma unroll
+  for (int j = 0; j < kRB; ++j) inf[j] = P.vinfo[nb[j]];
+  // past-the-row lanes and self loops hit u, whose word beats want
+#pragma unroll
+  for (int j = 0; j < kRB; ++j) old[j] = atomicMax(&P.dkey[nb[j]], want);
+  unsigned mask = 0;
+#pragma unroll
+  for (int j = 0; j < kRB; ++j) mask |= (old[j] < want ? 1u : 0u) << j;
+  if (mask == 0) return;
+  int32_t idx = atomicAdd(&S.cnt, __popc(mask));
+#pragma unroll
+  for (int j = 0; j < kRB; ++j) {
+    if (!(mask >> j & 1u)) continue;
+    if (idx < kOwnCap) {
+      S.u.own[cb ^ 1][idx][0] = nb[j];
+      S.u.own[cb ^ 1][idx][1] = inf[j].x;
+      S.u.own[cb ^ 1][idx][2] = inf[j].y;
+      S.u.own[cb ^ 1][idx][3] = du + 1;
+    } else {
+      // straight into the next round's frontier
+      const int32_t at = atomicAdd(tail, 1);
+      atomicAdd(&S.appended, 1);
+      if (at < room) {
+        st_rec(&P.qi[ring_pos(o, ring, g_e + at)], make_int4(nb[j], inf[j].x, inf[j].y, du + 1));
+      } else {
+        S.ovf = 1;
+      }
+      S.spill = 1;
+    }
+    ++idx;
+  }
+}
+
 // One step of an asynchronous pass over a graph with a fixed-stride row
 // copy.  A record's row is already in LDS (the first kORowCap records of the
 // own buffer) or at a known address, so the supersede test of the record,
@@ -1276,7 +1330,10 @@ __device__ __forceinline__ bool async_bfs_pass(const BfsParams& P, Team& t, Shar
     }
     const long long r0 = wall_clock64();
     for (int step = 0; step < P.search_round; ++step) {
-      if (threadIdx.x == 0) S.cnt = 0;
+      if (threadIdx.x == 0) {
+        S.cnt = 0;
+        S.nheavy = 0;
+      }
       __syncthreads();
       ++d_steps;
       if (P.ell != nullptr) {
@@ -1300,53 +1357,31 @@ __device__ __forceinline__ bool async_bfs_pass(const BfsParams& P, Team& t, Shar
             __hip_atomic_load(&P.dkey[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const unsigned long long want = dist_key(tag, du + 1);
         if (cur == dist_key(tag, du)) ++d_exp; else ++d_sup;
-        for (int32_t k0 = e.y; k0 < e.z; k0 += kRB) {
-          int32_t nb[kRB];
-          load_batch(P.colidx, k0, e.z, u, nb);
-          if (cur != dist_key(tag, du)) break;
-          int4 inf[kRB];
-          unsigned long long old[kRB];
-          // the records are gathered alongside the atomics: reading the
-          // words first to spare the atomics of edges into vertices already
-          // as close adds a dependent round trip per step, which measured
-          // slower (3.5 -> 5.6 us per step on the 128^3 grid)
-#pragma unroll
-          for (int j = 0; j < kRB; ++j) inf[j] = P.vinfo[nb[j]];
-          // past-the-row lanes and self loops hit u, whose word beats want
-#pragma unroll
-          for (int j = 0; j < kRB; ++j) old[j] = atomicMax(&P.dkey[nb[j]], want);
-          unsigned mask = 0;
-#pragma unroll
-          for (int j = 0; j < kRB; ++j) mask |= (old[j] < want ? 1u : 0u) << j;
-          if (mask == 0) continue;
-          int32_t idx = atomicAdd(&S.cnt, __popc(mask));
-#pragma unroll
-          for (int j = 0; j < kRB; ++j) {
-            if (!(mask >> j & 1u)) continue;
-            if (idx < kOwnCap) {
-              S.u.own[cb ^ 1][idx][0] = nb[j];
-              S.u.own[cb ^ 1][idx][1] = inf[j].x;
-              S.u.own[cb ^ 1][idx][2] = inf[j].y;
-              S.u.own[cb ^ 1][idx][3] = du + 1;
-            } else {
-              // straight into the next round's frontier
-              const int32_t at = atomicAdd(tail + l3, 1);
-              atomicAdd(&S.appended, 1);
-              if (at < room) {
-                st_rec(&P.qi[ring_pos(o, ring, g_e + at)], make_int4(nb[j], inf[j].x, inf[j].y,
-                                                                     du + 1));
-              } else {
-                S.ovf = 1;
-              }
-              S.spill = 1;
-            }
-            ++idx;
+        if (cur != dist_key(tag, du)) continue;
+        if (e.z - e.y > kHeavyRow) {
+          // a long row: the whole work-group expands it below
+          const int h = atomicAdd(&S.nheavy, 1);
+          if (h < kHeavyCap) {
+            S.heavy[h] = e;
+            continue;
           }
         }
+        for (int32_t k0 = e.y; k0 < e.z; k0 += kRB)
+          async_expand_batch(P, S, u, du, k0, e.z, want, cb, o, ring, room, g_e, tail + l3);
+      }
+      __syncthreads();
+      // the records on long rows, one at a time, a batch per thread
+      const int nh = S.nheavy < kHeavyCap ? S.nheavy : kHeavyCap;
+      for (int h = 0; h < nh; ++h) {
+        const int4 e = S.heavy[h];
+        const unsigned long long want = dist_key(tag, e.w + 1);
+        for (int32_t k0 = e.y + static_cast<int32_t>(threadIdx.x) * kRB; k0 < e.z; k0 += B * kRB)
+          async_expand_batch(P, S, e.x, e.w, k0, e.z, want, cb, o, ring, room, g_e, tail + l3);
       }
       }
       __syncthreads();
       const int32_t cnt = S.cnt;
+      if (threadIdx.x == 0) S.nheavy = 0;  // (read by every thread before the barrier)
       own_n = cnt < kOwnCap ? cnt : kOwnCap;
       cb ^= 1;
       n_glob = 0;
@@ -1922,6 +1957,7 @@ __device__ __forceinline__ void global_label_level(const BfsParams& P, Team& t, 
   const long long ta = wall_clock64();
   const bool one_round = hi - lo <= B;
   bool captured = false;
+  bool deferred = false;  // a parent on a row longer than kHeavyRow, counted below
   int c_mine = 0;
   int32_t cnb[kRB];
   int4 cinf[kRB];
@@ -1959,13 +1995,43 @@ __device__ __forceinline__ void global_label_level(const BfsParams& P, Team& t, 
       captured = true;
       c = __popc(cmask);
     } else {
-      c = count_long_row(P, p, u, e.y, e.z);
-      P.tmp[p] = c;
+      int h = kHeavyCap;
+      if (e.z - e.y > kHeavyRow) h = atomicAdd(&S.nheavy, 1);
+      if (h < kHeavyCap) {
+        // a long row: its children are counted by the whole work-group below
+        S.heavy[h] = make_int4(p, u, e.y, e.z);
+        deferred = true;
+        c = 0;
+      } else {
+        c = count_long_row(P, p, u, e.y, e.z);
+        P.tmp[p] = c;
+      }
     }
     c_mine = c;
     wg_total += c;
   }
-  const long long tot = block_sum_i64(wg_total, S.red);
+  // the count's block sum also says whether any parent was deferred, so that
+  // a level without such a row pays no extra barrier
+  long long tot = block_sum_i64(wg_total + (deferred ? (1ll << 40) : 0ll), S.red);
+  if (tot >> 40) {
+    tot &= (1ll << 40) - 1;
+    const int nh = S.nheavy < kHeavyCap ? S.nheavy : kHeavyCap;
+    for (int h = 0; h < nh; ++h) {
+      const int4 hv = S.heavy[h];
+      const uint32_t pl = static_cast<uint32_t>(hv.x);
+      long long mine = 0;
+      for (int32_t k = hv.z + static_cast<int32_t>(threadIdx.x); k < hv.w; k += B) {
+        const int32_t w = P.colidx[k];
+        mine += (w != hv.y && ld_relaxed(&P.claim[w]) == pl) ? 1 : 0;
+      }
+      const long long cnt = block_sum_i64(mine, S.red);
+      tot += cnt;
+      if (threadIdx.x == 0) P.tmp[hv.x] = static_cast<int32_t>(cnt);
+      if (one_round && hv.x - lo == static_cast<int32_t>(threadIdx.x)) c_mine = static_cast<int>(cnt);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) S.nheavy = 0;
+  }
   const long long t1 = wall_clock64();
   // A work-group whose children all sit in registers (every parent's row is
   // one batch, one parent per thread) and fit its LDS list orders them
@@ -2512,7 +2578,10 @@ __device__ __forceinline__ void order_main(const BfsParams& P) {
   t.sub_seq = 0;
   t.ldone = 0;
   t.woke = 0;
-  if (threadIdx.x == 0) S.lown_ok = 0;
+  if (threadIdx.x == 0) {
+    S.lown_ok = 0;
+    S.nheavy = 0;
+  }
   t.aborted = false;
   t.abort_flag = P.abort_flag;
   t.shuffle = P.shuffle;
