@@ -40,14 +40,17 @@ import numpy as np
 from . import rcm
 
 # Large single graphs: team shape, labelling sub-team, round length of the
-# asynchronous search, rebalance interval of the level-synchronous passes.
+# asynchronous search, rebalance interval of the level-synchronous passes,
+# and the width below which one work-group walks a level alone (0 = the
+# library's 256).
 SINGLE_CANDIDATES: List[Dict[str, int]] = [
     dict(mode=1, team_size=w, block_threads=256, label_team=lt, search_round=sr,
-         rebalance_levels=rb)
+         rebalance_levels=rb, narrow_cutoff=nc)
     for w in (128, 256)
     for lt in (64, 96, 128)
     for sr in (12, 16, 24)
     for rb in (4, 8)
+    for nc in (0, 128, 160)
 ]
 
 # Small single graphs: the one-work-group engine against teams of the
