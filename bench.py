@@ -52,7 +52,7 @@ WORKLOADS = {
 # sources at the time of the measurement, so a changed kernel reports null.
 # Summaries with the commands: profiles/k_order_<workload>_hbm_counters.md.
 MEASURED_TRAFFIC = {
-    "grid3d_128x128x128": ("221615345e97deec", 5641125343),
+    "grid3d_128x128x128": ("221615345e97deec", 5644434219),
 }
 KERNEL_SOURCES = ("paper_1610_08128_amd/csrc/rcm_bfs.hip",
                   "paper_1610_08128_amd/csrc/rcm_common.hpp")
