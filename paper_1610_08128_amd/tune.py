@@ -53,6 +53,11 @@ SINGLE_CANDIDATES: List[Dict[str, int]] = [
     for nc in (0, 128, 160)
 ]
 
+# Long narrow graphs (the strip): the round length of the asynchronous
+# search, which sets how many round barriers its narrow frontier meets.
+LONG_CANDIDATES: List[Dict[str, int]] = [
+    dict(mode=1, search_round=sr) for sr in (16, 32, 64, 128)]
+
 # Small single graphs: the one-work-group engine against teams of the
 # persistent kernel.
 SMALL_CANDIDATES: List[Dict[str, int]] = (
